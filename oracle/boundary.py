@@ -1,0 +1,184 @@
+"""ELIBB boundary reconstruction (Sec. II.C-E of the paper).
+
+For a cut link (x_F, i) -- i is the population that is missing at the boundary
+node F after streaming, so x_F - c_i lies in the solid -- the ELIBB general form
+(eq. ELIBB-general) rebuilds f_i(x_F, t+1) as a weighted sum of up to four
+quantities, each placed at a signed link coordinate s (eq. s, eq. x_to_s_helper):
+
+  name  quantity                                              s
+  P0    wall population at t+1,  ~f_i^{t+1}(x_W)              0
+  P1    post-collision wall population, ~f_i^*(x_W)           1
+  P2    post-collision bounced population f_ibar^*(x_F)       1 - q
+  P3    post-collision population f_i^*(x_F)                  1 + q
+
+and the target f_i^{t+1}(x_F) sits at s = q.  The weights are the Lagrange
+basis (eq. poli_coeff) over the variant's point set evaluated at s_ref = q.
+
+Readings taken where the paper is ambiguous (all listed in the design notes):
+* s uses |c_i|^2 in the denominator so that the helper values of eq.
+  x_to_s_helper hold (eq. s prints |c_i|); this reproduces the printed BFL
+  (eq. bfl) and ELIBB-U coefficients.
+* the post-collision wall population sits at s = 1 (the resting-wall value of
+  eq. x_to_s_helper); wall motion enters only through the momentum correction
+  (eq. ME-solid-to-fluid) and the wall equilibria.
+* the wall equilibria use rho_F(t) and u_w(t+1) for P0, u_w(t) for P1
+  (eq. ELIBB-approximation-eq1/eq2); the wall non-equilibria use the bounced
+  non-equilibrium of node F at time t (eq. neqbb-s): pre-collision for P0,
+  post-collision for P1.
+* the moving-wall correction (eq. ME-solid-to-fluid) is added to nodal
+  populations with s < 1, i.e. to P2 only, with rho = rho_F(t), u_w = u_w(t).
+* the ELIBB-F coefficients printed in Sec. II.D are garbled (they do not sum to
+  one); the Lagrange rule is used instead.  UQ and FQ fall back to F below the
+  cutoff q_min (0.01 in the paper).
+
+Status: the s-rule and Lagrange weights are pinned against the printed BFL and
+ELIBB-U coefficients and against polynomial exactness; the assembly is pinned by
+exact invariants (rest state, co-moving uniform flow) and by the q = 1/2
+reduction to textbook half-way bounce-back with Ladd's correction.
+"""
+import numpy as np
+
+VARIANTS = ("FQ", "F", "UQ", "U", "HWBB")
+
+# s-coordinate of each interpolation point as a function of q (eq. x_to_s_helper)
+S_OF_POINT = {
+    "P0": lambda q: np.zeros_like(q),
+    "P1": lambda q: np.ones_like(q),
+    "P2": lambda q: 1.0 - q,
+    "P3": lambda q: 1.0 + q,
+    # f_ibar^*(x_FF), the non-local population of the BFL scheme (not used by ELIBB)
+    "PFF": lambda q: -q,
+}
+POINTS = ("P0", "P1", "P2", "P3")
+
+
+def bfl_coefficients(q):
+    """Linear BFL weights from the same s-rule (oracle-only comparator, Sec. II.B).
+
+    q < 1/2: points {PFF (s=-q), P2 (s=1-q)};  q >= 1/2: points {P2, P3 (s=1+q)}.
+    Returns dict point -> weight array.
+    """
+    q = np.asarray(q, dtype=np.float64)
+    out = {"PFF": np.zeros_like(q), "P2": np.zeros_like(q), "P3": np.zeros_like(q)}
+    for sel, key in ((q < 0.5, ("PFF", "P2")), (q >= 0.5, ("P2", "P3"))):
+        if sel.any():
+            qs = q[sel]
+            for p, a in zip(key, lagrange_weights([S_OF_POINT[k](qs) for k in key], qs)):
+                out[p][sel] = a
+    return out
+
+
+def point_set(variant, q, q_cut=0.01):
+    """Interpolation points used by a variant for one value of q (Sec. II.D)."""
+    if variant == "HWBB":
+        return ("P2",)
+    if variant == "U":
+        return ("P0", "P1")
+    if variant == "F" or (variant in ("UQ", "FQ") and q < q_cut):
+        return ("P0", "P2") if q < 0.5 else ("P2", "P1")
+    if variant == "UQ":
+        return ("P0", "P2", "P1")
+    if variant == "FQ":
+        return ("P0", "P2", "P1") if q < 0.5 else ("P2", "P1", "P3")
+    raise ValueError(f"unknown variant {variant!r}")
+
+
+def lagrange_weights(s_nodes, s_ref):
+    """Lagrange basis polynomials at s_ref (eq. poli_coeff).
+
+    s_nodes: list of arrays (one per interpolation point); s_ref: array.
+    Returns a list of arrays a_j with sum_j a_j s_j^m = s_ref^m for m <= n.
+    """
+    out = []
+    for j, sj in enumerate(s_nodes):
+        a = np.ones_like(s_ref)
+        for k, sk in enumerate(s_nodes):
+            if k != j:
+                a = a * (s_ref - sk) / (sj - sk)
+        out.append(a)
+    return out
+
+
+def point_set_groups(variant, q, q_cut=0.01):
+    """Vectorised form of point_set: list of (mask, point set) covering all q."""
+    q = np.asarray(q, dtype=np.float64)
+    lo, hi = q < 0.5, q >= 0.5
+    f_sets = [(lo, ("P0", "P2")), (hi, ("P2", "P1"))]
+    if variant == "HWBB":
+        return [(np.ones(q.shape, bool), ("P2",))]
+    if variant == "U":
+        return [(np.ones(q.shape, bool), ("P0", "P1"))]
+    if variant == "F":
+        return f_sets
+    cut = q < q_cut
+    fallback = [(m & cut, key) for m, key in f_sets]
+    if variant == "UQ":
+        return fallback + [(~cut, ("P0", "P2", "P1"))]
+    if variant == "FQ":
+        return fallback + [(~cut & lo, ("P0", "P2", "P1")), (~cut & hi, ("P2", "P1", "P3"))]
+    raise ValueError(f"unknown variant {variant!r}")
+
+
+def coefficients(variant, q, q_cut=0.01):
+    """Coefficient matrix (n_links x 4) on (P0, P1, P2, P3) for an array of q.
+
+    Links are grouped by point set; within a group the generic Lagrange product
+    is evaluated with s_ref = q.
+    """
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    out = np.zeros((q.size, 4), dtype=np.float64)
+    for sel, key in point_set_groups(variant, q, q_cut):
+        if not sel.any():
+            continue
+        qs = q[sel]
+        s_nodes = [S_OF_POINT[p](qs) for p in key]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            weights = lagrange_weights(s_nodes, qs)
+        for p, a in zip(key, weights):
+            out[sel, POINTS.index(p)] = a
+    # The unified quadratic point set {P0 (s=0), P2 (s=1-q), P1 (s=1)} has two
+    # coincident nodes at q = 1 exactly (the node next to a wall point lying on
+    # a lattice node).  The Lagrange weights are continuous there; take their
+    # limit q -> 1: a(P0) -> -1, a(P2) -> 1, a(P1) -> 1.
+    if variant == "UQ":
+        at_one = q == 1.0
+        out[at_one] = (-1.0, 1.0, 1.0, 0.0)
+    return out
+
+
+def equilibrium_dir(lat, i, rho, u):
+    """Second-order equilibrium of direction(s) i (eq. Eq2ndOrder) for given rho, u.
+
+    i: int array (n,), rho: (n,), u: (3, n).
+    """
+    c = lat.c[i].T.astype(np.float64)          # (3, n)
+    w = lat.w[i]
+    cu = (c * u).sum(axis=0)
+    uu = (u * u).sum(axis=0)
+    cs2 = lat.cs2
+    return w * rho * (1.0 + cu / cs2 + (cu * cu - cs2 * uu) / (2.0 * cs2 * cs2))
+
+
+def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1):
+    """The four interpolation quantities P0..P3 for links with missing direction i.
+
+    i: (n,) missing directions; rho_F: (n,) density of node F at t;
+    feq_F, f_F, fstar_F: (Q, n) equilibrium, pre- and post-collision populations
+    of node F at time t; uw_t, uw_t1: (3, n) wall velocity at x_W at t and t+1.
+    Returns P (4, n).
+    """
+    ib = lat.opp[i]
+    n = np.arange(i.size)
+    n_pre = f_F[ib, n] - feq_F[ib, n]          # bounced pre-collision non-equilibrium (eq. neqbb-s)
+    n_post = fstar_F[ib, n] - feq_F[ib, n]     # bounced post-collision non-equilibrium
+    P0 = equilibrium_dir(lat, i, rho_F, uw_t1) + n_pre
+    P1 = equilibrium_dir(lat, i, rho_F, uw_t) + n_post
+    cu_w = (lat.c[i].T.astype(np.float64) * uw_t).sum(axis=0)
+    P2 = fstar_F[ib, n] + 2.0 * lat.w[i] * rho_F * cu_w / lat.cs2   # eq. ME-solid-to-fluid
+    P3 = fstar_F[i, n]
+    return np.stack([P0, P1, P2, P3])
+
+
+def reconstruct(coef, P):
+    """f_i(x_F, t+1) = sum_k a_k P_k  (eq. interpolated_bb_equation)."""
+    return (coef.T * P).sum(axis=0)

@@ -1,0 +1,210 @@
+"""One lattice-Boltzmann time step with ELIBB boundaries, plain FP64 NumPy.
+
+State: the pre-collision populations f_i(x, t) of every fluid node (NaN on solid
+nodes, so that a read of solid data poisons the result).  One step t -> t+1
+(Sec. II.A, eq. LBE; Sec. II.B-E):
+
+1. moments at every fluid node: rho = sum_i f_i, rho u = sum_i c_i f_i + F/2
+   (the F/2 shift belongs to Guo's forcing, a textbook addition: the paper has no
+   body force);
+2. collision: f*_i = f_i - omega (f_i - f^eq_i(rho, u)) + (1 - omega/2) S_i with
+   omega = 1/tau (eq. LB-BGK, tau = taubar + 1/2) and the second-order
+   equilibrium (eq. Eq2ndOrder); S_i is Guo's source term;
+3. streaming: f_i(x, t+1) = f*_i(x - c_i, t) for every pair that is not a cut
+   link, wrapping on periodic axes (eq. LBE);
+4. zero-gradient outlet (a reading: open boundaries are outside the paper);
+5. every cut link is rebuilt by the ELIBB (eq. ELIBB-general) from node F's own
+   time-t data (see oracle.boundary).
+
+Fresh-node refill for moving bodies (Sec. III.C and the LIR appendix, which is
+run before collide-and-stream; the LIR algorithm itself is only in a missing
+figure) is replaced by an equilibrium refill: a node that became fluid takes
+f^eq(rho_bar, u_body(x)), rho_bar the mean density of its neighbours that hold
+valid populations (rho0 if there are none).
+
+Status: pinned -- exact invariants (rest, co-moving uniform flow, periodic mass
+and momentum, momentum growth by F per node and step under Guo forcing), the
+textbook half-way bounce-back reduction, and closed-form flows (circular
+Couette, impulsively started Couette, force-driven Poiseuille); the outlet and
+the refill are "parity unpinned" beyond self-consistency checks.
+"""
+import numpy as np
+
+from . import boundary
+
+
+def equilibrium(lat, rho, u):
+    """f^eq_i(rho, u) for all i (eq. Eq2ndOrder).  rho (n,), u (3, n) -> (Q, n)."""
+    cs2 = lat.cs2
+    c = lat.c.astype(np.float64)                 # (Q, 3)
+    cu = c @ u                                   # (Q, n)
+    uu = (u * u).sum(axis=0)                     # (n,)
+    return lat.w[:, None] * rho[None, :] * (1.0 + cu / cs2 + (cu * cu - cs2 * uu[None, :]) / (2.0 * cs2 * cs2))
+
+
+def moments(lat, f, force):
+    """rho and u of populations f (Q, n); u includes the F/2 shift of Guo's scheme."""
+    rho = f.sum(axis=0)
+    j = lat.c.astype(np.float64).T @ f           # (3, n)
+    u = (j + 0.5 * np.asarray(force, dtype=np.float64)[:, None]) / rho[None, :]
+    return rho, u
+
+
+def guo_source(lat, u, force):
+    """S_i = w_i [ (c_i - u)/cs2 + (c_i . u) c_i / cs2^2 ] . F   (Guo, Zheng & Shi 2002)."""
+    cs2 = lat.cs2
+    F = np.asarray(force, dtype=np.float64)
+    c = lat.c.astype(np.float64)
+    cF = c @ F                                   # (Q,)
+    uF = F @ u                                   # (n,)
+    cu = c @ u                                   # (Q, n)
+    return lat.w[:, None] * ((cF[:, None] - uF[None, :]) / cs2 + cu * cF[:, None] / (cs2 * cs2))
+
+
+def collide(lat, f, tau, force):
+    """BGK collision with Guo forcing. Returns f*, rho, u, f^eq (all on the given nodes)."""
+    omega = 1.0 / tau
+    rho, u = moments(lat, f, force)
+    feq = equilibrium(lat, rho, u)
+    fstar = f - omega * (f - feq)
+    if np.any(np.asarray(force) != 0.0):
+        fstar = fstar + (1.0 - 0.5 * omega) * guo_source(lat, u, force)
+    return fstar, rho, u, feq
+
+
+class Simulation:
+    """A lattice with a fixed (or externally updated) geometry and link list."""
+
+    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0)):
+        self.dom = dom
+        self.lat = dom.lat
+        self.tau = float(tau)
+        self.force = np.asarray(force, dtype=np.float64).reshape(3)
+        self.rho0 = float(rho0)
+        self.u0 = np.asarray(u0, dtype=np.float64).reshape(3)
+        self.f = None
+        self.fluid = None
+        self.t = 0
+
+    # -- geometry -----------------------------------------------------------------
+    def set_geometry(self, fluid, links, variant="FQ", q_cut=0.01):
+        """Install a fluid mask and a cut-link list (dict from oracle.geometry.cut_links)."""
+        dom, lat = self.dom, self.lat
+        fl = np.asarray(fluid, dtype=bool).reshape(-1)
+        self.fluid = fl
+        self.variant, self.q_cut = variant, float(q_cut)
+        L = {k: np.asarray(v) for k, v in links.items()}
+        self.links = L
+        self.coef = boundary.coefficients(variant, L["q"], q_cut)
+        cut = np.zeros((lat.q, dom.N), dtype=bool)
+        if L["node"].size:
+            if not fl[L["node"]].all():
+                raise ValueError("a link starts on a non-fluid node")
+            if (L["dir"] == 0).any():
+                raise ValueError("direction 0 cannot be cut")
+            if np.any(cut[L["dir"], L["node"]]):
+                raise ValueError("duplicate link")
+            cut[L["dir"], L["node"]] = True
+            if np.unique(L["dir"] * dom.N + L["node"]).size != L["node"].size:
+                raise ValueError("duplicate link")
+        X = dom.coords()
+        nodes = np.flatnonzero(fl)
+        self.stream, self.outlet = [], []
+        from .geometry import _source, _index, beyond_outlet, outlet_producer
+        for i in range(lat.q):
+            xs = X[:, nodes]
+            src, inside = _source(dom, xs.copy(), lat.c[i])
+            sidx = np.where(inside, _index(dom, np.where(inside, src, 0)), 0)
+            ok = inside & fl[sidx] & ~cut[i, nodes]
+            if (inside & fl[sidx] & cut[i, nodes]).any():
+                raise ValueError(f"direction {i}: a link whose source node is fluid")
+            self.stream.append((nodes[ok], sidx[ok]))
+            rest = ~ok & ~cut[i, nodes]
+            od, osrc = np.zeros(0, np.int64), np.zeros(0, np.int64)
+            if rest.any() and dom.outlet_face is not None:
+                bo = beyond_outlet(dom, src[:, rest])
+                prod = outlet_producer(dom, fl, xs[:, rest], lat.c[i])
+                good = bo & (prod >= 0)
+                od, osrc = nodes[rest][good], prod[good]
+                rest_idx = np.flatnonzero(rest)[good]
+                rest[rest_idx] = False
+            if rest.any():
+                bad = nodes[np.flatnonzero(rest)[0]]
+                raise ValueError(f"population (node={bad}, dir={i}) is neither streamed nor covered by a link")
+            self.outlet.append((od, osrc))
+
+    # -- state --------------------------------------------------------------------
+    def init_equilibrium(self, rho=None, u=None):
+        lat, N = self.lat, self.dom.N
+        rho = np.full(N, self.rho0) if rho is None else np.asarray(rho, dtype=np.float64).reshape(N)
+        u = np.repeat(self.u0.reshape(3, 1), N, axis=1) if u is None else np.asarray(u, dtype=np.float64).reshape(3, N)
+        self.f = np.full((lat.q, N), np.nan)
+        fl = self.fluid
+        self.f[:, fl] = equilibrium(lat, rho[fl], u[:, fl])
+        self.t = 0
+
+    def step(self):
+        lat = self.lat
+        fl = self.fluid
+        nodes = np.flatnonzero(fl)
+        f = self.f
+        fstar = np.full_like(f, np.nan)
+        feq = np.full_like(f, np.nan)
+        rho = np.full(f.shape[1], np.nan)
+        u = np.full((3, f.shape[1]), np.nan)
+        fs, r, uu, fe = collide(lat, f[:, nodes], self.tau, self.force)
+        fstar[:, nodes], rho[nodes], u[:, nodes], feq[:, nodes] = fs, r, uu, fe
+        fnew = np.full_like(f, np.nan)
+        for i in range(lat.q):
+            dst, src = self.stream[i]
+            fnew[i, dst] = fstar[i, src]
+            od, osrc = self.outlet[i]
+            fnew[i, od] = fstar[i, osrc]
+        L = self.links
+        if L["node"].size:
+            n, d = L["node"], L["dir"]
+            P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"])
+            fnew[d, n] = boundary.reconstruct(self.coef, P)
+        self.f = fnew
+        self.t += 1
+
+    def run(self, n):
+        for _ in range(int(n)):
+            self.step()
+
+    def macros(self):
+        """rho (N,) and u (3, N) of the current state; NaN on solid nodes."""
+        rho, u = moments(self.lat, self.f, self.force)
+        return rho, u
+
+    # -- moving geometry ----------------------------------------------------------
+    def refill(self, new_fluid, u_body):
+        """Equilibrium refill of nodes that become fluid (old solid -> new fluid).
+
+        u_body: (3, N) body velocity used at the fresh nodes.  Must be called with
+        the new geometry before the step that first uses it.
+        """
+        lat, dom = self.lat, self.dom
+        new_fl = np.asarray(new_fluid, dtype=bool).reshape(-1)
+        old_fl = self.fluid
+        fresh = new_fl & ~old_fl
+        valid = new_fl & old_fl
+        rho_all = np.where(valid, np.nan_to_num(self.f).sum(axis=0), 0.0)
+        X = dom.coords()
+        idx = np.flatnonzero(fresh)
+        f = self.f.copy()
+        f[:, ~new_fl] = np.nan
+        if idx.size:
+            tot = np.zeros(idx.size)
+            cnt = np.zeros(idx.size)
+            from .geometry import _source, _index
+            for j in range(1, lat.q):
+                nb, inside = _source(dom, X[:, idx].copy(), -lat.c[j])     # x + c_j
+                nidx = np.where(inside, _index(dom, np.where(inside, nb, 0)), 0)
+                ok = inside & valid[nidx]
+                tot += np.where(ok, rho_all[nidx], 0.0)
+                cnt += ok
+            rho_bar = np.where(cnt > 0, tot / np.maximum(cnt, 1), self.rho0)
+            f[:, idx] = equilibrium(lat, rho_bar, np.asarray(u_body)[:, idx])
+        self.f = f
+        return idx

@@ -1,0 +1,181 @@
+/*
+ * liblbm -- fused lattice-Boltzmann BGK collide-stream step with the enhanced
+ * local interpolated bounce-back (ELIBB) boundary condition of Marson,
+ * Thorimbert, Latt & Chopard, "Enhanced single-node boundary condition for the
+ * Lattice Boltzmann Method" (arXiv 2009.04604), for AMD Instinct MI355X (gfx950).
+ *
+ * Conventions used by every call
+ * ------------------------------
+ * - Lattice units throughout.  Node index n = x + nx * (y + ny * z),
+ *   0 <= x < nx, 0 <= y < ny, 0 <= z < nz (nz == 1 for D2Q9).
+ * - Direction order (both lattices; Sec. II.A uses the standard velocity sets):
+ *     D2Q9   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(1,-1) 7:(-1,1) 8:(-1,-1)
+ *     D3Q19  0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..10 = (+-1,+-1,0); 11..14 = (+-1,0,+-1);
+ *            15..18 = (0,+-1,+-1); each group in sign order (+,+),(+,-),(-,+),(-,-).
+ * - Population arrays exchanged with the host are [Q][N] float64, N = nx*ny*nz.
+ * - Host pointers passed in are caller-owned and only read (or written) during
+ *   the call.  Device memory is library-owned unless the caller hands an arena.
+ * - Every call returns LBM_OK (0) or a negative code; lbm_last_error() then
+ *   gives a message for the calling thread.  A failed call leaves the domain as
+ *   it was, except where stated.
+ * - All device work is enqueued on the domain's stream (a hipStream_t, e.g.
+ *   torch.cuda.current_stream().cuda_stream); only calls that return data to
+ *   the host synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument; nothing was changed                  */
+  LBM_ENOMEM = -2,    /* device or host allocation failed                       */
+  LBM_EDEVICE = -3,   /* HIP runtime error (no device, launch failure, ...)     */
+  LBM_EUNSTABLE = -4, /* NaN/Inf in the populations (returned by lbm_macros)    */
+  LBM_ESTATE = -5     /* call not valid in the domain's current state           */
+};
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+
+/* Storage of the populations.  Collision arithmetic is FP64 for LBM_F64 and
+ * FP32 for the others; the 16-bit forms store h_i = f_i - w_i rounded to
+ * nearest even and convert back to FP32 on load. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFTED = 2, LBM_BF16_SHIFTED = 3 };
+
+/* Boundary variants (Sec. II.D).  ELIBB-FQ is the default.  UQ and FQ fall back
+ * to ELIBB-F below q_cutoff.  LBM_HWBB is half-way bounce-back with Ladd's
+ * moving-wall term (eq. ME-solid-to-fluid). */
+enum { LBM_ELIBB_FQ = 0, LBM_ELIBB_F = 1, LBM_ELIBB_UQ = 2, LBM_ELIBB_U = 3, LBM_HWBB = 4 };
+
+/* Domain faces: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z. */
+enum { LBM_FACE_NONE = -1 };
+
+typedef struct lbm_domain_s* lbm_domain;
+
+typedef struct {
+  int32_t lattice;       /* LBM_D2Q9 or LBM_D3Q19                                     */
+  int32_t nx, ny, nz;    /* lattice size; nz must be 1 for D2Q9                       */
+  int32_t periodic;      /* bit0 x, bit1 y, bit2 z                                    */
+  int32_t storage;       /* LBM_F64 / LBM_F32 / LBM_F16_SHIFTED / LBM_BF16_SHIFTED    */
+  double tau;            /* BGK relaxation time tau = taubar + 1/2 (eq. LB-BGK), > 0.5 */
+  double force[3];       /* constant body-force density (Guo forcing); zeros = off    */
+  double rho0, u0[3];    /* initial equilibrium state                                 */
+  int32_t outlet_face;   /* face with zero-gradient outflow, or LBM_FACE_NONE; must be
+                            on a non-periodic axis                                     */
+  void* stream;          /* hipStream_t for all device work; NULL = default stream     */
+  void* arena;           /* optional caller-owned device memory for the two population
+                            buffers (>= lbm_arena_bytes(desc) bytes, 256-byte aligned);
+                            NULL = the library allocates them                          */
+  size_t arena_bytes;
+} lbm_domain_desc;
+
+/* Bytes of the two population buffers of a domain (what an arena must hold). */
+size_t lbm_arena_bytes(const lbm_domain_desc* d);
+
+/* Create a domain (Sec. II.A lattice, eq. LBE).  fluid_mask: host, N bytes, 1 =
+ * fluid node, 0 = solid.  All fluid nodes start at f^eq(rho0, u0) (eq.
+ * Eq2ndOrder).  Faces on non-periodic axes are walls or the outlet; every
+ * population they leave missing must be covered by lbm_set_boundary_links
+ * before the first step.  Errors: LBM_EINVAL (sizes, tau <= 0.5, enum values,
+ * outlet face on a periodic axis), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_init_domain(const lbm_domain_desc* d, const uint8_t* fluid_mask, lbm_domain* out);
+
+/* Install the cut-link list (replaces any previous list) -- Sec. II.B-E.
+ * A link (node, dir) names the population f_dir that is missing at the fluid
+ * boundary node `node` after streaming, because node - c_dir is solid or lies
+ * beyond a non-periodic face.  Its f_dir(x_F, t+1) is rebuilt by eq.
+ * ELIBB-general from the node's own time-t data:
+ *   q      (0, 1]: |x_W - x_F| / |c_dir|, x_W the first wall crossing
+ *   uw_t   [3*n] wall velocity at x_W at time t (NULL: wall at rest)
+ *   uw_t1  [3*n] wall velocity at x_W at time t+1 (NULL: equal to uw_t)
+ * Velocity triples are (x, y, z) per link; z ignored for D2Q9.
+ * Validation (LBM_EINVAL, message names the first offending link): node is a
+ * fluid node; 1 <= dir < Q; node - c_dir is not a fluid node; the pair is not
+ * covered by the outlet; 0 < q <= 1; no duplicate (node, dir); every missing
+ * population of every fluid node is covered by a link or by the outlet;
+ * variant in range; q_cutoff >= 0 (the paper uses 0.01).  Host arrays are
+ * copied. */
+int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir,
+                           const double* q, const double* uw_t, const double* uw_t1,
+                           int32_t variant, double q_cutoff);
+
+/* Advance n_steps >= 0 time steps (collide, stream, rebuild every cut link);
+ * asynchronous on the domain's stream.  LBM_ESTATE if links are missing. */
+int lbm_step(lbm_domain d, int32_t n_steps);
+
+/* Moments of the current pre-collision state (time t): rho [N], u [N*D] (node-
+ * major: u[n*D + a]) -- solid nodes get 0 -- and sums = {mass, mom_x, mom_y,
+ * (mom_z), residual} summed over fluid nodes in FP64 in a fixed order (same
+ * result every call for the same state).  u includes Guo's F/2 shift.  The
+ * residual is ||u - u_prev|| / ||u|| where u_prev is the field at the previous
+ * lbm_macros call (the initial field for the first call).  Any pointer may be
+ * NULL.  Synchronises the stream.  Returns LBM_EUNSTABLE if a NaN/Inf was found
+ * (outputs are still written). */
+int lbm_macros(lbm_domain d, double* rho, double* u, double* sums);
+
+/* Export / import the pre-collision populations f_i(x, t) as [Q][N] float64
+ * (solid nodes read as 0 and are ignored on import).  For 16-bit storage the
+ * import rounds to the storage format.  Both synchronise the stream. */
+int lbm_get_state(lbm_domain d, double* f);
+int lbm_set_state(lbm_domain d, const double* f);
+
+/* Change the stream used by later calls. */
+int lbm_set_stream(lbm_domain d, void* stream);
+
+typedef struct {
+  int64_t n_nodes, n_fluid, n_boundary_nodes, n_links;
+  int64_t population_bytes;   /* both buffers                         */
+  int64_t link_bytes;         /* boundary-node and link records       */
+  int64_t steps_done;
+  int32_t q, storage;
+} lbm_domain_info;
+
+int lbm_get_info(lbm_domain d, lbm_domain_info* info);
+
+/* Release every resource of the domain (does not free a caller arena). */
+int lbm_free_domain(lbm_domain d);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* lbm_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Host geometry builder: fluid mask and cut links with exact intersections
+ * (Sec. II.B: q = |x_W - x_F| / |c_i|, first wall crossing along the link).
+ * A node is fluid iff it is strictly inside the fluid region; a node exactly
+ * on a wall is solid (its neighbours get q = 1).
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_geometry_s* lbm_geometry;
+
+int lbm_geometry_create(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, int32_t periodic,
+                        int32_t outlet_face, lbm_geometry* out);
+/* Sphere (3D) or disk (D2Q9, centre z ignored): solid inside (solid_inside=1) or
+ * outside.  Wall velocity u_w = V + Omega x (x_W - centre) (minimum image on
+ * periodic axes).  V, Omega may be NULL (zero). */
+int lbm_geometry_add_sphere(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
+                            const double V[3], const double Omega[3]);
+/* n solid-inside spheres at rest: centres [3n], radii [n]. */
+int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, const double* radii);
+/* Plane wall parallel to a non-periodic face at distance q_face in (0, 1] from
+ * the first node layer.  Wall velocity uw (NULL = rest); profile 1 scales it by
+ * 4 (y + 1/2)(ny - 1/2 - y) / ny^2 at the wall point (parabolic inlet across y). */
+int lbm_geometry_add_face_wall(lbm_geometry g, int32_t face, double q_face, const double uw[3],
+                               int32_t profile);
+/* Classify nodes and find every cut link.  Outputs counts. */
+int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links);
+/* Copy the results of lbm_geometry_build: mask [N]; node, dir, q [n_links];
+ * uw_t, uw_t1 [3*n_links] (any may be NULL). Links are ordered by node, dir. */
+int lbm_geometry_get(lbm_geometry g, uint8_t* mask, int64_t* node, int8_t* dir, double* q,
+                     double* uw_t, double* uw_t1);
+int lbm_geometry_free(lbm_geometry g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -26,6 +26,7 @@ are pinned against a bisection of the signed distance.
 import numpy as np
 
 FACES = ("-x", "+x", "-y", "+y", "-z", "+z")
+LAM_MIN = 1e-12      # smallest q given to a link whose node lies on the wall within rounding
 
 
 class Domain:
@@ -42,10 +43,11 @@ class Domain:
             assert not self.periodic[outlet_face // 2], "outlet face must be on a non-periodic axis"
         self.N = nx * ny * nz
 
-    def coords(self):
-        """Integer coordinates (3, N) of every node, node index n = x + nx (y + ny z)."""
+    def coords(self, idx=None):
+        """Integer coordinates (3, n) of the given nodes (all by default), node index
+        n = x + nx (y + ny z)."""
         nx, ny, nz = self.n
-        idx = np.arange(self.N)
+        idx = np.arange(self.N) if idx is None else np.asarray(idx, dtype=np.int64)
         return np.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)])
 
     def min_image(self, d):
@@ -89,8 +91,10 @@ class Sphere:
         sq = np.sqrt(np.where(ok, disc, 0.0))
         # |d - lam c|^2 = R^2  <=>  a lam^2 - 2 b lam + c0 = 0
         lam = (b - sq) / a if self.solid_inside else (b + sq) / a
-        good = ok & (lam > 0.0) & (lam <= 1.0 + 1e-12)
-        return np.where(good, np.minimum(lam, 1.0), np.nan)
+        # a fluid node lying on the surface to within rounding gives a root at
+        # lam ~ 0 (possibly -1e-16): it is accepted and clamped to LAM_MIN
+        good = ok & (lam > -1e-12) & (lam <= 1.0 + 1e-12)
+        return np.where(good, np.clip(lam, LAM_MIN, 1.0), np.nan)
 
     def velocity(self, dom, xw):
         r = dom.min_image(xw - self.centre[:, None])
@@ -239,19 +243,24 @@ def beyond_outlet(dom, src):
     return src[a] < 0 if f % 2 == 0 else src[a] >= dom.n[a]
 
 
-def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None):
+def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None, nodes=None):
     """All cut links of a fluid mask.
 
     Returns a dict of arrays: node (n,), dir (n,), q (n,), uw_t (3, n), uw_t1 (3, n).
     Links are ordered by node index, then direction.  ``uw_t1_fn(shape, xw)``
     optionally gives the wall velocity at t+1 (moving bodies); by default the wall
-    velocity does not change over the step.
+    velocity does not change over the step.  ``nodes`` restricts the search to the
+    given fluid nodes (sorted ascending).
     """
     lat = dom.lat
     fl = fluid.reshape(-1)
-    X = dom.coords()
-    xs = X[:, fl]
-    nodes = np.flatnonzero(fl)
+    if nodes is None:
+        nodes = np.flatnonzero(fl)
+    else:
+        nodes = np.asarray(nodes, dtype=np.int64)
+        assert fl[nodes].all() and np.all(np.diff(nodes) > 0)
+    X = dom.coords(nodes)
+    xs = X
     out = {"node": [], "dir": [], "q": [], "uw_t": [], "uw_t1": []}
     for i in range(1, lat.q):
         c = lat.c[i]

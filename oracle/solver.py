@@ -208,3 +208,54 @@ class Simulation:
             f[:, idx] = equilibrium(lat, rho_bar, np.asarray(u_body)[:, idx])
         self.f = f
         return idx
+
+
+def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01):
+    """f(x, t+1) at the given fluid nodes only, from the full state f (Q, N) at t.
+
+    The same step as Simulation.step, evaluated node by node: every pulled
+    population is the post-collision value of its source node (collided here),
+    or the outlet producer's, or the ELIBB value of the node's own cut link.
+    ``links`` must contain every cut link of the requested nodes (other links
+    are ignored).  Returns (Q, len(nodes)).
+    """
+    from .geometry import _source, _index, beyond_outlet, outlet_producer
+    lat = dom.lat
+    fl = np.asarray(fluid, dtype=bool).reshape(-1)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    X = dom.coords()
+    xs = X[:, nodes]
+    out = np.full((lat.q, nodes.size), np.nan)
+    force = np.asarray(force, dtype=np.float64)
+    # the nodes' own collision (needed by their links)
+    fs_self, rho_s, u_s, feq_s = collide(lat, f[:, nodes], tau, force)
+    L = {k: np.asarray(v) for k, v in links.items()}
+    key = L["node"] * lat.q + L["dir"]
+    order = np.argsort(key)
+    for i in range(lat.q):
+        src, inside = _source(dom, xs.copy(), lat.c[i])
+        sidx = np.where(inside, _index(dom, np.where(inside, src, 0)), 0)
+        k = np.searchsorted(key[order], nodes * lat.q + i)
+        k = np.minimum(k, key.size - 1) if key.size else k
+        is_cut = (key.size > 0) & (key[order][k] == nodes * lat.q + i) if key.size else np.zeros(nodes.size, bool)
+        stream = inside & fl[sidx] & ~is_cut
+        if stream.any():
+            fs_src, _, _, _ = collide(lat, f[:, sidx[stream]], tau, force)
+            out[i, stream] = fs_src[i]
+        rest = ~stream & ~is_cut
+        if rest.any() and dom.outlet_face is not None:
+            bo = beyond_outlet(dom, src[:, rest])
+            prod = outlet_producer(dom, fl, xs[:, rest], lat.c[i])
+            good = bo & (prod >= 0)
+            if good.any():
+                fs_p, _, _, _ = collide(lat, f[:, prod[good]], tau, force)
+                idx = np.flatnonzero(rest)[good]
+                out[i, idx] = fs_p[i]
+        if is_cut.any():
+            sel = np.flatnonzero(is_cut)
+            li = order[k[sel]]
+            coef = boundary.coefficients(variant, L["q"][li], q_cut)
+            P = boundary.link_points(lat, np.full(sel.size, i), rho_s[sel], feq_s[:, sel], f[:, nodes[sel]],
+                                     fs_self[:, sel], L["uw_t"][:, li], L["uw_t1"][:, li])
+            out[i, sel] = boundary.reconstruct(coef, P)
+    return out

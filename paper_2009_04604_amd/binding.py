@@ -1,0 +1,323 @@
+"""ctypes binding of liblbm (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies the device memory arena for the population buffers and the
+stream (torch.cuda.current_stream()), nothing else.  The functions keep the
+C names (lbm_init_domain, lbm_set_boundary_links, lbm_step, lbm_macros, ...);
+``Domain`` and ``Geometry`` are thin object wrappers over them.
+
+The library must have been built (``python -m paper_2009_04604_amd.build``);
+loading fails loudly otherwise -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LATTICES = {"D2Q9": 0, "D3Q19": 1}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
+FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
+Q_OF = {"D2Q9": 9, "D3Q19": 19}
+D_OF = {"D2Q9": 2, "D3Q19": 3}
+
+EXPORTED = [
+    "lbm_arena_bytes", "lbm_init_domain", "lbm_set_boundary_links", "lbm_step", "lbm_macros",
+    "lbm_get_state", "lbm_set_state", "lbm_set_stream", "lbm_get_info", "lbm_free_domain",
+    "lbm_last_error", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
+    "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
+]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblbm error {code}: {msg}")
+        self.code = code
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
+        ("force", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 3),
+        ("outlet_face", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_size_t),
+    ]
+
+
+class DomainInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64), ("n_boundary_nodes", ctypes.c_int64),
+        ("n_links", ctypes.c_int64), ("population_bytes", ctypes.c_int64), ("link_bytes", ctypes.c_int64),
+        ("steps_done", ctypes.c_int64), ("q", ctypes.c_int32), ("storage", ctypes.c_int32),
+    ]
+
+
+_lib = None
+P = ctypes.c_void_p
+I32, I64, DBL = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+def lib():
+    """Load liblbm.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_04604_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "lbm_arena_bytes": (ctypes.c_size_t, [P]),
+        "lbm_init_domain": (I32, [P, P, P]),
+        "lbm_set_boundary_links": (I32, [P, I64, P, P, P, P, P, I32, DBL]),
+        "lbm_step": (I32, [P, I32]),
+        "lbm_macros": (I32, [P, P, P, P]),
+        "lbm_get_state": (I32, [P, P]),
+        "lbm_set_state": (I32, [P, P]),
+        "lbm_set_stream": (I32, [P, P]),
+        "lbm_get_info": (I32, [P, P]),
+        "lbm_free_domain": (I32, [P]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_geometry_create": (I32, [I32, I32, I32, I32, I32, I32, P]),
+        "lbm_geometry_add_sphere": (I32, [P, P, DBL, I32, P, P]),
+        "lbm_geometry_add_spheres": (I32, [P, I64, P, P]),
+        "lbm_geometry_add_face_wall": (I32, [P, I32, DBL, P, I32]),
+        "lbm_geometry_build": (I32, [P, P, P]),
+        "lbm_geometry_get": (I32, [P, P, P, P, P, P, P]),
+        "lbm_geometry_free": (I32, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != LBM_OK:
+        raise LBMError(code, lib().lbm_last_error().decode())
+    return code
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, True), force=(0, 0, 0),
+              rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, arena=None, arena_bytes=0):
+    d = DomainDesc()
+    d.lattice = LATTICES[lattice]
+    d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+    d.periodic = sum(int(bool(p)) << a for a, p in enumerate(periodic))
+    d.storage = STORAGE[storage]
+    d.tau = float(tau)
+    for a in range(3):
+        d.force[a] = float(force[a])
+        d.u0[a] = float(u0[a])
+    d.rho0 = float(rho0)
+    d.outlet_face = -1 if outlet_face is None else (FACES[outlet_face] if isinstance(outlet_face, str) else int(outlet_face))
+    d.stream = stream
+    d.arena = arena
+    d.arena_bytes = int(arena_bytes)
+    return d
+
+
+# ---- C names ------------------------------------------------------------------
+def lbm_arena_bytes(desc):
+    return lib().lbm_arena_bytes(ctypes.byref(desc))
+
+
+def lbm_init_domain(desc, fluid_mask):
+    m = np.ascontiguousarray(np.asarray(fluid_mask).reshape(-1), dtype=np.uint8)
+    h = ctypes.c_void_p()
+    _check(lib().lbm_init_domain(ctypes.byref(desc), _ptr(m), ctypes.byref(h)))
+    return h
+
+
+def lbm_set_boundary_links(h, node, dir, q, uw_t=None, uw_t1=None, variant="FQ", q_cutoff=0.01):
+    node = np.ascontiguousarray(node, dtype=np.int64)
+    dir = np.ascontiguousarray(dir, dtype=np.int8)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n = node.size
+
+    def vel(u):
+        if u is None:
+            return None
+        u = np.asarray(u, dtype=np.float64)
+        if u.shape == (3, n):
+            u = u.T
+        return np.ascontiguousarray(u.reshape(n, 3))
+    uw_t, uw_t1 = vel(uw_t), vel(uw_t1)
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    _check(lib().lbm_set_boundary_links(h, n, _ptr(node), _ptr(dir), _ptr(q), _ptr(uw_t), _ptr(uw_t1), v, float(q_cutoff)))
+
+
+def lbm_step(h, n_steps):
+    _check(lib().lbm_step(h, int(n_steps)))
+
+
+def lbm_macros(h, N, D, fields=True):
+    rho = np.empty(N) if fields else None
+    u = np.empty(N * D) if fields else None
+    sums = np.empty(D + 2)
+    code = lib().lbm_macros(h, _ptr(rho), _ptr(u), _ptr(sums))
+    if code not in (LBM_OK, LBM_EUNSTABLE):
+        _check(code)
+    return rho, (u.reshape(N, D) if fields else None), sums, code == LBM_EUNSTABLE
+
+
+def lbm_get_state(h, Q, N):
+    f = np.empty((Q, N))
+    _check(lib().lbm_get_state(h, _ptr(f)))
+    return f
+
+
+def lbm_set_state(h, f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(lib().lbm_set_state(h, _ptr(f)))
+
+
+def lbm_get_info(h):
+    info = DomainInfo()
+    _check(lib().lbm_get_info(h, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in DomainInfo._fields_}
+
+
+def lbm_free_domain(h):
+    _check(lib().lbm_free_domain(h))
+
+
+# ---- object wrappers ----------------------------------------------------------
+class Domain:
+    """One lattice resident on the GPU.
+
+    fluid_mask: (nz, ny, nx) or flat bool array.  The population buffers live in
+    a torch uint8 tensor (the arena) kept alive by this object; work goes to the
+    current torch stream unless ``stream`` is given.
+    """
+
+    def __init__(self, lattice, nx, ny, nz, fluid_mask, tau, storage="f32", periodic=(True, True, True),
+                 force=(0, 0, 0), rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, torch_arena=True):
+        self.lattice, self.storage = lattice, storage
+        self.n = (int(nx), int(ny), int(nz))
+        self.N = int(nx) * int(ny) * int(nz)
+        self.Q, self.D = Q_OF[lattice], D_OF[lattice]
+        if stream is None:
+            stream = _torch_stream()
+        desc = make_desc(lattice, nx, ny, nz, tau, storage, periodic, force, rho0, u0, outlet_face, stream)
+        self._arena = None
+        if torch_arena:
+            import torch
+            nbytes = lbm_arena_bytes(desc)
+            self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._arena.data_ptr()
+            desc.arena = (base + 255) // 256 * 256
+            desc.arena_bytes = nbytes
+        self.desc = desc
+        self.h = lbm_init_domain(desc, fluid_mask)
+
+    def set_boundary_links(self, links=None, variant="FQ", q_cutoff=0.01, **kw):
+        if links is not None:
+            kw = {"node": links["node"], "dir": links["dir"], "q": links["q"],
+                  "uw_t": links.get("uw_t"), "uw_t1": links.get("uw_t1"), **kw}
+        lbm_set_boundary_links(self.h, variant=variant, q_cutoff=q_cutoff, **kw)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+
+    def macros(self, fields=True):
+        """(rho [N], u [N, D], sums, unstable) -- synchronises the stream."""
+        return lbm_macros(self.h, self.N, self.D, fields)
+
+    def get_state(self):
+        return lbm_get_state(self.h, self.Q, self.N)
+
+    def set_state(self, f):
+        lbm_set_state(self.h, f)
+
+    def set_stream(self, stream):
+        _check(lib().lbm_set_stream(self.h, stream))
+
+    def info(self):
+        return lbm_get_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_free_domain(self.h)
+            self.h = None
+            self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    """Host geometry builder (lbm_geometry_*): fluid mask and cut links."""
+
+    def __init__(self, lattice, nx, ny, nz=1, periodic=(True, True, True), outlet_face=None):
+        self.lattice = lattice
+        self.n = (int(nx), int(ny), int(nz))
+        self.N = int(nx) * int(ny) * int(nz)
+        per = sum(int(bool(p)) << a for a, p in enumerate(periodic))
+        of = -1 if outlet_face is None else (FACES[outlet_face] if isinstance(outlet_face, str) else int(outlet_face))
+        h = ctypes.c_void_p()
+        _check(lib().lbm_geometry_create(LATTICES[lattice], int(nx), int(ny), int(nz), per, of, ctypes.byref(h)))
+        self.h = h
+
+    def add_sphere(self, centre, radius, solid_inside=True, V=None, Omega=None):
+        c = np.ascontiguousarray(centre, dtype=np.float64).reshape(3)
+        Vv = None if V is None else np.ascontiguousarray(V, dtype=np.float64).reshape(3)
+        Om = None if Omega is None else np.ascontiguousarray(Omega, dtype=np.float64).reshape(3)
+        _check(lib().lbm_geometry_add_sphere(self.h, _ptr(c), float(radius), int(bool(solid_inside)), _ptr(Vv), _ptr(Om)))
+
+    def add_spheres(self, centres, radii):
+        c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
+        r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+        _check(lib().lbm_geometry_add_spheres(self.h, r.size, _ptr(c), _ptr(r)))
+
+    def add_face_wall(self, face, q_face=0.5, uw=None, profile=0):
+        f = FACES[face] if isinstance(face, str) else int(face)
+        u = None if uw is None else np.ascontiguousarray(uw, dtype=np.float64).reshape(3)
+        _check(lib().lbm_geometry_add_face_wall(self.h, f, float(q_face), _ptr(u), int(profile)))
+
+    def build(self):
+        nf, nl = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lbm_geometry_build(self.h, ctypes.byref(nf), ctypes.byref(nl)))
+        n = nl.value
+        mask = np.empty(self.N, dtype=np.uint8)
+        node = np.empty(n, dtype=np.int64)
+        d = np.empty(n, dtype=np.int8)
+        q = np.empty(n)
+        uw = np.empty((n, 3))
+        uw1 = np.empty((n, 3))
+        _check(lib().lbm_geometry_get(self.h, _ptr(mask), _ptr(node), _ptr(d), _ptr(q), _ptr(uw), _ptr(uw1)))
+        return mask, {"node": node, "dir": d.astype(np.int64), "q": q, "uw_t": uw, "uw_t1": uw1}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lib().lbm_geometry_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

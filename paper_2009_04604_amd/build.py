@@ -1,0 +1,59 @@
+"""Build liblbm.so (the HIP kernels and the C-ABI) for gfx950 in-tree.
+
+    python -m paper_2009_04604_amd.build        # or build() from Python
+
+Every build recompiles from source into paper_2009_04604_amd/liblbm.so.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "liblbm.so")
+BUILD_DIR = os.path.join(HERE, "_build")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
+# device code: gfx950 only; packed FP32 instructions disabled
+DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+SOURCES = ["kernels.hip", "api.cpp", "geometry.cpp"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout)
+        raise RuntimeError(f"compilation failed: {os.path.basename(cmd[-1])}")
+    return r.stdout
+
+
+def build(verbose=False):
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(BUILD_DIR, src + ".o")
+        cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", "-o", obj, path]
+        if src.endswith(".cpp"):
+            # host builder: no FMA contraction, so that the geometry arithmetic
+            # rounds exactly like the plain double-precision definition
+            cmd.insert(1, "-ffp-contract=off")
+        out = _run(cmd)
+        if verbose and out.strip():
+            print(out)
+        objs.append(obj)
+    tmp = OUT + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
+    os.replace(tmp, OUT)
+    return OUT
+
+
+def clean():
+    shutil.rmtree(BUILD_DIR, ignore_errors=True)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,573 @@
+// C-ABI of liblbm: domain management, validation of the cut-link list, and the
+// host side of the step / moments / state calls.  See include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "elibb.hpp"
+#include "error.hpp"
+#include "internal.hpp"
+#include "lattice.hpp"
+#include "storage.hpp"
+
+using namespace lbm;
+
+namespace lbm {
+thread_local std::string g_err;
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace lbm
+
+namespace {
+
+int fail(int code, const std::string& msg) { return set_error(code, msg); }
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(LBM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Lat {
+  int Q, D;
+  int c[19][3];
+  double w[19];
+};
+
+template <class L>
+Lat make_lat() {
+  Lat l{};
+  l.Q = L::Q;
+  l.D = L::D;
+  for (int i = 0; i < L::Q; ++i) {
+    l.c[i][0] = L::cx(i);
+    l.c[i][1] = L::cy(i);
+    l.c[i][2] = L::cz(i);
+    l.w[i] = L::w(i);
+  }
+  return l;
+}
+
+const Lat& lat_of(int lattice) {
+  static const Lat a = make_lat<D2Q9>(), b = make_lat<D3Q19>();
+  return lattice == LBM_D2Q9 ? a : b;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename P>
+int dalloc(P*& p, size_t bytes) {
+  void* q = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                                   std::string("hipMalloc: ") + hipGetErrorString(e));
+  p = static_cast<P*>(q);
+  return LBM_OK;
+}
+
+// Source of the pull x - c_i: returns false if outside a non-periodic face;
+// otherwise writes the wrapped coordinates.
+bool pull_source(const lbm_domain_s* d, const int c[3], int x, int y, int z, int s[3]) {
+  const int n[3] = {d->g.nx, d->g.ny, d->g.nz};
+  const int per[3] = {d->g.perx, d->g.pery, d->g.perz};
+  const int p[3] = {x, y, z};
+  bool inside = true;
+  for (int a = 0; a < 3; ++a) {
+    int v = p[a] - c[a];
+    if (per[a]) {
+      v = (v % n[a] + n[a]) % n[a];
+    } else if (v < 0 || v >= n[a]) {
+      inside = false;
+    }
+    s[a] = v;
+  }
+  return inside;
+}
+
+// For a pull source beyond the outlet face: node index of the producer (the
+// source brought back onto the face layer) if it exists and is fluid, else -1.
+int64_t outlet_producer(const lbm_domain_s* d, const int s[3]) {
+  const int f = d->desc.outlet_face;
+  if (f < 0) return -1;
+  const int a = f >> 1;
+  const int n[3] = {d->g.nx, d->g.ny, d->g.nz};
+  const bool beyond = (f & 1) ? s[a] >= n[a] : s[a] < 0;
+  if (!beyond) return -1;
+  int p[3] = {s[0], s[1], s[2]};
+  p[a] = (f & 1) ? n[a] - 1 : 0;
+  for (int b = 0; b < 3; ++b)
+    if (p[b] < 0 || p[b] >= n[b]) return -1;
+  const int64_t idx = p[0] + (int64_t)n[0] * (p[1] + (int64_t)n[1] * p[2]);
+  return d->mask[idx] ? idx : -1;
+}
+
+StepParams step_params(lbm_domain_s* d) {
+  StepParams p{};
+  p.g = d->g;
+  p.src = d->buf[d->cur];
+  p.dst = d->buf[1 - d->cur];
+  p.seg_fluid = d->seg_fluid;
+  p.seg_bnd = d->seg_bnd;
+  p.seg_bbase = d->seg_bbase;
+  p.bmask = d->bmask;
+  p.blink = d->blink;
+  p.lq = d->lq;
+  p.lg = d->lg;
+  p.omega = 1.0 / d->desc.tau;
+  for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
+  p.has_force = (d->desc.force[0] != 0.0 || d->desc.force[1] != 0.0 || d->desc.force[2] != 0.0);
+  p.variant = d->variant;
+  p.q_cut = d->q_cut;
+  p.outlet_face = d->desc.outlet_face;
+  return p;
+}
+
+// Count populations of fluid nodes that are neither streamed nor outlet-covered
+// and not in `linked` (per-node direction mask; may be empty).
+int64_t first_uncovered(const lbm_domain_s* d, const std::vector<uint32_t>& linked, int* bad_dir) {
+  const Lat& L = lat_of(d->desc.lattice);
+  const int nx = d->g.nx, ny = d->g.ny, nz = d->g.nz;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+        if (!d->mask[n]) continue;
+        for (int i = 1; i < L.Q; ++i) {
+          int s[3];
+          const bool inside = pull_source(d, L.c[i], x, y, z, s);
+          if (inside && d->mask[s[0] + (int64_t)nx * (s[1] + (int64_t)ny * s[2])]) continue;
+          if (!linked.empty() && ((linked[n] >> i) & 1u)) continue;
+          if (!inside && outlet_producer(d, s) >= 0) continue;
+          *bad_dir = i;
+          return n;
+        }
+      }
+  return -1;
+}
+
+void free_links(lbm_domain_s* d) {
+  dfree(d->bmask);
+  dfree(d->blink);
+  dfree(d->lq);
+  dfree(d->lg);
+  d->nb = d->nl = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return lbm::g_err.c_str(); }
+
+size_t lbm_arena_bytes(const lbm_domain_desc* d) {
+  if (!d || (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)) return 0;
+  const int Q = d->lattice == LBM_D2Q9 ? 9 : 19;
+  const int64_t NX = d->nx + ((d->periodic & 1) ? 0 : 2);
+  const int64_t NY = d->ny + ((d->periodic & 2) ? 0 : 2);
+  const int64_t NZ = d->lattice == LBM_D2Q9 ? 1 : d->nz + ((d->periodic & 4) ? 0 : 2);
+  const size_t one = (size_t)(NX * NY * NZ) * Q * storage_bytes(d->storage);
+  const size_t aligned = (one + 255) / 256 * 256;
+  return 2 * aligned;
+}
+
+int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_domain* out) {
+  if (!desc || !fluid_mask || !out) return fail(LBM_EINVAL, "null argument");
+  const lbm_domain_desc& d = *desc;
+  if (d.lattice != LBM_D2Q9 && d.lattice != LBM_D3Q19) return fail(LBM_EINVAL, "lattice must be LBM_D2Q9 or LBM_D3Q19");
+  if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
+  if (d.lattice == LBM_D2Q9 && d.nz != 1) return fail(LBM_EINVAL, "nz must be 1 for D2Q9");
+  if (d.storage < LBM_F64 || d.storage > LBM_BF16_SHIFTED) return fail(LBM_EINVAL, "invalid storage");
+  if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return fail(LBM_EINVAL, "tau must be finite and > 0.5");
+  if (!(d.rho0 > 0.0) || !std::isfinite(d.rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d.force[a]) || !std::isfinite(d.u0[a])) return fail(LBM_EINVAL, "non-finite force or u0");
+  if (d.lattice == LBM_D2Q9 && (d.force[2] != 0.0 || d.u0[2] != 0.0)) return fail(LBM_EINVAL, "z components must be 0 for D2Q9");
+  int per = d.periodic;
+  if (d.lattice == LBM_D2Q9) per |= 4;
+  if (d.outlet_face < -1 || d.outlet_face > 5) return fail(LBM_EINVAL, "outlet_face out of range");
+  if (d.outlet_face >= 0 && ((per >> (d.outlet_face >> 1)) & 1)) return fail(LBM_EINVAL, "outlet face lies on a periodic axis");
+  const int64_t N = (int64_t)d.nx * d.ny * d.nz;
+  const size_t need = lbm_arena_bytes(desc);
+  if (d.arena && d.arena_bytes < need) return fail(LBM_EINVAL, "arena too small: need " + std::to_string(need) + " bytes");
+  if (d.arena && ((uintptr_t)d.arena & 255)) return fail(LBM_EINVAL, "arena must be 256-byte aligned");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(LBM_EDEVICE, "no HIP device");
+
+  auto* dm = new lbm_domain_s();   // value-initialised: every pointer null, counters 0
+  dm->desc = d;
+  dm->desc.periodic = per;
+  const Lat& L = lat_of(d.lattice);
+  dm->Q = L.Q;
+  dm->D = L.D;
+  GridGeom& g = dm->g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.nz = d.nz;
+  g.perx = per & 1;
+  g.pery = (per >> 1) & 1;
+  g.perz = (per >> 2) & 1;
+  g.px = g.perx ? 0 : 1;
+  g.py = g.pery ? 0 : 1;
+  g.pz = g.perz ? 0 : 1;
+  g.NX = g.nx + 2 * g.px;
+  g.NY = g.ny + 2 * g.py;
+  g.NZ = g.nz + 2 * g.pz;
+  g.nseg_x = (g.nx + SEG - 1) / SEG;
+  g.nseg = (int64_t)g.nseg_x * g.ny * g.nz;
+  g.npad = (int64_t)g.NX * g.NY * g.NZ;
+  dm->N = N;
+  dm->elem = storage_bytes(d.storage);
+  dm->stream = static_cast<hipStream_t>(d.stream);
+  dm->variant = LBM_ELIBB_FQ;
+  dm->q_cut = 0.01;
+  dm->mask.assign(fluid_mask, fluid_mask + N);
+  for (auto& v : dm->mask) v = v ? 1 : 0;
+  dm->n_fluid = std::accumulate(dm->mask.begin(), dm->mask.end(), (int64_t)0);
+
+  auto cleanup = [&](int code) {
+    lbm_free_domain(dm);
+    return code;
+  };
+  const size_t one = need / 2;
+  if (d.arena) {
+    dm->buf[0] = d.arena;
+    dm->buf[1] = static_cast<char*>(d.arena) + one;
+    dm->own_buf = false;
+  } else {
+    dm->own_buf = true;
+    if (int e = dalloc(dm->buf[0], one)) return cleanup(e);
+    if (int e = dalloc(dm->buf[1], one)) return cleanup(e);
+  }
+  hipError_t he = hipMemsetAsync(dm->buf[0], 0, one, dm->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(dm->buf[1], 0, one, dm->stream);
+  if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(he)));
+
+  // segment masks
+  std::vector<uint64_t> sf(g.nseg, 0);
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x)
+        if (dm->mask[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)])
+          sf[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] |= 1ull << (x % SEG);
+  if (int e = dalloc(dm->seg_fluid, g.nseg * 8)) return cleanup(e);
+  if (int e = dalloc(dm->seg_bnd, g.nseg * 8)) return cleanup(e);
+  if (int e = dalloc(dm->seg_bbase, g.nseg * 4)) return cleanup(e);
+  he = hipMemcpyAsync(dm->seg_fluid, sf.data(), g.nseg * 8, hipMemcpyHostToDevice, dm->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bnd, 0, g.nseg * 8, dm->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bbase, 0, g.nseg * 4, dm->stream);
+  if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
+
+  // reductions and the velocity snapshot of the residual
+  dm->red_blocks = (g.nseg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  if (int e = dalloc(dm->partials, dm->red_blocks * NPART * 8)) return cleanup(e);
+  if (int e = dalloc(dm->sums, NPART * 8)) return cleanup(e);
+  if (int e = dalloc(dm->uprev, N * L.D * 8)) return cleanup(e);
+  {
+    std::vector<double> up((size_t)N * L.D, 0.0);
+    for (int64_t n = 0; n < N; ++n)
+      if (dm->mask[n])
+        for (int a = 0; a < L.D; ++a) up[n * L.D + a] = d.u0[a] + 0.5 * d.force[a] / d.rho0;
+    he = hipMemcpy(dm->uprev, up.data(), up.size() * 8, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
+  }
+
+  InitParams ip{};
+  ip.g = g;
+  ip.dst = dm->buf[0];
+  ip.seg_fluid = dm->seg_fluid;
+  ip.f_in = nullptr;
+  ip.rho0 = d.rho0;
+  for (int a = 0; a < 3; ++a) ip.u0[a] = d.u0[a];
+  he = launch_init(d.lattice, d.storage, ip, dm->stream);
+  if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(he)));
+  dm->cur = 0;
+  int bad_dir = 0;
+  dm->links_ok = first_uncovered(dm, {}, &bad_dir) < 0;
+  *out = dm;
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir, const double* q,
+                           const double* uw_t, const double* uw_t1, int32_t variant, double q_cutoff) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (n_links < 0) return fail(LBM_EINVAL, "n_links < 0");
+  if (n_links > 0 && (!node || !dir || !q)) return fail(LBM_EINVAL, "node, dir and q are required");
+  if (variant < LBM_ELIBB_FQ || variant > LBM_HWBB) return fail(LBM_EINVAL, "invalid variant");
+  if (!(q_cutoff >= 0.0) || !std::isfinite(q_cutoff)) return fail(LBM_EINVAL, "q_cutoff must be finite and >= 0");
+  if (n_links >= (int64_t)1 << 31) return fail(LBM_EINVAL, "too many links");
+  const Lat& L = lat_of(d->desc.lattice);
+  const int64_t N = d->N;
+  const int nx = d->g.nx, ny = d->g.ny;
+  auto where = [&](int64_t k) {
+    return "link " + std::to_string(k) + " (node " + std::to_string(node[k]) + ", dir " + std::to_string((int)dir[k]) + ")";
+  };
+  std::vector<int64_t> order(n_links);
+  std::iota(order.begin(), order.end(), 0);
+  for (int64_t k = 0; k < n_links; ++k) {
+    if (node[k] < 0 || node[k] >= N) return fail(LBM_EINVAL, where(k) + ": node out of range");
+    if (dir[k] < 1 || dir[k] >= L.Q) return fail(LBM_EINVAL, where(k) + ": dir out of range");
+    if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1]");
+    for (int a = 0; a < 3; ++a) {
+      if (uw_t && !std::isfinite(uw_t[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t");
+      if (uw_t1 && !std::isfinite(uw_t1[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t1");
+    }
+    if (!d->mask[node[k]]) return fail(LBM_EINVAL, where(k) + ": node is not fluid");
+    const int64_t n = node[k];
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+    int s[3];
+    const bool inside = pull_source(d, L.c[(int)dir[k]], x, y, z, s);
+    if (inside && d->mask[s[0] + (int64_t)nx * (s[1] + (int64_t)ny * s[2])])
+      return fail(LBM_EINVAL, where(k) + ": node - c_dir is a fluid node (not a cut link)");
+    if (!inside && outlet_producer(d, s) >= 0) return fail(LBM_EINVAL, where(k) + ": population is covered by the outlet");
+  }
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return node[a] != node[b] ? node[a] < node[b] : dir[a] < dir[b];
+  });
+  for (int64_t k = 1; k < n_links; ++k)
+    if (node[order[k]] == node[order[k - 1]] && dir[order[k]] == dir[order[k - 1]])
+      return fail(LBM_EINVAL, where(order[k]) + ": duplicate link");
+
+  std::vector<uint32_t> linked(N, 0u);
+  for (int64_t k = 0; k < n_links; ++k) linked[node[k]] |= 1u << dir[k];
+  int bad_dir = 0;
+  const int64_t bad = first_uncovered(d, linked, &bad_dir);
+  if (bad >= 0)
+    return fail(LBM_EINVAL, "population (node " + std::to_string(bad) + ", dir " + std::to_string(bad_dir) +
+                                ") is missing after streaming and not covered by a link");
+
+  // boundary nodes, segment masks and link records
+  const GridGeom& g = d->g;
+  std::vector<uint32_t> bmask;
+  std::vector<int32_t> blink;
+  std::vector<int64_t> bnode;
+  for (int64_t k = 0; k < n_links; ++k) {
+    const int64_t n = node[order[k]];
+    if (bnode.empty() || bnode.back() != n) {
+      bnode.push_back(n);
+      bmask.push_back(0u);
+      blink.push_back((int32_t)k);
+    }
+    bmask.back() |= 1u << dir[order[k]];
+  }
+  std::vector<uint64_t> sb(g.nseg, 0);
+  std::vector<int32_t> sbase(g.nseg, 0);
+  {
+    size_t b = 0;
+    for (int64_t s = 0; s < g.nseg; ++s) {
+      sbase[s] = (int32_t)b;
+      const int64_t row = s / g.nseg_x;
+      const int sx = (int)(s % g.nseg_x);
+      const int64_t first = row * nx + (int64_t)sx * SEG;
+      const int64_t last = row * nx + std::min<int64_t>((int64_t)(sx + 1) * SEG, nx);
+      while (b < bnode.size() && bnode[b] < last) {
+        sb[s] |= 1ull << (bnode[b] - first);
+        ++b;
+      }
+    }
+  }
+  const bool f64 = d->desc.storage == LBM_F64;
+  bool moving = false;
+  for (int64_t k = 0; k < 3 * n_links && !moving; ++k)
+    moving = (uw_t && uw_t[k] != 0.0) || (uw_t1 && uw_t1[k] != 0.0);
+  std::vector<double> qd(n_links), gd(moving ? n_links : 0);
+  for (int64_t k = 0; k < n_links; ++k) {
+    const int64_t o = order[k];
+    qd[k] = q[o];
+    if (moving) {
+      const int i = dir[o];
+      const double* u0 = uw_t ? uw_t + 3 * o : nullptr;
+      const double* u1 = uw_t1 ? uw_t1 + 3 * o : u0;
+      double cu0 = 0, uu0 = 0, cu1 = 0, uu1 = 0;
+      for (int a = 0; a < L.D; ++a) {
+        const double v0 = u0 ? u0[a] : 0.0, v1 = u1 ? u1[a] : 0.0;
+        cu0 += L.c[i][a] * v0;
+        uu0 += v0 * v0;
+        cu1 += L.c[i][a] * v1;
+        uu1 += v1 * v1;
+      }
+      if (f64) {
+        const Coef<double> c = elibb_coefficients<double>(variant, q[o], q_cutoff);
+        gd[k] = wall_term<double>(c, cu0, uu0, cu1, uu1);
+      } else {
+        const Coef<float> c = elibb_coefficients<float>(variant, (float)q[o], (float)q_cutoff);
+        const Coef<double> cd{c.a4, c.a5, c.a2, c.a3};
+        gd[k] = wall_term<double>(cd, cu0, uu0, cu1, uu1);
+      }
+    }
+  }
+  // upload (replace previous arrays)
+  free_links(d);
+  d->links_ok = false;
+  const size_t rs = f64 ? 8 : 4;
+  if (int e = dalloc(d->bmask, bmask.size() * 4)) return e;
+  if (int e = dalloc(d->blink, blink.size() * 4)) return e;
+  if (int e = dalloc(d->lq, qd.size() * rs)) return e;
+  if (moving)
+    if (int e = dalloc(d->lg, gd.size() * rs)) return e;
+  HIP_TRY(hipMemcpy(d->bmask, bmask.data(), bmask.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->blink, blink.data(), blink.size() * 4, hipMemcpyHostToDevice));
+  auto upload_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
+    if (f64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    std::vector<float> f(v.begin(), v.end());
+    return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  };
+  HIP_TRY(upload_real(d->lq, qd));
+  if (moving) HIP_TRY(upload_real(d->lg, gd));
+  HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->seg_bbase, sbase.data(), g.nseg * 4, hipMemcpyHostToDevice));
+  d->nb = (int64_t)bnode.size();
+  d->nl = n_links;
+  d->variant = variant;
+  d->q_cut = q_cutoff;
+  d->links_ok = true;
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_step(lbm_domain d, int32_t n_steps) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (n_steps < 0) return fail(LBM_EINVAL, "n_steps < 0");
+  if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set: some populations would be missing");
+  for (int32_t s = 0; s < n_steps; ++s) {
+    StepParams p = step_params(d);
+    hipError_t e = launch_step(d->desc.lattice, d->desc.storage, p, d->stream);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step kernel: ") + hipGetErrorString(e));
+    d->cur ^= 1;
+    ++d->steps;
+  }
+  return LBM_OK;
+}
+
+int lbm_macros(lbm_domain d, double* rho, double* u, double* sums) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  const int64_t N = d->N;
+  if (rho && !d->rho_tmp)
+    if (int e = dalloc(d->rho_tmp, N * 8)) return e;
+  if (u && !d->u_tmp)
+    if (int e = dalloc(d->u_tmp, N * d->D * 8)) return e;
+  MacroParams p{};
+  p.g = d->g;
+  p.src = d->buf[d->cur];
+  p.seg_fluid = d->seg_fluid;
+  for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
+  p.rho = rho ? d->rho_tmp : nullptr;
+  p.u = u ? d->u_tmp : nullptr;
+  p.uprev = d->uprev;
+  p.partials = d->partials;
+  HIP_TRY(launch_macros(d->desc.lattice, d->desc.storage, p, d->red_blocks, d->stream));
+  HIP_TRY(launch_reduce(d->partials, d->red_blocks, d->sums, d->stream));
+  double h[NPART];
+  HIP_TRY(hipMemcpyAsync(h, d->sums, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  if (rho) HIP_TRY(hipMemcpyAsync(rho, d->rho_tmp, N * 8, hipMemcpyDeviceToHost, d->stream));
+  if (u) HIP_TRY(hipMemcpyAsync(u, d->u_tmp, N * d->D * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  if (sums) {
+    int k = 0;
+    sums[k++] = h[0];
+    sums[k++] = h[1];
+    sums[k++] = h[2];
+    if (d->D == 3) sums[k++] = h[3];
+    sums[k++] = h[5] > 0.0 ? std::sqrt(h[4] / h[5]) : (h[4] > 0.0 ? INFINITY : 0.0);
+  }
+  if (h[6] > 0.0) return fail(LBM_EUNSTABLE, "non-finite density or velocity at " + std::to_string((int64_t)h[6]) + " nodes");
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_domain d, double* f) {
+  if (!d || !f) return fail(LBM_EINVAL, "null argument");
+  double* tmp = nullptr;
+  const size_t bytes = (size_t)d->N * d->Q * 8;
+  if (int e = dalloc(tmp, bytes)) return e;
+  ExportParams p{};
+  p.g = d->g;
+  p.src = d->buf[d->cur];
+  p.seg_fluid = d->seg_fluid;
+  p.f_out = tmp;
+  hipError_t e = launch_export(d->desc.lattice, d->desc.storage, p, d->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, bytes, hipMemcpyDeviceToHost, d->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("get_state: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_domain d, const double* f) {
+  if (!d || !f) return fail(LBM_EINVAL, "null argument");
+  double* tmp = nullptr;
+  const size_t bytes = (size_t)d->N * d->Q * 8;
+  if (int e = dalloc(tmp, bytes)) return e;
+  InitParams p{};
+  p.g = d->g;
+  p.dst = d->buf[d->cur];
+  p.seg_fluid = d->seg_fluid;
+  p.f_in = tmp;
+  hipError_t e = hipMemcpyAsync(tmp, f, bytes, hipMemcpyHostToDevice, d->stream);
+  if (e == hipSuccess) e = launch_init(d->desc.lattice, d->desc.storage, p, d->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_domain d, void* stream) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  d->stream = static_cast<hipStream_t>(stream);
+  d->desc.stream = stream;
+  return LBM_OK;
+}
+
+int lbm_get_info(lbm_domain d, lbm_domain_info* info) {
+  if (!d || !info) return fail(LBM_EINVAL, "null argument");
+  info->n_nodes = d->N;
+  info->n_fluid = d->n_fluid;
+  info->n_boundary_nodes = d->nb;
+  info->n_links = d->nl;
+  info->population_bytes = (int64_t)(2 * d->g.npad * d->Q * d->elem);
+  const int64_t rs = d->desc.storage == LBM_F64 ? 8 : 4;
+  info->link_bytes = d->nb * 8 + d->nl * rs * (d->lg ? 2 : 1) + d->g.nseg * 20;
+  info->steps_done = d->steps;
+  info->q = d->Q;
+  info->storage = d->desc.storage;
+  return LBM_OK;
+}
+
+int lbm_free_domain(lbm_domain d) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (d->stream) (void)hipStreamSynchronize(d->stream);
+  else (void)hipDeviceSynchronize();
+  if (d->own_buf) {
+    dfree(d->buf[0]);
+    dfree(d->buf[1]);
+  }
+  dfree(d->seg_fluid);
+  dfree(d->seg_bnd);
+  dfree(d->seg_bbase);
+  free_links(d);
+  dfree(d->partials);
+  dfree(d->sums);
+  dfree(d->uprev);
+  dfree(d->rho_tmp);
+  dfree(d->u_tmp);
+  delete d;
+  return LBM_OK;
+}
+
+}  // extern "C"

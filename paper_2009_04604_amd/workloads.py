@@ -1,0 +1,65 @@
+"""Workload set-ups on the product path: geometry from the library's host
+builder (lbm_geometry_*), domains on the GPU (lbm_init_domain,
+lbm_set_boundary_links).  Inputs are the seeded recipes of ``synth``.
+"""
+import numpy as np
+
+import synth
+
+from . import binding as B
+
+
+def annulus_geometry(p):
+    """Circular Couette annulus: inner cylinder turning at u_inner, outer at rest."""
+    g = B.Geometry("D2Q9", p["nx"], p["ny"], 1)
+    om1 = p["u_inner"] / p["r1"]
+    g.add_sphere(p["centre"], p["r1"], True, Omega=(0, 0, om1))
+    g.add_sphere(p["centre"], p["r2"], False)
+    mask, links = g.build()
+    g.close()
+    return mask, links
+
+
+def channel_geometry(p):
+    """Channel with a cylinder: parabolic inlet at x = -1/2, walls at y = -1/2 and
+    ny - 1/2, zero-gradient outlet at +x."""
+    nx, ny = p["nx"], p["ny"]
+    g = B.Geometry("D2Q9", nx, ny, 1, periodic=(False, False, True), outlet_face="+x")
+    g.add_sphere(p["centre"], p["radius"], True)
+    g.add_face_wall("-x", 0.5, uw=(p["u_max"], 0, 0), profile=1)
+    g.add_face_wall("-y", 0.5)
+    g.add_face_wall("+y", 0.5)
+    mask, links = g.build()
+    g.close()
+    return mask, links
+
+
+def packing_geometry(n, centres, radii):
+    g = B.Geometry("D3Q19", n, n, n)
+    g.add_spheres(centres, radii)
+    mask, links = g.build()
+    g.close()
+    return mask, links
+
+
+def couette_domain(p, storage="f64", variant="FQ"):
+    mask, links = annulus_geometry(p)
+    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage, rho0=p.get("rho0", 1.0))
+    d.set_boundary_links(links, variant=variant)
+    return d, mask, links
+
+
+def channel_domain(p, storage="f32", variant="FQ"):
+    mask, links = channel_geometry(p)
+    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage,
+                 periodic=(False, False, True), outlet_face="+x")
+    d.set_boundary_links(links, variant=variant)
+    return d, mask, links
+
+
+def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), variant="FQ", spheres=None):
+    centres, radii = synth.sphere_packing(n=n) if spheres is None else spheres
+    mask, links = packing_geometry(n, centres, radii)
+    d = B.Domain("D3Q19", n, n, n, mask, tau, storage=storage, force=force)
+    d.set_boundary_links(links, variant=variant)
+    return d, mask, links

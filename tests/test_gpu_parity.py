@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (relative L2 of the velocity over fluid nodes, all components, after
+the stated step count): FP64 storage 1e-12, FP32 storage 1e-5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import analytic, geometry as G, lattice as OL, metrics, solver
+from tests.gpu_cases import Case, annulus_case, channel_case, fluid_velocity_error
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_couette_annulus_full_run(gpu_lib, storage):
+    """48x48 circular Couette, FQ, 5000 steps (the parity configuration)."""
+    case = annulus_case()
+    _say("case annulus 48x48", storage)
+    d, mask, links = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    steps = 5000
+    d.step(steps)
+    sim.run(steps)
+    err, rg, ro, sums, unstable = fluid_velocity_error(d, sim)
+    _say("rel L2 velocity", err)
+    assert not unstable
+    assert err <= TOL[storage]
+    # mass sum in FP64 on the GPU
+    assert abs(sums[0] - ro.sum()) <= (1e-12 if storage == "f64" else 1e-5) * ro.sum()
+    # the GPU field against the analytic profile (Sec. III.B closed form)
+    rho, u, _, _ = d.macros()
+    X = np.stack(np.meshgrid(np.arange(48), np.arange(48), indexing="xy"), 0).reshape(2, -1).astype(float)
+    fl = mask.astype(bool)
+    r = np.hypot(X[0, fl] - 24, X[1, fl] - 24)
+    e = metrics.rrse(np.linalg.norm(u[fl], axis=1), analytic.circular_couette(r, 8.0, 20.0, 0.01 / 8))
+    assert e < 5e-3
+    d.close()
+
+
+@pytest.mark.parametrize("variant,tau", [("FQ", 0.8), ("F", 0.8), ("UQ", 1.5), ("U", 0.7), ("HWBB", 0.8)])
+def test_couette_variants_f64(gpu_lib, variant, tau):
+    case = annulus_case(tau=tau)
+    _say("case annulus variant", variant, tau)
+    d, _, _ = case.gpu(gpu_lib, "f64", variant)
+    sim = case.oracle(variant)
+    d.step(400)
+    sim.run(400)
+    err = fluid_velocity_error(d, sim)[0]
+    assert err <= 1e-12
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_channel_cylinder(gpu_lib, storage):
+    """Cylinder channel with parabolic inlet, walls and zero-gradient outlet,
+    ragged row length (200 = 3 segments + 8)."""
+    case = channel_case()
+    _say("case channel 200x80", storage)
+    d, _, _ = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    d.step(1500)
+    sim.run(1500)
+    err = fluid_velocity_error(d, sim)[0]
+    _say("rel L2 velocity", err)
+    assert err <= TOL[storage]
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_packing_crop_with_force(gpu_lib, storage):
+    """D3Q19 random packing (the 256^3 recipe at 40^3, radii 3..6) with Guo forcing."""
+    n = 40
+    c, r = synth.sphere_packing(n=n, r_min=3.0, r_max=6.0, solid_fraction=0.4, seed=5)
+    case = Case("D3Q19", (n, n, n), spheres=[(cc, rr, True, None, None) for cc, rr in zip(c, r)],
+                tau=0.9, force=(1e-5, 0.0, 0.0))
+    _say("case packing 40^3", storage)
+    d, _, _ = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    d.step(150)
+    sim.run(150)
+    err = fluid_velocity_error(d, sim)[0]
+    _say("rel L2 velocity", err)
+    assert err <= TOL[storage]
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_ragged_3d_walls_moving_sphere(gpu_lib, storage):
+    """67x29x23 D3Q19: non-periodic y with plane walls at q = 0.3 (top wall
+    sliding), periodic x and z, a rotating translating sphere; ragged rows
+    (67 = 64 + 3)."""
+    case = Case("D3Q19", (67, 29, 23), periodic=(True, False, True),
+                spheres=[((30.4, 14.2, 11.7), 6.3, True, (0.01, -0.005, 0.002), (0.001, 0.0015, -0.002))],
+                faces=[(2, 0.3, None, 0), (3, 0.3, (0.02, 0.0, 0.01), 0)], tau=0.75, rho0=1.02)
+    _say("case ragged 3d", storage)
+    d, _, _ = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    d.step(120)
+    sim.run(120)
+    err = fluid_velocity_error(d, sim)[0]
+    _say("rel L2 velocity", err)
+    assert err <= TOL[storage]
+    d.close()
+
+
+def test_all_fluid_periodic_no_links(gpu_lib):
+    """Empty link list: periodic all-fluid box from a perturbed state."""
+    case = Case("D3Q19", (20, 9, 7), tau=0.7, force=(2e-5, 0, -1e-5))
+    d, _, _ = case.gpu(gpu_lib, "f64")
+    sim = case.oracle()
+    rng = np.random.default_rng(4)
+    sim.f = sim.f * (1.0 + 0.01 * rng.standard_normal(sim.f.shape))
+    d.set_state(sim.f)
+    d.step(30)
+    sim.run(30)
+    f_g = d.get_state()
+    assert np.abs(f_g - sim.f).max() < 1e-14
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_state_roundtrip(gpu_lib, storage):
+    case = annulus_case()
+    d, mask, _ = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    sim.run(20)
+    f = np.nan_to_num(sim.f)
+    d.set_state(f)
+    g = d.get_state()
+    fl = mask.astype(bool)
+    tol = {"f64": 0.0, "f32": 1e-7, "f16s": 2e-4, "bf16s": 2e-3}[storage]
+    assert np.abs(g[:, fl] - f[:, fl]).max() <= tol * max(1.0, np.abs(f).max()) + (0 if storage == "f64" else 1e-12)
+    assert np.all(g[:, ~fl] == 0.0)
+    d.close()
+
+
+def test_sums_are_deterministic_and_consistent(gpu_lib):
+    case = annulus_case()
+    d, mask, _ = case.gpu(gpu_lib, "f32")
+    d.step(100)
+    rho1, u1, s1, _ = d.macros()
+    rho2, u2, s2, _ = d.macros()
+    assert np.array_equal(rho1, rho2) and np.array_equal(u1, u2)
+    assert np.array_equal(s1[:3], s2[:3])
+    assert s2[-1] == 0.0                      # no change since the last query
+    fl = mask.astype(bool)
+    assert abs(s1[0] - rho1[fl].sum()) < 1e-9 * s1[0]
+    d.close()
+
+
+@pytest.mark.parametrize("storage,bound", [("f16s", 3e-2), ("bf16s", 2e-1)])
+def test_shifted_16bit_error_stated(gpu_lib, storage, bound):
+    """16-bit shifted storage on the annulus: error against the FP64 oracle after
+    5000 steps is printed and bounded."""
+    case = annulus_case()
+    d, _, _ = case.gpu(gpu_lib, storage)
+    sim = case.oracle()
+    d.step(5000)
+    sim.run(5000)
+    err = fluid_velocity_error(d, sim)[0]
+    _say(storage, "rel L2 velocity vs FP64 oracle", err)
+    assert err <= bound
+    d.close()

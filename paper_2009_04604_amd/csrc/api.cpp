@@ -116,18 +116,27 @@ int64_t outlet_producer(const lbm_domain_s* d, const int s[3]) {
   return d->mask[idx] ? idx : -1;
 }
 
+// Device view of the links; lv_in / lv_out chosen by the caller.
+LinkView link_view(const lbm_domain_s* d, const void* lv_in, void* lv_out) {
+  LinkView lk{};
+  lk.seg_fluid = d->seg_fluid;
+  lk.seg_bnd = d->seg_bnd;
+  lk.seg_lbase = d->seg_lbase;
+  lk.lld = d->lld;
+  lk.lnode = d->lnode;
+  lk.lq = d->lq;
+  lk.lg = d->lg;
+  lk.lv_in = lv_in;
+  lk.lv_out = lv_out;
+  return lk;
+}
+
 StepParams step_params(lbm_domain_s* d) {
   StepParams p{};
   p.g = d->g;
   p.src = d->buf[d->cur];
   p.dst = d->buf[1 - d->cur];
-  p.seg_fluid = d->seg_fluid;
-  p.seg_bnd = d->seg_bnd;
-  p.seg_bbase = d->seg_bbase;
-  p.bmask = d->bmask;
-  p.blink = d->blink;
-  p.lq = d->lq;
-  p.lg = d->lg;
+  p.lk = link_view(d, d->lv[d->cur], d->lv[1 - d->cur]);
   p.omega = 1.0 / d->desc.tau;
   for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
   p.has_force = (d->desc.force[0] != 0.0 || d->desc.force[1] != 0.0 || d->desc.force[2] != 0.0);
@@ -135,6 +144,32 @@ StepParams step_params(lbm_domain_s* d) {
   p.q_cut = d->q_cut;
   p.outlet_face = d->desc.outlet_face;
   return p;
+}
+
+// Export the current state to a device [Q][N] float64 buffer.
+hipError_t export_state(lbm_domain_s* d, double* dev_f) {
+  ExportParams p{};
+  p.g = d->g;
+  p.src = d->buf[d->cur];
+  p.lk = link_view(d, d->lv[d->cur], nullptr);
+  p.f_out = dev_f;
+  return launch_export(d->desc.lattice, d->desc.storage, p, d->stream);
+}
+
+// Import a state from a device [Q][N] float64 buffer (null: the equilibrium of
+// rho0, u0) into the pull slots and the current link values.
+hipError_t import_state(lbm_domain_s* d, const double* dev_f) {
+  InitParams ip{};
+  ip.g = d->g;
+  ip.dst = d->buf[d->cur];
+  ip.lk = link_view(d, nullptr, d->lv[d->cur]);
+  ip.nlinks = d->nl;
+  ip.f_in = dev_f;
+  ip.rho0 = d->desc.rho0;
+  for (int a = 0; a < 3; ++a) ip.u0[a] = d->desc.u0[a];
+  hipError_t e = launch_init(d->desc.lattice, d->desc.storage, ip, d->stream);
+  if (e == hipSuccess) e = launch_init_links(d->desc.lattice, d->desc.storage, ip, d->stream);
+  return e;
 }
 
 // Count populations of fluid nodes that are neither streamed nor outlet-covered
@@ -161,8 +196,10 @@ int64_t first_uncovered(const lbm_domain_s* d, const std::vector<uint32_t>& link
 }
 
 void free_links(lbm_domain_s* d) {
-  dfree(d->bmask);
-  dfree(d->blink);
+  dfree(d->lld);
+  dfree(d->lnode);
+  dfree(d->lv[0]);
+  dfree(d->lv[1]);
   dfree(d->lq);
   dfree(d->lg);
   d->nb = d->nl = 0;
@@ -230,7 +267,14 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   g.NZ = g.nz + 2 * g.pz;
   g.nseg_x = (g.nx + SEG - 1) / SEG;
   g.nseg = (int64_t)g.nseg_x * g.ny * g.nz;
+  g.div_nseg_x = make_fastdiv((uint32_t)g.nseg_x);
+  g.div_ny = make_fastdiv((uint32_t)g.ny);
+  g.xcd_remap = 0;
   g.npad = (int64_t)g.NX * g.NY * g.NZ;
+  if (g.npad >= ((int64_t)1 << 31)) {
+    delete dm;
+    return fail(LBM_EINVAL, "lattice too large: more than 2^31 padded nodes");
+  }
   dm->N = N;
   dm->elem = storage_bytes(d.storage);
   dm->stream = static_cast<hipStream_t>(d.stream);
@@ -267,14 +311,14 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
           sf[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] |= 1ull << (x % SEG);
   if (int e = dalloc(dm->seg_fluid, g.nseg * 8)) return cleanup(e);
   if (int e = dalloc(dm->seg_bnd, g.nseg * 8)) return cleanup(e);
-  if (int e = dalloc(dm->seg_bbase, g.nseg * 4)) return cleanup(e);
+  if (int e = dalloc(dm->seg_lbase, (g.nseg + 1) * 4)) return cleanup(e);
   he = hipMemcpyAsync(dm->seg_fluid, sf.data(), g.nseg * 8, hipMemcpyHostToDevice, dm->stream);
   if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bnd, 0, g.nseg * 8, dm->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bbase, 0, g.nseg * 4, dm->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(dm->seg_lbase, 0, (g.nseg + 1) * 4, dm->stream);
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
 
   // reductions and the velocity snapshot of the residual
-  dm->red_blocks = (g.nseg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  dm->red_blocks = grid_blocks(g);
   if (int e = dalloc(dm->partials, dm->red_blocks * NPART * 8)) return cleanup(e);
   if (int e = dalloc(dm->sums, NPART * 8)) return cleanup(e);
   if (int e = dalloc(dm->uprev, N * L.D * 8)) return cleanup(e);
@@ -287,14 +331,8 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
     if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
   }
 
-  InitParams ip{};
-  ip.g = g;
-  ip.dst = dm->buf[0];
-  ip.seg_fluid = dm->seg_fluid;
-  ip.f_in = nullptr;
-  ip.rho0 = d.rho0;
-  for (int a = 0; a < 3; ++a) ip.u0[a] = d.u0[a];
-  he = launch_init(d.lattice, d.storage, ip, dm->stream);
+  dm->cur = 0;
+  he = import_state(dm, nullptr);
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(he)));
   dm->cur = 0;
   int bad_dir = 0;
@@ -352,36 +390,25 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
     return fail(LBM_EINVAL, "population (node " + std::to_string(bad) + ", dir " + std::to_string(bad_dir) +
                                 ") is missing after streaming and not covered by a link");
 
-  // boundary nodes, segment masks and link records
+  // segment masks and link records: links sorted by (node, dir) are contiguous
+  // per segment; each carries its node's lane and its direction
   const GridGeom& g = d->g;
-  std::vector<uint32_t> bmask;
-  std::vector<int32_t> blink;
-  std::vector<int64_t> bnode;
+  std::vector<uint64_t> sb(g.nseg, 0);
+  std::vector<int32_t> slb(g.nseg + 1, 0);
+  std::vector<uint16_t> lld(n_links);
+  int64_t nb = 0;
   for (int64_t k = 0; k < n_links; ++k) {
     const int64_t n = node[order[k]];
-    if (bnode.empty() || bnode.back() != n) {
-      bnode.push_back(n);
-      bmask.push_back(0u);
-      blink.push_back((int32_t)k);
-    }
-    bmask.back() |= 1u << dir[order[k]];
+    const int64_t row = n / nx;
+    const int x = (int)(n - row * nx);
+    const int64_t s = row * g.nseg_x + x / SEG;
+    const int lane = x % SEG;
+    if (!((sb[s] >> lane) & 1ull)) ++nb;
+    sb[s] |= 1ull << lane;
+    slb[s + 1] += 1;
+    lld[k] = (uint16_t)(lane | (int(dir[order[k]]) << 8));
   }
-  std::vector<uint64_t> sb(g.nseg, 0);
-  std::vector<int32_t> sbase(g.nseg, 0);
-  {
-    size_t b = 0;
-    for (int64_t s = 0; s < g.nseg; ++s) {
-      sbase[s] = (int32_t)b;
-      const int64_t row = s / g.nseg_x;
-      const int sx = (int)(s % g.nseg_x);
-      const int64_t first = row * nx + (int64_t)sx * SEG;
-      const int64_t last = row * nx + std::min<int64_t>((int64_t)(sx + 1) * SEG, nx);
-      while (b < bnode.size() && bnode[b] < last) {
-        sb[s] |= 1ull << (bnode[b] - first);
-        ++b;
-      }
-    }
-  }
+  for (int64_t s = 0; s < g.nseg; ++s) slb[s + 1] += slb[s];
   const bool f64 = d->desc.storage == LBM_F64;
   bool moving = false;
   for (int64_t k = 0; k < 3 * n_links && !moving; ++k)
@@ -412,27 +439,48 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
       }
     }
   }
+  // the current state (pulled with the old links) survives the replacement
+  double* fstate = nullptr;
+  if (int e = dalloc(fstate, (size_t)N * d->Q * 8)) return e;
+  if (hipError_t he = export_state(d, fstate); he != hipSuccess) {
+    (void)hipFree(fstate);
+    return fail(LBM_EDEVICE, std::string("export: ") + hipGetErrorString(he));
+  }
   // upload (replace previous arrays)
+  HIP_TRY(hipStreamSynchronize(d->stream));
   free_links(d);
   d->links_ok = false;
   const size_t rs = f64 ? 8 : 4;
-  if (int e = dalloc(d->bmask, bmask.size() * 4)) return e;
-  if (int e = dalloc(d->blink, blink.size() * 4)) return e;
-  if (int e = dalloc(d->lq, qd.size() * rs)) return e;
-  if (moving)
-    if (int e = dalloc(d->lg, gd.size() * rs)) return e;
-  HIP_TRY(hipMemcpy(d->bmask, bmask.data(), bmask.size() * 4, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d->blink, blink.data(), blink.size() * 4, hipMemcpyHostToDevice));
-  auto upload_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
-    if (f64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
-    std::vector<float> f(v.begin(), v.end());
-    return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  std::vector<int32_t> lnode(n_links);
+  for (int64_t k = 0; k < n_links; ++k) lnode[k] = (int32_t)node[order[k]];
+  auto up = [&]() -> int {
+    if (int e = dalloc(d->lld, lld.size() * 2)) return e;
+    if (int e = dalloc(d->lnode, lnode.size() * 4)) return e;
+    if (int e = dalloc(d->lq, qd.size() * rs)) return e;
+    if (int e = dalloc(d->lv[0], qd.size() * rs)) return e;
+    if (int e = dalloc(d->lv[1], qd.size() * rs)) return e;
+    if (moving)
+      if (int e = dalloc(d->lg, gd.size() * rs)) return e;
+    HIP_TRY(hipMemcpy(d->lld, lld.data(), lld.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->lnode, lnode.data(), lnode.size() * 4, hipMemcpyHostToDevice));
+    auto upload_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
+      if (f64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+      std::vector<float> f(v.begin(), v.end());
+      return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+    };
+    HIP_TRY(upload_real(d->lq, qd));
+    if (moving) HIP_TRY(upload_real(d->lg, gd));
+    HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->seg_lbase, slb.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice));
+    d->nb = nb;
+    d->nl = n_links;
+    HIP_TRY(import_state(d, fstate));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return LBM_OK;
   };
-  HIP_TRY(upload_real(d->lq, qd));
-  if (moving) HIP_TRY(upload_real(d->lg, gd));
-  HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d->seg_bbase, sbase.data(), g.nseg * 4, hipMemcpyHostToDevice));
-  d->nb = (int64_t)bnode.size();
+  const int code = up();
+  (void)hipFree(fstate);
+  if (code != LBM_OK) return code;
   d->nl = n_links;
   d->variant = variant;
   d->q_cut = q_cutoff;
@@ -465,7 +513,7 @@ int lbm_macros(lbm_domain d, double* rho, double* u, double* sums) {
   MacroParams p{};
   p.g = d->g;
   p.src = d->buf[d->cur];
-  p.seg_fluid = d->seg_fluid;
+  p.lk = link_view(d, d->lv[d->cur], nullptr);
   for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
   p.rho = rho ? d->rho_tmp : nullptr;
   p.u = u ? d->u_tmp : nullptr;
@@ -496,12 +544,7 @@ int lbm_get_state(lbm_domain d, double* f) {
   double* tmp = nullptr;
   const size_t bytes = (size_t)d->N * d->Q * 8;
   if (int e = dalloc(tmp, bytes)) return e;
-  ExportParams p{};
-  p.g = d->g;
-  p.src = d->buf[d->cur];
-  p.seg_fluid = d->seg_fluid;
-  p.f_out = tmp;
-  hipError_t e = launch_export(d->desc.lattice, d->desc.storage, p, d->stream);
+  hipError_t e = export_state(d, tmp);
   if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, bytes, hipMemcpyDeviceToHost, d->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   (void)hipFree(tmp);
@@ -514,13 +557,8 @@ int lbm_set_state(lbm_domain d, const double* f) {
   double* tmp = nullptr;
   const size_t bytes = (size_t)d->N * d->Q * 8;
   if (int e = dalloc(tmp, bytes)) return e;
-  InitParams p{};
-  p.g = d->g;
-  p.dst = d->buf[d->cur];
-  p.seg_fluid = d->seg_fluid;
-  p.f_in = tmp;
   hipError_t e = hipMemcpyAsync(tmp, f, bytes, hipMemcpyHostToDevice, d->stream);
-  if (e == hipSuccess) e = launch_init(d->desc.lattice, d->desc.storage, p, d->stream);
+  if (e == hipSuccess) e = import_state(d, tmp);
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
@@ -542,7 +580,7 @@ int lbm_get_info(lbm_domain d, lbm_domain_info* info) {
   info->n_links = d->nl;
   info->population_bytes = (int64_t)(2 * d->g.npad * d->Q * d->elem);
   const int64_t rs = d->desc.storage == LBM_F64 ? 8 : 4;
-  info->link_bytes = d->nb * 8 + d->nl * rs * (d->lg ? 2 : 1) + d->g.nseg * 20;
+  info->link_bytes = d->nl * (2 + rs * (d->lg ? 2 : 1)) + d->g.nseg * 20;
   info->steps_done = d->steps;
   info->q = d->Q;
   info->storage = d->desc.storage;
@@ -559,7 +597,7 @@ int lbm_free_domain(lbm_domain d) {
   }
   dfree(d->seg_fluid);
   dfree(d->seg_bnd);
-  dfree(d->seg_bbase);
+  dfree(d->seg_lbase);
   free_links(d);
   dfree(d->partials);
   dfree(d->sums);

@@ -68,6 +68,53 @@ LBM_HD Coef<T> elibb_coefficients(int variant, T q, T q_cut) {
   return c;
 }
 
+// Branch-free form of elibb_coefficients for the kernels.  FP32 uses the
+// hardware reciprocal (1 ulp); FP64 divides exactly.
+template <typename T>
+__device__ __forceinline__ T fast_recip(T x) {
+  return T(1) / x;
+}
+#if defined(__HIP_DEVICE_COMPILE__)
+template <>
+__device__ __forceinline__ float fast_recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+#endif
+
+template <typename T>
+__device__ __forceinline__ Coef<T> elibb_coefficients_fast(int variant, T q, T q_cut) {
+  const T one = T(1), two = T(2), half = T(0.5);
+  const T tq1 = two * q - one;                 // 2q - 1
+  const T omq = one - q;                       // 1 - q
+  const T rq = fast_recip(q);
+  const T rom = fast_recip(omq > T(0) ? omq : one);
+  const bool lo = q < half;
+  // linear (ELIBB-F) weights
+  const T fa4 = lo ? -tq1 * rom : T(0);
+  const T fa2 = lo ? q * rom : omq * rq;
+  const T fa5 = lo ? T(0) : tq1 * rq;
+  // quadratic weights: UQ everywhere, FQ below 1/2
+  const T r2 = rq * rq;
+  const bool fq_hi = (variant == FQ) && !lo;
+  const T qa4 = fq_hi ? T(0) : -tq1;
+  const T qa2 = fq_hi ? omq * half * r2 : one;
+  const T qa5 = fq_hi ? tq1 * r2 : tq1;
+  const T qa3 = fq_hi ? -tq1 * omq * half * r2 : T(0);
+  Coef<T> c;
+  if (variant == HWBB) {
+    c = Coef<T>{T(0), T(0), one, T(0)};
+  } else if (variant == U) {
+    c = Coef<T>{omq, q, T(0), T(0)};
+  } else {
+    const bool linear = (variant == F) || (q < q_cut);
+    c.a4 = linear ? fa4 : qa4;
+    c.a5 = linear ? fa5 : qa5;
+    c.a2 = linear ? fa2 : qa2;
+    c.a3 = linear ? T(0) : qa3;
+  }
+  return c;
+}
+
 // Wall-velocity term of a link.  With P0 = w rho e0 + n_pre,
 // P1 = w rho e1 + n_post, P2 = f*_ibar + w rho m (eq. ELIBB-general, eq.
 // ME-solid-to-fluid), e0 = f^eq_i(1, u_w(t+1)) / w_i, e1 = f^eq_i(1, u_w(t)) / w_i

@@ -11,11 +11,23 @@
 //              ELIBB value f_i(x_F, t+1) written by the boundary node itself.
 // segments     one wave (64 lanes) handles 64 consecutive x of one row (y, z):
 //              seg_fluid / seg_bnd are 64-bit lane masks of fluid and boundary
-//              nodes, seg_bbase the index of the segment's first boundary node.
-// boundary     per boundary node b (sorted by node index): bmask[b] bit i set iff
-//              (node, i) is a cut link; blink[b] the index of its first link.
-// links        per link, ordered by (node, dir): q and, when any wall moves, the
-//              wall factor G (see elibb.hpp).
+//              nodes; the segment's cut links are links[seg_lbase[s] ..
+//              seg_lbase[s+1]) (nseg + 1 entries).
+// links        ordered by (node, dir), so each segment's links are contiguous:
+//              ld (uint16) = lane of the boundary node in its segment | dir << 8,
+//              q and, when any wall moves, the wall term Gw (see elibb.hpp),
+//              lnode the node index (used only outside the step).
+// link values  with a static link list the rebuilt populations live in two
+//              per-link arrays lv[2] (shifted, like the populations): step t
+//              reads f_i(x_F, t) of every cut link from lv_in while pulling
+//              and writes f_i(x_F, t+1) to lv_out, coalesced.  Without link
+//              value arrays (moving geometry) the rebuilt value is stored in the
+//              solid-side slot x_F - c_i that x_F pulls instead.
+//              A wave stages its boundary nodes' populations and moments in LDS,
+//              patches the cut directions, and rebuilds its links one per lane.
+// block order  workgroups are dealt to the 8 XCDs round-robin; the kernels
+//              remap the workgroup id so that each XCD walks a contiguous range
+//              of rows (neighbouring rows share its L2).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -31,27 +43,50 @@ constexpr int SEG = 64;          // lanes per segment (one wavefront)
 constexpr int WAVES_PER_BLOCK = 4;
 constexpr int BLOCK = SEG * WAVES_PER_BLOCK;
 
+// Division by a run-time constant d < 2^31 for dividends n < 2^31:
+// n / d = (umulhi(n, m) + n) >> s  (m, s chosen on the host).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0u, 0u};
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  f.s = l;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  return f;
+}
+
 struct GridGeom {
   int32_t nx, ny, nz;            // domain size
   int32_t NX, NY, NZ;            // padded storage size
   int32_t px, py, pz;            // halo widths (0 or 1)
   int32_t perx, pery, perz;      // periodic flags
   int32_t nseg_x;                // segments per row
-  int64_t nseg;                  // total segments
+  int64_t nseg;                  // total segments (< 2^31)
+  FastDiv div_nseg_x, div_ny;    // fast division by nseg_x and ny
+  int32_t xcd_remap;             // 1: each XCD walks a contiguous eighth of the rows
   int64_t npad;                  // NX * NY * NZ (stride between direction arrays)
+};
+
+struct LinkView {
+  const uint64_t* seg_fluid;
+  const uint64_t* seg_bnd;
+  const int32_t* seg_lbase;      // [nseg + 1]
+  const uint16_t* lld;           // link lane | dir << 8
+  const int32_t* lnode;          // link node index
+  const void* lq;                // link q (double for FP64 storage, float otherwise)
+  const void* lg;                // link wall term Gw, or null when every wall rests
+  const void* lv_in;             // link values at t (null: slot mode)
+  void* lv_out;                  // link values at t+1
 };
 
 struct StepParams {
   GridGeom g;
   const void* src;
   void* dst;
-  const uint64_t* seg_fluid;
-  const uint64_t* seg_bnd;
-  const int32_t* seg_bbase;
-  const uint32_t* bmask;
-  const int32_t* blink;
-  const void* lq;                // link q (double for FP64 storage, float otherwise)
-  const void* lg;                // link wall factor G, or null when every wall rests
+  LinkView lk;
   double omega;
   double force[3];
   int32_t has_force;
@@ -63,7 +98,8 @@ struct StepParams {
 struct InitParams {
   GridGeom g;
   void* dst;
-  const uint64_t* seg_fluid;
+  LinkView lk;                   // lv_out receives the cut-link values (list mode)
+  int64_t nlinks;
   const double* f_in;            // [Q][N] or null for the equilibrium (rho0, u0)
   double rho0, u0[3];
 };
@@ -71,14 +107,14 @@ struct InitParams {
 struct ExportParams {
   GridGeom g;
   const void* src;
-  const uint64_t* seg_fluid;
+  LinkView lk;                   // lv_in holds the cut-link values (list mode)
   double* f_out;                 // [Q][N]
 };
 
 struct MacroParams {
   GridGeom g;
   const void* src;
-  const uint64_t* seg_fluid;
+  LinkView lk;
   double force[3];
   double* rho;                   // [N] or null
   double* u;                     // [N*D] or null
@@ -87,9 +123,13 @@ struct MacroParams {
 };
 constexpr int NPART = 8;         // mass, mom x/y/z, |du|^2, |u|^2, non-finite count, pad
 
+// Number of workgroups of the lattice kernels (a multiple of the 8 XCDs).
+int64_t grid_blocks(const GridGeom& g);
+
 // Launchers (kernels.hip); dispatch on lattice and storage.
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s);
 hipError_t launch_init(int lattice, int storage, const InitParams& p, hipStream_t s);
+hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipStream_t s);
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s);
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
@@ -111,13 +151,14 @@ struct lbm_domain_s {
   // segments
   uint64_t* seg_fluid;
   uint64_t* seg_bnd;
-  int32_t* seg_bbase;
+  int32_t* seg_lbase;
   // boundary nodes and links
   int64_t nb, nl;
-  uint32_t* bmask;
-  int32_t* blink;
+  uint16_t* lld;
+  int32_t* lnode;
   void* lq;
   void* lg;
+  void* lv[2];                   // link values (list mode), lv[cur] is current
   bool links_ok;
   int32_t variant;
   double q_cut;

@@ -70,13 +70,20 @@ typedef struct {
                             on a non-periodic axis                                     */
   void* stream;          /* hipStream_t for all device work; NULL = default stream     */
   void* arena;           /* optional caller-owned device memory for the two population
-                            buffers (>= lbm_arena_bytes(desc) bytes, 256-byte aligned);
-                            NULL = the library allocates them                          */
+                            buffers (>= lbm_arena_bytes(desc, mask) bytes, 256-byte
+                            aligned); NULL = the library allocates them               */
   size_t arena_bytes;
+  int32_t layout;        /* LBM_LAYOUT_COMPACT (default): only fluid nodes are stored;
+                            LBM_LAYOUT_DENSE: every node (plus a halo layer on
+                            non-periodic axes)                                          */
 } lbm_domain_desc;
 
-/* Bytes of the two population buffers of a domain (what an arena must hold). */
-size_t lbm_arena_bytes(const lbm_domain_desc* d);
+enum { LBM_LAYOUT_COMPACT = 0, LBM_LAYOUT_DENSE = 1 };
+
+/* Bytes of the two population buffers of a domain (what an arena must hold).
+ * fluid_mask (host, N bytes) is needed for the compact layout; NULL gives the
+ * dense-layout size, an upper bound. */
+size_t lbm_arena_bytes(const lbm_domain_desc* d, const uint8_t* fluid_mask);
 
 /* Create a domain (Sec. II.A lattice, eq. LBE).  fluid_mask: host, N bytes, 1 =
  * fluid node, 0 = solid.  All fluid nodes start at f^eq(rho0, u0) (eq.
@@ -121,12 +128,21 @@ int lbm_macros(lbm_domain d, double* rho, double* u, double* sums);
 
 /* Export / import the pre-collision populations f_i(x, t) as [Q][N] float64
  * (solid nodes read as 0 and are ignored on import).  For 16-bit storage the
- * import rounds to the storage format.  Both synchronise the stream. */
+ * import rounds to the storage format.  At a zero-gradient outlet an inward
+ * population equals, by construction, the same population one node upstream;
+ * on import that upstream value is kept.  Both synchronise the stream. */
 int lbm_get_state(lbm_domain d, double* f);
 int lbm_set_state(lbm_domain d, const double* f);
 
 /* Change the stream used by later calls. */
 int lbm_set_stream(lbm_domain d, void* stream);
+
+/* Launch options (no effect on results): LBM_OPT_XCD_REMAP = 1 deals the
+ * workgroups so that each of the 8 XCDs walks a contiguous range of rows
+ * (neighbouring rows then share an L2); 0 keeps the hardware round-robin.
+ * Default: 1 for the compact layout, 0 for the dense one. */
+enum { LBM_OPT_XCD_REMAP = 0 };
+int lbm_set_launch_option(lbm_domain d, int32_t option, int32_t value);
 
 typedef struct {
   int64_t n_nodes, n_fluid, n_boundary_nodes, n_links;

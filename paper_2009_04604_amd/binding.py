@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
+LAYOUTS = {"compact": 0, "dense": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
 FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
@@ -27,7 +28,7 @@ D_OF = {"D2Q9": 2, "D3Q19": 3}
 
 EXPORTED = [
     "lbm_arena_bytes", "lbm_init_domain", "lbm_set_boundary_links", "lbm_step", "lbm_macros",
-    "lbm_get_state", "lbm_set_state", "lbm_set_stream", "lbm_get_info", "lbm_free_domain",
+    "lbm_get_state", "lbm_set_state", "lbm_set_stream", "lbm_set_launch_option", "lbm_get_info", "lbm_free_domain",
     "lbm_last_error", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
 ]
@@ -45,7 +46,7 @@ class DomainDesc(ctypes.Structure):
         ("periodic", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
         ("force", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 3),
         ("outlet_face", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
-        ("arena_bytes", ctypes.c_size_t),
+        ("arena_bytes", ctypes.c_size_t), ("layout", ctypes.c_int32),
     ]
 
 
@@ -71,7 +72,8 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_04604_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     sig = {
-        "lbm_arena_bytes": (ctypes.c_size_t, [P]),
+        "lbm_arena_bytes": (ctypes.c_size_t, [P, P]),
+        "lbm_set_launch_option": (I32, [P, I32, I32]),
         "lbm_init_domain": (I32, [P, P, P]),
         "lbm_set_boundary_links": (I32, [P, I64, P, P, P, P, P, I32, DBL]),
         "lbm_step": (I32, [P, I32]),
@@ -119,7 +121,7 @@ def _torch_stream():
 
 
 def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, True), force=(0, 0, 0),
-              rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, arena=None, arena_bytes=0):
+              rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, arena=None, arena_bytes=0, layout="compact"):
     d = DomainDesc()
     d.lattice = LATTICES[lattice]
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
@@ -134,12 +136,18 @@ def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, Tru
     d.stream = stream
     d.arena = arena
     d.arena_bytes = int(arena_bytes)
+    d.layout = LAYOUTS[layout]
     return d
 
 
 # ---- C names ------------------------------------------------------------------
-def lbm_arena_bytes(desc):
-    return lib().lbm_arena_bytes(ctypes.byref(desc))
+def lbm_arena_bytes(desc, fluid_mask=None):
+    m = None if fluid_mask is None else np.ascontiguousarray(np.asarray(fluid_mask).reshape(-1), dtype=np.uint8)
+    return lib().lbm_arena_bytes(ctypes.byref(desc), _ptr(m))
+
+
+def lbm_set_launch_option(h, option, value):
+    _check(lib().lbm_set_launch_option(h, int(option), int(value)))
 
 
 def lbm_init_domain(desc, fluid_mask):
@@ -212,18 +220,20 @@ class Domain:
     """
 
     def __init__(self, lattice, nx, ny, nz, fluid_mask, tau, storage="f32", periodic=(True, True, True),
-                 force=(0, 0, 0), rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, torch_arena=True):
+                 force=(0, 0, 0), rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, torch_arena=True,
+                 layout="compact"):
         self.lattice, self.storage = lattice, storage
         self.n = (int(nx), int(ny), int(nz))
         self.N = int(nx) * int(ny) * int(nz)
         self.Q, self.D = Q_OF[lattice], D_OF[lattice]
         if stream is None:
             stream = _torch_stream()
-        desc = make_desc(lattice, nx, ny, nz, tau, storage, periodic, force, rho0, u0, outlet_face, stream)
+        desc = make_desc(lattice, nx, ny, nz, tau, storage, periodic, force, rho0, u0, outlet_face, stream,
+                         layout=layout)
         self._arena = None
         if torch_arena:
             import torch
-            nbytes = lbm_arena_bytes(desc)
+            nbytes = lbm_arena_bytes(desc, fluid_mask)
             self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
             base = self._arena.data_ptr()
             desc.arena = (base + 255) // 256 * 256
@@ -252,6 +262,9 @@ class Domain:
 
     def set_stream(self, stream):
         _check(lib().lbm_set_stream(self.h, stream))
+
+    def set_launch_option(self, option, value):
+        lbm_set_launch_option(self.h, option, value)
 
     def info(self):
         return lbm_get_info(self.h)

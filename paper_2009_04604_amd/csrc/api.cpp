@@ -120,6 +120,7 @@ int64_t outlet_producer(const lbm_domain_s* d, const int s[3]) {
 LinkView link_view(const lbm_domain_s* d, const void* lv_in, void* lv_out) {
   LinkView lk{};
   lk.seg_fluid = d->seg_fluid;
+  lk.seg_fbase = d->seg_fbase;
   lk.seg_bnd = d->seg_bnd;
   lk.seg_lbase = d->seg_lbase;
   lk.lld = d->lld;
@@ -211,13 +212,25 @@ extern "C" {
 
 const char* lbm_last_error(void) { return lbm::g_err.c_str(); }
 
-size_t lbm_arena_bytes(const lbm_domain_desc* d) {
-  if (!d || (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)) return 0;
-  const int Q = d->lattice == LBM_D2Q9 ? 9 : 19;
+namespace {
+// Elements per direction array: compact = fluid nodes + 2 guards, rounded up to
+// 64 elements; dense = the padded lattice.
+int64_t population_stride(const lbm_domain_desc* d, const uint8_t* mask) {
   const int64_t NX = d->nx + ((d->periodic & 1) ? 0 : 2);
   const int64_t NY = d->ny + ((d->periodic & 2) ? 0 : 2);
   const int64_t NZ = d->lattice == LBM_D2Q9 ? 1 : d->nz + ((d->periodic & 4) ? 0 : 2);
-  const size_t one = (size_t)(NX * NY * NZ) * Q * storage_bytes(d->storage);
+  if (d->layout == LBM_LAYOUT_DENSE || !mask) return NX * NY * NZ;
+  const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+  int64_t nf = 0;
+  for (int64_t n = 0; n < N; ++n) nf += mask[n] ? 1 : 0;
+  return (nf + 2 + 63) / 64 * 64;
+}
+}  // namespace
+
+size_t lbm_arena_bytes(const lbm_domain_desc* d, const uint8_t* fluid_mask) {
+  if (!d || (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)) return 0;
+  const int Q = d->lattice == LBM_D2Q9 ? 9 : 19;
+  const size_t one = (size_t)population_stride(d, fluid_mask) * Q * storage_bytes(d->storage);
   const size_t aligned = (one + 255) / 256 * 256;
   return 2 * aligned;
 }
@@ -239,7 +252,8 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (d.outlet_face < -1 || d.outlet_face > 5) return fail(LBM_EINVAL, "outlet_face out of range");
   if (d.outlet_face >= 0 && ((per >> (d.outlet_face >> 1)) & 1)) return fail(LBM_EINVAL, "outlet face lies on a periodic axis");
   const int64_t N = (int64_t)d.nx * d.ny * d.nz;
-  const size_t need = lbm_arena_bytes(desc);
+  if (d.layout != LBM_LAYOUT_COMPACT && d.layout != LBM_LAYOUT_DENSE) return fail(LBM_EINVAL, "invalid layout");
+  const size_t need = lbm_arena_bytes(desc, fluid_mask);
   if (d.arena && d.arena_bytes < need) return fail(LBM_EINVAL, "arena too small: need " + std::to_string(need) + " bytes");
   if (d.arena && ((uintptr_t)d.arena & 255)) return fail(LBM_EINVAL, "arena must be 256-byte aligned");
 
@@ -270,10 +284,13 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   g.div_nseg_x = make_fastdiv((uint32_t)g.nseg_x);
   g.div_ny = make_fastdiv((uint32_t)g.ny);
   g.xcd_remap = 0;
-  g.npad = (int64_t)g.NX * g.NY * g.NZ;
-  if (g.npad >= ((int64_t)1 << 31)) {
+  g.compact = d.layout == LBM_LAYOUT_COMPACT;
+  g.outlet = d.outlet_face;
+  g.xcd_remap = g.compact ? 1 : 0;
+  g.npad = population_stride(desc, fluid_mask);
+  if (g.npad >= ((int64_t)1 << 31) || g.nseg >= ((int64_t)1 << 31) / WAVES_PER_BLOCK) {
     delete dm;
-    return fail(LBM_EINVAL, "lattice too large: more than 2^31 padded nodes");
+    return fail(LBM_EINVAL, "lattice too large: more than 2^31 stored nodes");
   }
   dm->N = N;
   dm->elem = storage_bytes(d.storage);
@@ -309,10 +326,14 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
       for (int x = 0; x < g.nx; ++x)
         if (dm->mask[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)])
           sf[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] |= 1ull << (x % SEG);
+  std::vector<int32_t> sfb(g.nseg + 1, 0);
+  for (int64_t s = 0; s < g.nseg; ++s) sfb[s + 1] = sfb[s] + __builtin_popcountll(sf[s]);
+  if (int e = dalloc(dm->seg_fbase, (g.nseg + 1) * 4)) return cleanup(e);
   if (int e = dalloc(dm->seg_fluid, g.nseg * 8)) return cleanup(e);
   if (int e = dalloc(dm->seg_bnd, g.nseg * 8)) return cleanup(e);
   if (int e = dalloc(dm->seg_lbase, (g.nseg + 1) * 4)) return cleanup(e);
-  he = hipMemcpyAsync(dm->seg_fluid, sf.data(), g.nseg * 8, hipMemcpyHostToDevice, dm->stream);
+  he = hipMemcpy(dm->seg_fluid, sf.data(), g.nseg * 8, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(dm->seg_fbase, sfb.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bnd, 0, g.nseg * 8, dm->stream);
   if (he == hipSuccess) he = hipMemsetAsync(dm->seg_lbase, 0, (g.nseg + 1) * 4, dm->stream);
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
@@ -572,6 +593,13 @@ int lbm_set_stream(lbm_domain d, void* stream) {
   return LBM_OK;
 }
 
+int lbm_set_launch_option(lbm_domain d, int32_t option, int32_t value) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (option != LBM_OPT_XCD_REMAP || (value != 0 && value != 1)) return fail(LBM_EINVAL, "invalid launch option");
+  d->g.xcd_remap = value;
+  return LBM_OK;
+}
+
 int lbm_get_info(lbm_domain d, lbm_domain_info* info) {
   if (!d || !info) return fail(LBM_EINVAL, "null argument");
   info->n_nodes = d->N;
@@ -598,6 +626,7 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->seg_fluid);
   dfree(d->seg_bnd);
   dfree(d->seg_lbase);
+  dfree(d->seg_fbase);
   free_links(d);
   dfree(d->partials);
   dfree(d->sums);

@@ -2,13 +2,21 @@
 //
 // Device data layout of one domain
 // --------------------------------
-// populations  two buffers, structure of arrays [Q][NZ][NY][NX] of the storage
-//              type.  NX = nx + 2 px etc.: one halo layer (px = 1) on each
-//              non-periodic axis, none on periodic ones.  Pull scheme: the value
-//              that node x pulls in direction i lives in slot (x - c_i, i).
-//              After a step, slot (x, i) of a fluid node x holds its post-
-//              collision f*_i, and slot (x_F - c_i, i) of a cut link holds the
-//              ELIBB value f_i(x_F, t+1) written by the boundary node itself.
+// populations  two buffers, structure of arrays: Q direction arrays of
+//              `stride` elements each, holding the shifted populations
+//              h_i = f_i - w_i in the storage type.  Pull scheme: the value that
+//              node x pulls in direction i lives in slot (x - c_i, i); after a
+//              step slot (x, i) of a fluid node holds its post-collision h*_i.
+//   compact    (static geometry) only fluid nodes are stored, in node order:
+//              the slot of fluid node x is 1 + (number of fluid nodes before
+//              x), found from the segment masks and their prefix counts
+//              seg_fbase; element 0 and the tail are guards.  Solid nodes cost
+//              neither memory nor bandwidth.
+//   dense      (moving geometry) [NZ][NY][NX] with NX = nx + 2 px etc.: one
+//              halo layer on each non-periodic axis.
+// outlet       a zero-gradient outlet face is a clamp of the pull source onto
+//              the face layer: the outlet population reads the same slot as
+//              its upstream neighbour (read-only sharing).
 // segments     one wave (64 lanes) handles 64 consecutive x of one row (y, z):
 //              seg_fluid / seg_bnd are 64-bit lane masks of fluid and boundary
 //              nodes; the segment's cut links are links[seg_lbase[s] ..
@@ -67,11 +75,14 @@ struct GridGeom {
   int64_t nseg;                  // total segments (< 2^31)
   FastDiv div_nseg_x, div_ny;    // fast division by nseg_x and ny
   int32_t xcd_remap;             // 1: each XCD walks a contiguous eighth of the rows
-  int64_t npad;                  // NX * NY * NZ (stride between direction arrays)
+  int32_t compact;               // 1: compact (fluid-only) layout
+  int32_t outlet;                // outlet face or -1
+  int64_t npad;                  // elements between direction arrays (stride)
 };
 
 struct LinkView {
   const uint64_t* seg_fluid;
+  const int32_t* seg_fbase;      // [nseg + 1] fluid nodes before each segment
   const uint64_t* seg_bnd;
   const int32_t* seg_lbase;      // [nseg + 1]
   const uint16_t* lld;           // link lane | dir << 8
@@ -152,6 +163,7 @@ struct lbm_domain_s {
   uint64_t* seg_fluid;
   uint64_t* seg_bnd;
   int32_t* seg_lbase;
+  int32_t* seg_fbase;
   // boundary nodes and links
   int64_t nb, nl;
   uint16_t* lld;

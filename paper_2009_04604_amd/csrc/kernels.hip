@@ -25,9 +25,10 @@ struct Coords {
 // round-robin to the 8 XCDs; the logical block id makes XCD k walk the k-th
 // contiguous eighth of the rows (the grid is padded to a multiple of 8).
 struct SegInfo {
-  uint32_t seg;
+  uint32_t seg;      // wave-uniform
+  uint32_t sx;       // wave-uniform segment index within the row
   int lane;
-  Coords c;
+  Coords c;          // c.y, c.z wave-uniform
 };
 
 __device__ __forceinline__ uint32_t fast_div(uint32_t n, const FastDiv& f) {
@@ -46,11 +47,12 @@ __device__ __forceinline__ SegInfo seg_info(const GridGeom& g) {
   s.lane = threadIdx.x & (SEG - 1);
   const uint32_t wave = logical_block(g.xcd_remap) * WAVES_PER_BLOCK + __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
   s.seg = wave;
-  const uint32_t row = fast_div(wave, g.div_nseg_x);
-  const uint32_t sx = wave - row * (uint32_t)g.nseg_x;
-  const uint32_t z = fast_div(row, g.div_ny);
+  const uint32_t row = __builtin_amdgcn_readfirstlane(fast_div(wave, g.div_nseg_x));
+  const uint32_t sx = __builtin_amdgcn_readfirstlane(wave - row * (uint32_t)g.nseg_x);
+  const uint32_t z = __builtin_amdgcn_readfirstlane(fast_div(row, g.div_ny));
+  s.sx = sx;
   s.c.x = (int)sx * SEG + s.lane;
-  s.c.y = (int)(row - z * (uint32_t)g.ny);
+  s.c.y = (int)__builtin_amdgcn_readfirstlane(row - z * (uint32_t)g.ny);
   s.c.z = (int)z;
   return s;
 }
@@ -144,48 +146,124 @@ __device__ __forceinline__ Moments<R> moments(const R (&h)[L::Q], R Fx, R Fy, R 
   return m;
 }
 
-// Element offsets (within one direction array) of a node and of its pull
-// sources: source of direction i = xs[1 + cx] + ys[1 + cy] + zs[1 + cz], with
-// wrap on periodic axes and the halo layer beyond non-periodic faces.
-struct PullIndex {
+// Source coordinate of a pull along one axis: coord - c, wrapped on a periodic
+// axis, clamped onto the face layer at an outlet face, and otherwise left one
+// step outside (the dense layout's halo; the compact layout never reads it:
+// such pulls are cut links, patched from their link values).
+__device__ __forceinline__ int axis_src(int coord, int c, int n, int periodic, int out_lo, int out_hi) {
+  int v = coord - c;
+  if (periodic) return v < 0 ? v + n : (v >= n ? v - n : v);
+  if (v < 0 && out_lo) return 0;
+  if (v >= n && out_hi) return n - 1;
+  return v;
+}
+
+// Dense layout: element offsets of the pull sources, xs[1 + cx] + ys[1 + cy] + zs[1 + cz].
+struct DenseIndex {
   uint32_t xs[3], ys[3], zs[3];
   uint32_t self;
+  template <class L>
+  __device__ __forceinline__ uint32_t src(int i) const {
+    return xs[1 + L::cx(i)] + ys[1 + L::cy(i)] + zs[1 + L::cz(i)];
+  }
 };
 
-__device__ __forceinline__ PullIndex pull_index(const GridGeom& g, Coords c) {
+__device__ __forceinline__ DenseIndex dense_index(const GridGeom& g, Coords c) {
   const uint32_t NX = (uint32_t)g.NX, NXY = (uint32_t)g.NX * (uint32_t)g.NY;
-  const int xm = (g.perx && c.x == 0) ? g.nx - 1 : c.x - 1;
-  const int xp = (g.perx && c.x == g.nx - 1) ? 0 : c.x + 1;
-  const int ym = (g.pery && c.y == 0) ? g.ny - 1 : c.y - 1;
-  const int yp = (g.pery && c.y == g.ny - 1) ? 0 : c.y + 1;
-  const int zm = (g.perz && c.z == 0) ? g.nz - 1 : c.z - 1;
-  const int zp = (g.perz && c.z == g.nz - 1) ? 0 : c.z + 1;
-  PullIndex p;
-  // indexed by 1 + c: the source of direction c is x - c
-  p.xs[0] = (uint32_t)(xp + g.px);
-  p.xs[1] = (uint32_t)(c.x + g.px);
-  p.xs[2] = (uint32_t)(xm + g.px);
-  p.ys[0] = (uint32_t)(yp + g.py) * NX;
-  p.ys[1] = (uint32_t)(c.y + g.py) * NX;
-  p.ys[2] = (uint32_t)(ym + g.py) * NX;
-  p.zs[0] = (uint32_t)(zp + g.pz) * NXY;
-  p.zs[1] = (uint32_t)(c.z + g.pz) * NXY;
-  p.zs[2] = (uint32_t)(zm + g.pz) * NXY;
+  const int o = g.outlet;
+  DenseIndex p;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {   // k = 1 + c, the source of direction c is x - c
+    p.xs[k] = (uint32_t)(axis_src(c.x, k - 1, g.nx, g.perx, o == 0, o == 1) + g.px);
+    p.ys[k] = (uint32_t)(axis_src(c.y, k - 1, g.ny, g.pery, o == 2, o == 3) + g.py) * NX;
+    p.zs[k] = (uint32_t)(axis_src(c.z, k - 1, g.nz, g.perz, o == 4, o == 5) + g.pz) * NXY;
+  }
   p.self = p.xs[1] + p.ys[1] + p.zs[1];
   return p;
 }
 
+// Compact layout: slot of fluid node (x, row r) = 1 + fbase[seg] + popc(mask below x).
+// For each source row (y - cy, z - cz) the lane keeps P = slot the node x would
+// have in that row and B = whether (x, row) is fluid; then the source slot of
+// direction i is P (cx = 0), P - 1 (cx = +1, node x - 1) or P + B (cx = -1,
+// node x + 1), with the periodic wrap of the row ends handled by lo / hi.
 template <class L>
-__device__ __forceinline__ uint32_t src_of(const PullIndex& p, int i) {
-  return p.xs[1 + L::cx(i)] + p.ys[1 + L::cy(i)] + p.zs[1 + L::cz(i)];
+struct CompactIndex {
+  uint32_t P[3][3], B[3][3], lo[3][3], hi[3][3];
+  bool xlo, xhi;
+  uint32_t self;
+  template <class LL>
+  __device__ __forceinline__ uint32_t src(int i) const {
+    const int a = 1 + LL::cy(i), b = 1 + LL::cz(i);
+    if (LL::cx(i) == 0) return P[a][b];
+    if (LL::cx(i) == 1) return xlo ? lo[a][b] : P[a][b] - 1u;
+    return xhi ? hi[a][b] : P[a][b] + B[a][b];
+  }
+};
+
+template <class L>
+__device__ __forceinline__ CompactIndex<L> compact_index(const GridGeom& g, const LinkView& lk, const SegInfo& si) {
+  CompactIndex<L> p;
+  const uint32_t sx = si.sx;
+  // only the first and the last segment of a row hold the x-edge lanes; their
+  // pulls wrap (periodic x) or clamp onto the node itself (outlet, walls)
+  const bool edge = sx == 0 || sx == (uint32_t)g.nseg_x - 1;
+  const bool wrap = edge && g.perx;
+  const int o = g.outlet;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (L::D == 2 && b != 1) continue;
+      const int ys = axis_src(si.c.y, a - 1, g.ny, g.pery, o == 2, o == 3);
+      const int zs = axis_src(si.c.z, b - 1, g.nz, g.perz, o == 4, o == 5);
+      // rows beyond a wall face are never used (cut links): any in-range row will do
+      const uint32_t yy = (uint32_t)min(max(ys, 0), g.ny - 1), zz = (uint32_t)min(max(zs, 0), g.nz - 1);
+      const uint32_t row = yy + (uint32_t)g.ny * zz;
+      const uint32_t s0 = row * (uint32_t)g.nseg_x;
+      const uint64_t fm = lk.seg_fluid[s0 + sx];
+      const uint32_t fb = (uint32_t)lk.seg_fbase[s0 + sx] + 1u;
+      // number of fluid nodes of this segment below the lane (one mbcnt pair)
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
+      p.P[a][b] = fb + below;
+      p.B[a][b] = (uint32_t)((fm >> si.lane) & 1ull);
+      if (wrap) {
+        p.lo[a][b] = (uint32_t)lk.seg_fbase[s0 + (uint32_t)g.nseg_x];   // last fluid node of the row
+        p.hi[a][b] = (uint32_t)lk.seg_fbase[s0] + 1u;                     // first fluid node of the row
+      } else {
+        p.lo[a][b] = p.P[a][b];
+        p.hi[a][b] = p.P[a][b];
+      }
+    }
+  }
+  p.xlo = edge && si.c.x == 0;
+  p.xhi = edge && si.c.x == g.nx - 1;
+  p.self = p.P[1][1];
+  return p;
 }
 
-// Storage index of x - c for run-time c (element offset within one direction array).
+template <class L, bool COMPACT>
+struct IndexOf {
+  using type = DenseIndex;
+};
+template <class L>
+struct IndexOf<L, true> {
+  using type = CompactIndex<L>;
+};
+
+template <class L, bool COMPACT>
+__device__ __forceinline__ typename IndexOf<L, COMPACT>::type make_index(const GridGeom& g, const LinkView& lk,
+                                                                         const SegInfo& si) {
+  if constexpr (COMPACT) return compact_index<L>(g, lk, si);
+  else return dense_index(g, si.c);
+}
+
+// Dense-layout storage index of x - c for run-time c (slot mode only).
 __device__ __forceinline__ uint32_t src_index_dyn(const GridGeom& g, Coords c, int cx, int cy, int cz) {
-  int sx = c.x - cx, sy = c.y - cy, sz = c.z - cz;
-  sx = (g.perx && sx < 0) ? sx + g.nx : ((g.perx && sx >= g.nx) ? sx - g.nx : sx);
-  sy = (g.pery && sy < 0) ? sy + g.ny : ((g.pery && sy >= g.ny) ? sy - g.ny : sy);
-  sz = (g.perz && sz < 0) ? sz + g.nz : ((g.perz && sz >= g.nz) ? sz - g.nz : sz);
+  const int o = g.outlet;
+  const int sx = axis_src(c.x, cx, g.nx, g.perx, o == 0, o == 1);
+  const int sy = axis_src(c.y, cy, g.ny, g.pery, o == 2, o == 3);
+  const int sz = axis_src(c.z, cz, g.nz, g.perz, o == 4, o == 5);
   return (uint32_t)(sx + g.px) + (uint32_t)g.NX * ((uint32_t)(sy + g.py) + (uint32_t)g.NY * (uint32_t)(sz + g.pz));
 }
 
@@ -235,9 +313,10 @@ __device__ __forceinline__ void patch_links(R (&h)[L::Q], R (*stage)[BLOCK], boo
 //  3. the wave rebuilds its cut links one per lane (eq. ELIBB-general with the
 //     closed-form weights) from the staged data of its boundary nodes and
 //     writes them to lv_out (list mode) or to the solid-side slot (slot mode);
-//  4. zero-gradient outlet copy on the outlet face layer.
+// The zero-gradient outlet needs no work of its own: its pulls are clamped onto
+// the face layer (see axis_src).
 // ---------------------------------------------------------------------------
-template <class L, int S>
+template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
   using St = Storage<S>;
   using T = typename St::T;
@@ -290,28 +369,29 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
     }
   }
 
-  const PullIndex pi = pull_index(g, c);
+  const auto ix = make_index<L, COMPACT>(g, lk, si);
   R h[L::Q];
   if (fluid) {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * np + src_of<L>(pi, i), i);
+    for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * np + ix.template src<L>(i), i);
   }
   const bool bnd = fluid && ((lk.seg_bnd[si.seg] >> si.lane) & 1ull);
   if (has_links && list_mode) patch_links<L, R, 2>(h, stage, bnd, tid, wbase, lb0, lb1, si.lane, lk.lld, lvi, ldp, vp);
 
   Moments<R> m;
   if (!fluid) {
-    // solid lane of a non-empty segment: zero populations, so that the shared
-    // cache lines are written whole (list mode; nothing reads these slots)
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) h[i] = R(0);
   }
   m = moments<L, R>(h, col.Fx, col.Fy, col.Fz);
-  if (fluid || (list_mode && inrow)) {
+  // dense layout, list mode: solid lanes of a non-empty segment store zeros so
+  // that the shared cache lines are written whole (nothing reads those slots);
+  // the compact layout has no solid slots
+  if (fluid || (!COMPACT && list_mode && inrow)) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], m);
-      St::template store<L>(dst + i * np + pi.self, fluid ? v : R(0), i);
+      St::template store<L>(dst + i * np + ix.self, fluid ? v : R(0), i);
     }
   }
   if (fluid) {
@@ -372,33 +452,11 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
     for (int k = lb0 + si.lane + 2 * SEG; k < lb1; k += SEG) rebuild(k, lk.lld[k], lq[k], lg ? lg[k] : R(0));
   }
 
-  // zero-gradient outlet: the face-layer node writes its post-collision values of
-  // the inward directions into the halo slot beyond the face, which its
-  // neighbour along the face pulls.
-  if (fluid && p.outlet_face >= 0) {
-    const int f = p.outlet_face, a = f >> 1;
-    const int sgn = (f & 1) ? 1 : -1;
-    const int coord = a == 0 ? c.x : (a == 1 ? c.y : c.z);
-    const int n_a = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-    if (coord == (sgn > 0 ? n_a - 1 : 0)) {
-      Coords halo = c;
-      if (a == 0) halo.x += sgn;
-      else if (a == 1) halo.y += sgn;
-      else halo.z += sgn;
-      const uint32_t hidx = src_index_dyn(g, halo, 0, 0, 0);
-#pragma unroll
-      for (int i = 1; i < L::Q; ++i) {
-        const int ca = a == 0 ? L::cx(i) : (a == 1 ? L::cy(i) : L::cz(i));
-        if (ca == -sgn)
-          St::template store<L>(dst + i * np + hidx, col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], m), i);
-      }
-    }
-  }
 }
 
 // Pre-collision shifted populations of one lane's node (pull + link patch).
 // Every lane of the wave must call it (the patch is a wave-level exchange).
-template <class L, int S>
+template <class L, int S, bool COMPACT>
 __device__ __forceinline__ void gather_state(const GridGeom& g, const LinkView& lk, const void* srcv, const SegInfo& si,
                                              bool fluid, typename Storage<S>::R (&h)[L::Q],
                                              typename Storage<S>::R (*stage)[BLOCK]) {
@@ -406,12 +464,12 @@ __device__ __forceinline__ void gather_state(const GridGeom& g, const LinkView& 
   using T = typename St::T;
   using R = typename St::R;
   const T* src = static_cast<const T*>(srcv);
-  const PullIndex pi = pull_index(g, si.c);
+  const auto ix = make_index<L, COMPACT>(g, lk, si);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) h[i] = R(0);
   if (fluid) {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * (size_t)g.npad + src_of<L>(pi, i), i);
+    for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * (size_t)g.npad + ix.template src<L>(i), i);
   }
   if (lk.lv_in) {
     const int lb0 = lk.seg_lbase[si.seg], lb1 = lk.seg_lbase[si.seg + 1];
@@ -438,23 +496,60 @@ __device__ __forceinline__ double init_value(const InitParams& p, int64_t n, int
   return L::w(i) * ((p.rho0 - 1.0) + p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
 }
 
-template <class L, int S>
+template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void init_kernel(InitParams p) {
   using St = Storage<S>;
   using T = typename St::T;
   using R = typename St::R;
   const GridGeom& g = p.g;
+  const LinkView& lk = p.lk;
   const SegInfo si = seg_info(g);
   if (si.seg >= g.nseg) return;
-  const uint64_t fm = p.lk.seg_fluid[si.seg];
+  const uint64_t fm = lk.seg_fluid[si.seg];
+  // directions of this lane that are cut links (list mode): their slot is not
+  // the node's to write (the value lives in the link arrays)
+  uint32_t cut = 0u;
+  if (lk.lv_out) {
+    const int lb0 = lk.seg_lbase[si.seg], lb1 = lk.seg_lbase[si.seg + 1];
+    for (int k = lb0; k < lb1; ++k) {
+      const int ld = lk.lld[k];
+      if ((ld & (SEG - 1)) == si.lane) cut |= 1u << (ld >> 8);
+    }
+  }
+  const auto ix = make_index<L, COMPACT>(g, lk, si);
   if (!((fm >> si.lane) & 1ull)) return;
   const Coords c = si.c;
   T* dst = static_cast<T*>(p.dst);
   const int64_t n = c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * c.z);
-  const PullIndex pi = pull_index(g, c);
+  // outlet layer: an inward population shares its (clamped) source slot with the
+  // upstream neighbour one layer in; that neighbour writes it if it is fluid
+  bool skip_out = false;
+  int oa = -1, osg = 0;
+  if (g.outlet >= 0) {
+    oa = g.outlet >> 1;
+    osg = (g.outlet & 1) ? 1 : -1;
+    const int coord = oa == 0 ? c.x : (oa == 1 ? c.y : c.z);
+    const int na = oa == 0 ? g.nx : (oa == 1 ? g.ny : g.nz);
+    if (coord == (osg > 0 ? na - 1 : 0) && na > 1) {
+      Coords q = c;
+      if (oa == 0) q.x -= osg;
+      else if (oa == 1) q.y -= osg;
+      else q.z -= osg;
+      const uint32_t wq = (uint32_t)(q.x / SEG) + (uint32_t)g.nseg_x * ((uint32_t)q.y + (uint32_t)g.ny * (uint32_t)q.z);
+      skip_out = (lk.seg_fluid[wq] >> (q.x % SEG)) & 1ull;
+    } else {
+      oa = -1;
+    }
+  }
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    St::template store<L>(dst + i * (size_t)g.npad + src_of<L>(pi, i), R(init_value<L>(p, n, i)), i);
+  for (int i = 0; i < L::Q; ++i) {
+    if ((cut >> i) & 1u) continue;
+    if (oa >= 0 && skip_out) {
+      const int ca = oa == 0 ? L::cx(i) : (oa == 1 ? L::cy(i) : L::cz(i));
+      if (ca == -osg) continue;
+    }
+    St::template store<L>(dst + i * (size_t)g.npad + ix.template src<L>(i), R(init_value<L>(p, n, i)), i);
+  }
 }
 
 template <class L, int S>
@@ -474,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) void init_links_kernel(InitParams p) {
 // ---------------------------------------------------------------------------
 // Export of the pre-collision state f_i(x, t) to [Q][N] float64.
 // ---------------------------------------------------------------------------
-template <class L, int S>
+template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void export_kernel(ExportParams p) {
   using R = typename Storage<S>::R;
   __shared__ R stage[L::Q][BLOCK];
@@ -484,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) void export_kernel(ExportParams p) {
   const bool in = si.c.x < g.nx;
   const bool fluid = in && ((p.lk.seg_fluid[si.seg] >> si.lane) & 1ull);
   R h[L::Q];
-  gather_state<L, S>(g, p.lk, p.src, si, fluid, h, stage);
+  gather_state<L, S, COMPACT>(g, p.lk, p.src, si, fluid, h, stage);
   if (!in) return;
   const Coords c = si.c;
   const int64_t n = c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * c.z);
@@ -510,7 +605,7 @@ __device__ __forceinline__ void block_sum_fixed(double (*sh)[BLOCK], double* v, 
   }
 }
 
-template <class L, int S>
+template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void macros_kernel(MacroParams p) {
   using R = typename Storage<S>::R;
   __shared__ double sh[NPART][BLOCK];
@@ -522,7 +617,7 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(MacroParams p) {
   const bool in = seg_ok && si.c.x < g.nx;
   const bool fluid = in && ((p.lk.seg_fluid[si.seg] >> si.lane) & 1ull);
   R h[L::Q];
-  if (seg_ok) gather_state<L, S>(g, p.lk, p.src, si, fluid, h, stage);
+  if (seg_ok) gather_state<L, S, COMPACT>(g, p.lk, p.src, si, fluid, h, stage);
   if (in) {
     const Coords c = si.c;
     const int64_t n = c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * c.z);
@@ -588,6 +683,29 @@ int64_t grid_blocks(const GridGeom& g) {
   return (b + 7) / 8 * 8;   // multiple of the XCD count, see logical_block()
 }
 
+#define LBM_DISPATCH_L(KERNEL, LAT, storage, C, grid, stream, params)                             \
+  do {                                                                                            \
+    switch (storage) {                                                                            \
+      case ST_F64: KERNEL<LAT, ST_F64, C><<<grid, BLOCK, 0, stream>>>(params); break;             \
+      case ST_F32: KERNEL<LAT, ST_F32, C><<<grid, BLOCK, 0, stream>>>(params); break;             \
+      case ST_F16S: KERNEL<LAT, ST_F16S, C><<<grid, BLOCK, 0, stream>>>(params); break;           \
+      default: KERNEL<LAT, ST_BF16S, C><<<grid, BLOCK, 0, stream>>>(params); break;               \
+    }                                                                                             \
+  } while (0)
+
+// lattice x storage x layout
+#define LBM_DISPATCH3(KERNEL, lattice, storage, compact, grid, stream, params)                    \
+  do {                                                                                            \
+    if (lattice == LBM_D2Q9) {                                                                    \
+      if (compact) LBM_DISPATCH_L(KERNEL, D2Q9, storage, true, grid, stream, params);             \
+      else LBM_DISPATCH_L(KERNEL, D2Q9, storage, false, grid, stream, params);                    \
+    } else {                                                                                      \
+      if (compact) LBM_DISPATCH_L(KERNEL, D3Q19, storage, true, grid, stream, params);            \
+      else LBM_DISPATCH_L(KERNEL, D3Q19, storage, false, grid, stream, params);                   \
+    }                                                                                             \
+  } while (0)
+
+// lattice x storage
 #define LBM_DISPATCH(KERNEL, lattice, storage, grid, stream, params)                              \
   do {                                                                                            \
     if (lattice == LBM_D2Q9) {                                                                    \
@@ -608,12 +726,12 @@ int64_t grid_blocks(const GridGeom& g) {
   } while (0)
 
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s) {
-  LBM_DISPATCH(step_kernel, lattice, storage, dim3((unsigned)grid_blocks(p.g)), s, p);
+  LBM_DISPATCH3(step_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_init(int lattice, int storage, const InitParams& p, hipStream_t s) {
-  LBM_DISPATCH(init_kernel, lattice, storage, dim3((unsigned)grid_blocks(p.g)), s, p);
+  LBM_DISPATCH3(init_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
   return hipGetLastError();
 }
 
@@ -624,12 +742,12 @@ hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipS
 }
 
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s) {
-  LBM_DISPATCH(export_kernel, lattice, storage, dim3((unsigned)grid_blocks(p.g)), s, p);
+  LBM_DISPATCH3(export_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s) {
-  LBM_DISPATCH(macros_kernel, lattice, storage, dim3((unsigned)nblocks), s, p);
+  LBM_DISPATCH3(macros_kernel, lattice, storage, p.g.compact, dim3((unsigned)nblocks), s, p);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ class Case:
         return sim
 
     # -- product path ----------------------------------------------------------
-    def gpu(self, B, storage="f64", variant="FQ", q_cut=0.01):
+    def gpu(self, B, storage="f64", variant="FQ", q_cut=0.01, layout="compact"):
         nx, ny, nz = self.n
         g = B.Geometry(self.lat, nx, ny, nz, periodic=self.periodic, outlet_face=self.outlet)
         for c, r, ins, V, Om in self.spheres:
@@ -51,7 +51,7 @@ class Case:
         mask, links = g.build()
         g.close()
         d = B.Domain(self.lat, nx, ny, nz, mask, self.tau, storage=storage, periodic=self.periodic,
-                     force=self.force, rho0=self.rho0, u0=self.u0, outlet_face=self.outlet)
+                     force=self.force, rho0=self.rho0, u0=self.u0, outlet_face=self.outlet, layout=layout)
         d.set_boundary_links(links, variant=variant, q_cutoff=q_cut)
         return d, mask, links
 

@@ -58,13 +58,14 @@ def test_couette_variants_f64(gpu_lib, variant, tau):
     d.close()
 
 
+@pytest.mark.parametrize("layout", ["compact", "dense"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_channel_cylinder(gpu_lib, storage):
+def test_channel_cylinder(gpu_lib, storage, layout):
     """Cylinder channel with parabolic inlet, walls and zero-gradient outlet,
     ragged row length (200 = 3 segments + 8)."""
     case = channel_case()
-    _say("case channel 200x80", storage)
-    d, _, _ = case.gpu(gpu_lib, storage)
+    _say("case channel 200x80", storage, layout)
+    d, _, _ = case.gpu(gpu_lib, storage, layout=layout)
     sim = case.oracle()
     d.step(1500)
     sim.run(1500)
@@ -74,15 +75,16 @@ def test_channel_cylinder(gpu_lib, storage):
     d.close()
 
 
+@pytest.mark.parametrize("layout", ["compact", "dense"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_packing_crop_with_force(gpu_lib, storage):
+def test_packing_crop_with_force(gpu_lib, storage, layout):
     """D3Q19 random packing (the 256^3 recipe at 40^3, radii 3..6) with Guo forcing."""
     n = 40
     c, r = synth.sphere_packing(n=n, r_min=3.0, r_max=6.0, solid_fraction=0.4, seed=5)
     case = Case("D3Q19", (n, n, n), spheres=[(cc, rr, True, None, None) for cc, rr in zip(c, r)],
                 tau=0.9, force=(1e-5, 0.0, 0.0))
-    _say("case packing 40^3", storage)
-    d, _, _ = case.gpu(gpu_lib, storage)
+    _say("case packing 40^3", storage, layout)
+    d, _, _ = case.gpu(gpu_lib, storage, layout=layout)
     sim = case.oracle()
     d.step(150)
     sim.run(150)
@@ -92,16 +94,17 @@ def test_packing_crop_with_force(gpu_lib, storage):
     d.close()
 
 
+@pytest.mark.parametrize("layout", ["compact", "dense"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_ragged_3d_walls_moving_sphere(gpu_lib, storage):
+def test_ragged_3d_walls_moving_sphere(gpu_lib, storage, layout):
     """67x29x23 D3Q19: non-periodic y with plane walls at q = 0.3 (top wall
     sliding), periodic x and z, a rotating translating sphere; ragged rows
     (67 = 64 + 3)."""
     case = Case("D3Q19", (67, 29, 23), periodic=(True, False, True),
                 spheres=[((30.4, 14.2, 11.7), 6.3, True, (0.01, -0.005, 0.002), (0.001, 0.0015, -0.002))],
                 faces=[(2, 0.3, None, 0), (3, 0.3, (0.02, 0.0, 0.01), 0)], tau=0.75, rho0=1.02)
-    _say("case ragged 3d", storage)
-    d, _, _ = case.gpu(gpu_lib, storage)
+    _say("case ragged 3d", storage, layout)
+    d, _, _ = case.gpu(gpu_lib, storage, layout=layout)
     sim = case.oracle()
     d.step(120)
     sim.run(120)
@@ -111,10 +114,11 @@ def test_ragged_3d_walls_moving_sphere(gpu_lib, storage):
     d.close()
 
 
-def test_all_fluid_periodic_no_links(gpu_lib):
+@pytest.mark.parametrize("layout", ["compact", "dense"])
+def test_all_fluid_periodic_no_links(gpu_lib, layout):
     """Empty link list: periodic all-fluid box from a perturbed state."""
     case = Case("D3Q19", (20, 9, 7), tau=0.7, force=(2e-5, 0, -1e-5))
-    d, _, _ = case.gpu(gpu_lib, "f64")
+    d, _, _ = case.gpu(gpu_lib, "f64", layout=layout)
     sim = case.oracle()
     rng = np.random.default_rng(4)
     sim.f = sim.f * (1.0 + 0.01 * rng.standard_normal(sim.f.shape))
@@ -126,10 +130,11 @@ def test_all_fluid_periodic_no_links(gpu_lib):
     d.close()
 
 
+@pytest.mark.parametrize("layout", ["compact", "dense"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
-def test_state_roundtrip(gpu_lib, storage):
+def test_state_roundtrip(gpu_lib, storage, layout):
     case = annulus_case()
-    d, mask, _ = case.gpu(gpu_lib, storage)
+    d, mask, _ = case.gpu(gpu_lib, storage, layout=layout)
     sim = case.oracle()
     sim.run(20)
     f = np.nan_to_num(sim.f)

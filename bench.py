@@ -35,24 +35,49 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="packing256", choices=["packing256", "channel2048"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
+    ap.add_argument("--layout", default="compact", choices=["compact", "dense"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the measurement, run one plain device copy of this size (for counter scaling)")
     return ap.parse_args()
 
 
-def build_workload(name, storage):
+def traffic_from_profile(workload, storage):
+    """HBM bytes per step-kernel launch measured with rocprofv3 counters (FETCH_SIZE
+    and WRITE_SIZE scaled by a copy kernel), if the summary in profiles/ was taken
+    on the current kernel sources; else None."""
+    from paper_2009_04604_amd.profiling import kernel_source_sha
+    path = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_{storage}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["kernel_bytes_per_launch.FETCH_SIZE"]) + float(kv["kernel_bytes_per_launch.WRITE_SIZE"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_workload(name, storage, layout):
     import synth
     from paper_2009_04604_amd import workloads as W
     if name == "packing256":
         n = 256
-        d, mask, links = W.packing_domain(n, storage)
+        d, mask, links = W.packing_domain(n, storage, layout=layout)
         cfg = {"workload": "sphere_packing_256^3_D3Q19", "lattice": "D3Q19", "n": [n, n, n], "porosity_target": 0.6,
                "tau": 0.9, "force": [1e-6, 0, 0], "variant": "ELIBB-FQ", "storage": storage}
     else:
         p = synth.cylinder_channel()
-        d, mask, links = W.channel_domain(p, storage)
+        d, mask, links = W.channel_domain(p, storage, layout=layout)
         cfg = {"workload": "cylinder_channel_2048x1024_D2Q9", "lattice": "D2Q9", "n": [p["nx"], p["ny"], 1],
                "reynolds": 100, "tau": p["tau"], "variant": "ELIBB-FQ", "storage": storage}
+    cfg["layout"] = layout
     return d, cfg
 
 
@@ -111,7 +136,7 @@ def main():
     from paper_2009_04604_amd import binding as B
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
-    d, cfg = build_workload(a.workload, a.storage)
+    d, cfg = build_workload(a.workload, a.storage, a.layout)
     info = d.info()
     nfl = info["n_fluid"]
     Q = info["q"]
@@ -137,7 +162,7 @@ def main():
     mlups = nfl * a.steps / wall / 1e6
     achieved = bytes_per_update * nfl / (kernel_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(a.workload, a.storage),
             "bytes_per_fluid_update": bytes_per_update,
             "link_bytes_per_fluid_update": round(info["link_bytes"] / nfl, 2),
             "kernel_ms": round(kernel_ms, 4)}
@@ -154,6 +179,13 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+    if a.calibration_copy_mib > 0:
+        n = a.calibration_copy_mib * 2**20 // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -42,24 +42,25 @@ def packing_geometry(n, centres, radii):
     return mask, links
 
 
-def couette_domain(p, storage="f64", variant="FQ"):
+def couette_domain(p, storage="f64", variant="FQ", layout="compact"):
     mask, links = annulus_geometry(p)
-    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage, rho0=p.get("rho0", 1.0))
+    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage, rho0=p.get("rho0", 1.0), layout=layout)
     d.set_boundary_links(links, variant=variant)
     return d, mask, links
 
 
-def channel_domain(p, storage="f32", variant="FQ"):
+def channel_domain(p, storage="f32", variant="FQ", layout="compact"):
     mask, links = channel_geometry(p)
     d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage,
-                 periodic=(False, False, True), outlet_face="+x")
+                 periodic=(False, False, True), outlet_face="+x", layout=layout)
     d.set_boundary_links(links, variant=variant)
     return d, mask, links
 
 
-def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), variant="FQ", spheres=None):
+def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), variant="FQ", spheres=None,
+                   layout="compact"):
     centres, radii = synth.sphere_packing(n=n) if spheres is None else spheres
     mask, links = packing_geometry(n, centres, radii)
-    d = B.Domain("D3Q19", n, n, n, mask, tau, storage=storage, force=force)
+    d = B.Domain("D3Q19", n, n, n, mask, tau, storage=storage, force=force, layout=layout)
     d.set_boundary_links(links, variant=variant)
     return d, mask, links

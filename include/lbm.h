@@ -112,6 +112,23 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
                            const double* q, const double* uw_t, const double* uw_t1,
                            int32_t variant, double q_cutoff);
 
+/* A rigid sphere in prescribed motion (Sec. II.E moving boundaries): centre
+ * x_c(t) = x0 + amplitude sin(2 pi t / period) direction, translational velocity
+ * V(t) = amplitude (2 pi / period) cos(2 pi t / period) direction, constant
+ * angular velocity omega.  Before every step t -> t+1 the library rebuilds on the
+ * device the fluid mask and the cut links of the sphere at time t (q by the exact
+ * ray-sphere intersection, u_w(t) = V(t) + omega x (x_W - x_c(t)),
+ * u_w(t+1) = V(t+1) + omega x (x_W - x_c(t))), and refills nodes that were solid
+ * at t-1 and are fluid at t with f^eq(rho_bar, V(t) + omega x (x - x_c(t))),
+ * rho_bar the mean density of their neighbours fluid at t-1 and t (rho0 if none).
+ * The LIR refill of the paper is not reproduced (its algorithm is only in a
+ * figure); this equilibrium refill replaces it.  Requirements (LBM_ESTATE
+ * otherwise): dense layout, no outlet, an all-fluid initial mask, no links and
+ * no step taken yet.  The state is reset to f^eq(rho0, u0) on the fluid nodes of
+ * time 0. */
+int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
+                          const double direction[3], const double omega[3], int32_t variant, double q_cutoff);
+
 /* Advance n_steps >= 0 time steps (collide, stream, rebuild every cut link);
  * asynchronous on the domain's stream.  LBM_ESTATE if links are missing. */
 int lbm_step(lbm_domain d, int32_t n_steps);

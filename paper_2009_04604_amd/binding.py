@@ -29,7 +29,7 @@ D_OF = {"D2Q9": 2, "D3Q19": 3}
 EXPORTED = [
     "lbm_arena_bytes", "lbm_init_domain", "lbm_set_boundary_links", "lbm_step", "lbm_macros",
     "lbm_get_state", "lbm_set_state", "lbm_set_stream", "lbm_set_launch_option", "lbm_get_info", "lbm_free_domain",
-    "lbm_last_error", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
+    "lbm_last_error", "lbm_set_moving_sphere", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
 ]
 
@@ -77,6 +77,7 @@ def lib():
         "lbm_init_domain": (I32, [P, P, P]),
         "lbm_set_boundary_links": (I32, [P, I64, P, P, P, P, P, I32, DBL]),
         "lbm_step": (I32, [P, I32]),
+        "lbm_set_moving_sphere": (I32, [P, P, DBL, DBL, DBL, P, P, I32, DBL]),
         "lbm_macros": (I32, [P, P, P, P]),
         "lbm_get_state": (I32, [P, P]),
         "lbm_set_state": (I32, [P, P]),
@@ -175,6 +176,15 @@ def lbm_set_boundary_links(h, node, dir, q, uw_t=None, uw_t1=None, variant="FQ",
     _check(lib().lbm_set_boundary_links(h, n, _ptr(node), _ptr(dir), _ptr(q), _ptr(uw_t), _ptr(uw_t1), v, float(q_cutoff)))
 
 
+def lbm_set_moving_sphere(h, x0, radius, amplitude, period, direction, omega, variant="FQ", q_cutoff=0.01):
+    x0 = np.ascontiguousarray(x0, dtype=np.float64).reshape(3)
+    e = np.ascontiguousarray(direction, dtype=np.float64).reshape(3)
+    om = np.ascontiguousarray(omega, dtype=np.float64).reshape(3)
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    _check(lib().lbm_set_moving_sphere(h, _ptr(x0), float(radius), float(amplitude), float(period), _ptr(e), _ptr(om),
+                                       v, float(q_cutoff)))
+
+
 def lbm_step(h, n_steps):
     _check(lib().lbm_step(h, int(n_steps)))
 
@@ -246,6 +256,9 @@ class Domain:
             kw = {"node": links["node"], "dir": links["dir"], "q": links["q"],
                   "uw_t": links.get("uw_t"), "uw_t1": links.get("uw_t1"), **kw}
         lbm_set_boundary_links(self.h, variant=variant, q_cutoff=q_cutoff, **kw)
+
+    def set_moving_sphere(self, x0, radius, amplitude, period, direction, omega, variant="FQ", q_cutoff=0.01):
+        lbm_set_moving_sphere(self.h, x0, radius, amplitude, period, direction, omega, variant, q_cutoff)
 
     def step(self, n=1):
         lbm_step(self.h, n)

@@ -173,6 +173,44 @@ hipError_t import_state(lbm_domain_s* d, const double* dev_f) {
   return e;
 }
 
+// Geometry of the moving sphere at time t on the device (classify, link prefix,
+// links, and with `refill` the fresh nodes of the current state).
+hipError_t rebuild_moving(lbm_domain_s* d, int64_t t, bool refill) {
+  MovingParams mp{};
+  mp.g = d->g;
+  const double two_pi = 2.0 * M_PI;
+  const double s = std::sin(two_pi * t / d->mv_period);
+  const double c0 = std::cos(two_pi * t / d->mv_period), c1 = std::cos(two_pi * (t + 1) / d->mv_period);
+  const double vamp = d->mv_amp * (two_pi / d->mv_period);
+  for (int a = 0; a < 3; ++a) {
+    mp.c[a] = d->mv_x0[a] + d->mv_amp * s * d->mv_dir[a];
+    mp.V[a] = vamp * c0 * d->mv_dir[a];
+    mp.V1[a] = vamp * c1 * d->mv_dir[a];
+    mp.Om[a] = d->mv_om[a];
+  }
+  if (d->D == 2) mp.c[2] = mp.V[2] = mp.V1[2] = 0.0;
+  mp.r = d->mv_r;
+  mp.variant = d->variant;
+  mp.q_cut = d->q_cut;
+  mp.reg_seg = d->reg_seg;
+  mp.nreg = d->nreg;
+  mp.seg_fluid = d->seg_fluid;
+  mp.seg_prev = d->seg_prev;
+  mp.seg_bnd = d->seg_bnd;
+  mp.seg_count = d->seg_count;
+  mp.seg_lbase = d->seg_lbase;
+  mp.lld = d->lld;
+  mp.lq = d->lq;
+  mp.lg = d->lg;
+  mp.pop = d->buf[d->cur];
+  mp.rho0 = d->desc.rho0;
+  hipError_t e = launch_moving_classify(d->desc.lattice, mp, d->stream);
+  if (e == hipSuccess) e = launch_exclusive_scan(d->seg_count, d->g.nseg, d->seg_lbase, d->stream);
+  if (e == hipSuccess) e = launch_moving_fill(d->desc.lattice, d->desc.storage, mp, d->stream);
+  if (e == hipSuccess && refill) e = launch_moving_refill(d->desc.lattice, d->desc.storage, mp, d->stream);
+  return e;
+}
+
 // Count populations of fluid nodes that are neither streamed nor outlet-covered
 // and not in `linked` (per-node direction mask; may be empty).
 int64_t first_uncovered(const lbm_domain_s* d, const std::vector<uint32_t>& linked, int* bad_dir) {
@@ -510,6 +548,84 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   return LBM_OK;
 }
 
+int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
+                          const double direction[3], const double omega[3], int32_t variant, double q_cutoff) {
+  if (!d || !x0 || !direction || !omega) return fail(LBM_EINVAL, "null argument");
+  if (!(radius > 0.0) || !(period > 0.0) || !(amplitude >= 0.0)) return fail(LBM_EINVAL, "radius, period must be > 0, amplitude >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(x0[a]) || !std::isfinite(direction[a]) || !std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite motion");
+  if (variant < LBM_ELIBB_FQ || variant > LBM_HWBB) return fail(LBM_EINVAL, "invalid variant");
+  if (!(q_cutoff >= 0.0) || !std::isfinite(q_cutoff)) return fail(LBM_EINVAL, "q_cutoff must be finite and >= 0");
+  if (d->g.compact) return fail(LBM_ESTATE, "a moving sphere needs the dense layout (desc.layout = LBM_LAYOUT_DENSE)");
+  if (d->desc.outlet_face >= 0) return fail(LBM_ESTATE, "a moving sphere needs a domain without outlet");
+  if (d->steps != 0 || d->moving || d->nl != 0) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
+  if (d->n_fluid != d->N) return fail(LBM_ESTATE, "the domain's initial mask must be all fluid");
+  const GridGeom& g = d->g;
+  if (!(g.perx && g.pery && g.perz)) return fail(LBM_ESTATE, "a moving sphere needs a fully periodic box");
+  {
+    const int n3[3] = {g.nx, g.ny, d->D == 3 ? g.nz : 1 << 30};
+    for (int a = 0; a < 3; ++a)
+      if (2.0 * (radius + std::fabs(amplitude * direction[a]) + 2.0) >= n3[a])
+        return fail(LBM_EINVAL, "the sphere and its sweep must fit in half the box on every axis");
+  }
+  // the region: segments of the box swept by the sphere (plus two nodes)
+  std::vector<char> in_seg(g.nseg, 0);
+  int lo[3], hi[3];
+  const int n[3] = {g.nx, g.ny, g.nz}, per[3] = {g.perx, g.pery, g.perz};
+  for (int a = 0; a < 3; ++a) {
+    const double ext = std::fabs(amplitude * direction[a]) + radius;
+    lo[a] = (int)std::floor(x0[a] - ext) - 2;
+    hi[a] = (int)std::ceil(x0[a] + ext) + 2;
+    if (d->D == 2 && a == 2) lo[a] = hi[a] = 0;
+    if (hi[a] - lo[a] + 1 >= n[a]) {
+      lo[a] = 0;
+      hi[a] = n[a] - 1;
+    } else if (!per[a]) {
+      lo[a] = std::max(lo[a], 0);
+      hi[a] = std::min(hi[a], n[a] - 1);
+    }
+  }
+  for (int zz = lo[2]; zz <= hi[2]; ++zz)
+    for (int yy = lo[1]; yy <= hi[1]; ++yy)
+      for (int xx = lo[0]; xx <= hi[0]; xx += 1) {
+        const int x = ((xx % n[0]) + n[0]) % n[0], y = ((yy % n[1]) + n[1]) % n[1], z = ((zz % n[2]) + n[2]) % n[2];
+        in_seg[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] = 1;
+      }
+  std::vector<int32_t> reg;
+  for (int64_t s2 = 0; s2 < g.nseg; ++s2)
+    if (in_seg[s2]) reg.push_back((int32_t)s2);
+  free_links(d);
+  const size_t rs = d->desc.storage == LBM_F64 ? 8 : 4;
+  d->nreg = (int64_t)reg.size();
+  d->link_cap = d->nreg * SEG * (d->Q - 1);
+  if (int e = dalloc(d->reg_seg, reg.size() * 4)) return e;
+  if (int e = dalloc(d->seg_prev, g.nseg * 8)) return e;
+  if (int e = dalloc(d->seg_count, g.nseg * 4)) return e;
+  if (int e = dalloc(d->lld, d->link_cap * 2)) return e;
+  if (int e = dalloc(d->lq, d->link_cap * rs)) return e;
+  if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
+  HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
+  HIP_TRY(hipMemset(d->seg_count, 0, g.nseg * 4));
+  for (int a = 0; a < 3; ++a) {
+    d->mv_x0[a] = x0[a];
+    d->mv_dir[a] = direction[a];
+    d->mv_om[a] = omega[a];
+  }
+  d->mv_r = radius;
+  d->mv_amp = amplitude;
+  d->mv_period = period;
+  d->variant = variant;
+  d->q_cut = q_cutoff;
+  d->moving = true;
+  HIP_TRY(rebuild_moving(d, 0, false));
+  HIP_TRY(import_state(d, nullptr));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  d->links_ok = true;
+  clear_error();
+  return LBM_OK;
+}
+
 int lbm_step(lbm_domain d, int32_t n_steps) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   if (n_steps < 0) return fail(LBM_EINVAL, "n_steps < 0");
@@ -520,6 +636,10 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step kernel: ") + hipGetErrorString(e));
     d->cur ^= 1;
     ++d->steps;
+    if (d->moving) {
+      e = rebuild_moving(d, d->steps, true);
+      if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("moving geometry: ") + hipGetErrorString(e));
+    }
   }
   return LBM_OK;
 }
@@ -606,9 +726,24 @@ int lbm_get_info(lbm_domain d, lbm_domain_info* info) {
   info->n_fluid = d->n_fluid;
   info->n_boundary_nodes = d->nb;
   info->n_links = d->nl;
+  if (d->moving) {   // the geometry of the current step lives on the device
+    std::vector<uint64_t> sf(d->g.nseg), sb(d->g.nseg);
+    int32_t nl = 0;
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    HIP_TRY(hipMemcpy(sf.data(), d->seg_fluid, d->g.nseg * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sb.data(), d->seg_bnd, d->g.nseg * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&nl, d->seg_lbase + d->g.nseg, 4, hipMemcpyDeviceToHost));
+    info->n_fluid = info->n_boundary_nodes = 0;
+    for (int64_t s2 = 0; s2 < d->g.nseg; ++s2) {
+      info->n_fluid += __builtin_popcountll(sf[s2]);
+      info->n_boundary_nodes += __builtin_popcountll(sb[s2]);
+    }
+    info->n_links = nl;
+  }
   info->population_bytes = (int64_t)(2 * d->g.npad * d->Q * d->elem);
   const int64_t rs = d->desc.storage == LBM_F64 ? 8 : 4;
-  info->link_bytes = d->nl * (2 + rs * (d->lg ? 2 : 1)) + d->g.nseg * 20;
+  // per link: ld, q, (Gw), two link values (list mode); per segment: masks and prefixes
+  info->link_bytes = info->n_links * (2 + rs * (1 + (d->lg ? 1 : 0) + (d->lv[0] ? 2 : 0))) + d->g.nseg * 24;
   info->steps_done = d->steps;
   info->q = d->Q;
   info->storage = d->desc.storage;
@@ -631,6 +766,9 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->partials);
   dfree(d->sums);
   dfree(d->uprev);
+  dfree(d->reg_seg);
+  dfree(d->seg_prev);
+  dfree(d->seg_count);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

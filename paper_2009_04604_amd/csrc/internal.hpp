@@ -134,6 +134,28 @@ struct MacroParams {
 };
 constexpr int NPART = 8;         // mass, mom x/y/z, |du|^2, |u|^2, non-finite count, pad
 
+// One moving sphere (dense layout, slot mode): the geometry of time t is rebuilt
+// on the device over a fixed region of segments (the sphere's sweep box).
+struct MovingParams {
+  GridGeom g;
+  double c[3], r;                // centre at t, radius
+  double V[3], V1[3], Om[3];     // translational velocity at t and t+1, angular velocity
+  int32_t variant;
+  double q_cut;
+  const int32_t* reg_seg;        // region segments
+  int64_t nreg;
+  uint64_t* seg_fluid;           // fluid mask at t (written by classify)
+  uint64_t* seg_prev;            // fluid mask at t-1 (written by classify)
+  uint64_t* seg_bnd;
+  int32_t* seg_count;            // cut links per segment
+  const int32_t* seg_lbase;      // exclusive prefix of seg_count
+  uint16_t* lld;
+  void* lq;
+  void* lg;
+  void* pop;                     // current population buffer (refill)
+  double rho0;
+};
+
 // Number of workgroups of the lattice kernels (a multiple of the 8 XCDs).
 int64_t grid_blocks(const GridGeom& g);
 
@@ -144,6 +166,10 @@ hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipS
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s);
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
+hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);
+hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, hipStream_t s);
+hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
+hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 
 }  // namespace lbm
 
@@ -182,4 +208,12 @@ struct lbm_domain_s {
   double* u_tmp;
   int64_t red_blocks;
   int64_t steps;
+  // moving sphere (lbm_set_moving_sphere)
+  bool moving;
+  double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
+  int32_t* reg_seg;
+  int64_t nreg;
+  uint64_t* seg_prev;
+  int32_t* seg_count;
+  int64_t link_cap;
 };

@@ -1,0 +1,304 @@
+// Device-side geometry of a moving rigid sphere (dense layout, slot mode): the
+// fluid mask, the cut links (q from the exact ray-sphere intersection, wall
+// velocity of the rigid-body motion, Sec. II.E moving boundaries) and the
+// equilibrium refill of fresh nodes are rebuilt every step over the segments
+// of the sphere's sweep region.
+//
+// Geometry arithmetic is done with explicitly rounded FP64 operations (no FMA
+// contraction) so that classification and q reproduce the plain double
+// precision definition bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "elibb.hpp"
+#include "internal.hpp"
+#include "lattice.hpp"
+#include "storage.hpp"
+
+namespace lbm {
+namespace {
+
+struct Site {
+  uint32_t seg;
+  int lane, x, y, z;
+};
+
+__device__ __forceinline__ Site region_site(const MovingParams& p, int64_t wave) {
+  Site s;
+  s.seg = (uint32_t)p.reg_seg[wave];
+  s.lane = threadIdx.x & 63;
+  const GridGeom& g = p.g;
+  const uint32_t row = s.seg / (uint32_t)g.nseg_x;
+  const uint32_t sx = s.seg - row * (uint32_t)g.nseg_x;
+  s.x = (int)sx * 64 + s.lane;
+  s.y = (int)(row % (uint32_t)g.ny);
+  s.z = (int)(row / (uint32_t)g.ny);
+  return s;
+}
+
+// minimum image on a periodic axis: d - L rint(d / L) (round half to even)
+__device__ __forceinline__ double min_image(double d, int L, int periodic) {
+  if (!periodic) return d;
+  const double Ld = (double)L;
+  return __dsub_rn(d, __dmul_rn(Ld, rint(__ddiv_rn(d, Ld))));
+}
+
+__device__ __forceinline__ void rel(const MovingParams& p, double x, double y, double z, double (&d)[3]) {
+  d[0] = min_image(__dsub_rn(x, p.c[0]), p.g.nx, p.g.perx);
+  d[1] = min_image(__dsub_rn(y, p.c[1]), p.g.ny, p.g.pery);
+  d[2] = min_image(__dsub_rn(z, p.c[2]), p.g.nz, p.g.perz);
+}
+
+__device__ __forceinline__ double norm2(const double (&d)[3]) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])), __dmul_rn(d[2], d[2]));
+}
+
+// solid (inside or on the sphere) at integer node coordinates
+__device__ __forceinline__ bool solid_at(const MovingParams& p, int x, int y, int z) {
+  double d[3];
+  rel(p, (double)x, (double)y, (double)z, d);
+  return norm2(d) <= __dmul_rn(p.r, p.r);
+}
+
+__device__ __forceinline__ int wrap(int v, int n, int periodic) {
+  if (!periodic) return v;
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// first crossing lam in (0, 1] of x_F - lam c with the sphere (entering root)
+__device__ __forceinline__ double crossing(const MovingParams& p, int x, int y, int z, int cx, int cy, int cz) {
+  double d[3];
+  rel(p, (double)x, (double)y, (double)z, d);
+  const double c[3] = {(double)cx, (double)cy, (double)cz};
+  const double A = __dadd_rn(__dadd_rn(__dmul_rn(c[0], c[0]), __dmul_rn(c[1], c[1])), __dmul_rn(c[2], c[2]));
+  const double B = __dadd_rn(__dadd_rn(__dmul_rn(d[0], c[0]), __dmul_rn(d[1], c[1])), __dmul_rn(d[2], c[2]));
+  const double C0 = __dsub_rn(norm2(d), __dmul_rn(p.r, p.r));
+  const double disc = __dsub_rn(__dmul_rn(B, B), __dmul_rn(A, C0));
+  const double sq = disc >= 0.0 ? __dsqrt_rn(disc) : 0.0;
+  const double lam = __ddiv_rn(__dsub_rn(B, sq), A);
+  return fmin(fmax(lam, 1e-12), 1.0);
+}
+
+// rigid-body velocity V + Omega x r, r the minimum image of x - centre(t)
+__device__ __forceinline__ void body_velocity(const MovingParams& p, const double (&V)[3], const double (&r)[3],
+                                              double (&u)[3]) {
+  u[0] = __dadd_rn(V[0], __dsub_rn(__dmul_rn(p.Om[1], r[2]), __dmul_rn(p.Om[2], r[1])));
+  u[1] = __dadd_rn(V[1], __dsub_rn(__dmul_rn(p.Om[2], r[0]), __dmul_rn(p.Om[0], r[2])));
+  u[2] = __dadd_rn(V[2], __dsub_rn(__dmul_rn(p.Om[0], r[1]), __dmul_rn(p.Om[1], r[0])));
+}
+
+// cut directions of the fluid node (x, y, z): source x - c_i inside the sphere
+template <class L>
+__device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y, int z) {
+  const GridGeom& g = p.g;
+  uint32_t m = 0u;
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const int sx = wrap(x - L::cx(i), g.nx, g.perx);
+    const int sy = wrap(y - L::cy(i), g.ny, g.pery);
+    const int sz = wrap(z - L::cz(i), g.nz, g.perz);
+    if (solid_at(p, sx, sy, sz)) m |= 1u << i;
+  }
+  return m;
+}
+
+template <class L>
+__global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave >= p.nreg) return;
+  const Site s = region_site(p, wave);
+  const GridGeom& g = p.g;
+  const bool in = s.x < g.nx;
+  const bool fluid = in && !solid_at(p, s.x, s.y, s.z);
+  const uint64_t fm = __ballot(fluid);
+  const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
+  const int cnt = __popc(cm);
+  const uint64_t bm = __ballot(cnt > 0);
+  int tot = cnt;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+  if (s.lane == 0) {
+    p.seg_prev[s.seg] = p.seg_fluid[s.seg];
+    p.seg_fluid[s.seg] = fm;
+    p.seg_bnd[s.seg] = bm;
+    p.seg_count[s.seg] = tot;
+  }
+}
+
+// exclusive prefix sum of n counts into out[0..n] (single workgroup, fixed order)
+__global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int32_t* in, int64_t n, int32_t* out) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = t * chunk, e = min(n, b + chunk);
+  int32_t acc = 0;
+  for (int64_t k = b; k < e; ++k) acc += in[k];
+  part[t] = acc;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const int32_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    out[n] = run;
+  }
+  __syncthreads();
+  int32_t run = part[t];
+  for (int64_t k = b; k < e; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+}
+
+template <class L, typename R>
+__global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave >= p.nreg) return;
+  const Site s = region_site(p, wave);
+  const bool fluid = (p.seg_fluid[s.seg] >> s.lane) & 1ull;
+  const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
+  // exclusive prefix of the lanes' link counts
+  const int cnt = __popc(cm);
+  int inc = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(inc, off, 64);
+    if (s.lane >= off) inc += v;
+  }
+  int k = p.seg_lbase[s.seg] + inc - cnt;
+  R* lq = static_cast<R*>(p.lq);
+  R* lg = static_cast<R*>(p.lg);
+  for (int i = 1; i < L::Q; ++i) {
+    if (!((cm >> i) & 1u)) continue;
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const double q = crossing(p, s.x, s.y, s.z, cx, cy, cz);
+    // wall point and its rigid-body velocity at t and t+1
+    const double xw[3] = {__dsub_rn((double)s.x, __dmul_rn(q, (double)cx)), __dsub_rn((double)s.y, __dmul_rn(q, (double)cy)),
+                          __dsub_rn((double)s.z, __dmul_rn(q, (double)cz))};
+    double r[3];
+    rel(p, xw[0], xw[1], xw[2], r);
+    double u0[3], u1[3];
+    const double V[3] = {p.V[0], p.V[1], p.V[2]}, V1[3] = {p.V1[0], p.V1[1], p.V1[2]};
+    body_velocity(p, V, r, u0);
+    body_velocity(p, V1, r, u1);
+    if (L::D == 2) u0[2] = u1[2] = 0.0;
+    const double cu0 = cx * u0[0] + cy * u0[1] + cz * u0[2];
+    const double cu1 = cx * u1[0] + cy * u1[1] + cz * u1[2];
+    const double uu0 = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
+    const double uu1 = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+    const Coef<R> a = elibb_coefficients<R>(p.variant, R(q), R(p.q_cut));
+    const Coef<double> ad{a.a4, a.a5, a.a2, a.a3};
+    p.lld[k] = (uint16_t)(s.lane | (i << 8));
+    lq[k] = R(q);
+    lg[k] = R(wall_term<double>(ad, cu0, uu0, cu1, uu1));
+    ++k;
+  }
+}
+
+// fresh nodes (solid at t-1, fluid at t): f = f^eq(rho_bar, u_body(x)), rho_bar the
+// mean density of the neighbours that are fluid at t-1 and t (rho0 if none)
+template <class L, int S>
+__global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
+  using St = Storage<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave >= p.nreg) return;
+  const Site s = region_site(p, wave);
+  const GridGeom& g = p.g;
+  const uint64_t fresh = p.seg_fluid[s.seg] & ~p.seg_prev[s.seg];
+  if (!((fresh >> s.lane) & 1ull)) return;
+  T* pop = static_cast<T*>(p.pop);
+  const size_t np = (size_t)g.npad;
+  auto slot = [&](int x, int y, int z) -> uint32_t {   // dense storage index (periodic box)
+    return (uint32_t)(x + g.px) + (uint32_t)g.NX * ((uint32_t)(y + g.py) + (uint32_t)g.NY * (uint32_t)(z + g.pz));
+  };
+  double tot = 0.0;
+  int cnt = 0;
+#pragma unroll
+  for (int j = 1; j < L::Q; ++j) {
+    const int yx = wrap(s.x + L::cx(j), g.nx, g.perx);
+    const int yy = wrap(s.y + L::cy(j), g.ny, g.pery);
+    const int yz = wrap(s.z + L::cz(j), g.nz, g.perz);
+    if (yx < 0 || yx >= g.nx || yy < 0 || yy >= g.ny || yz < 0 || yz >= g.nz) continue;
+    const uint32_t ys = (uint32_t)(yx / 64) + (uint32_t)g.nseg_x * ((uint32_t)yy + (uint32_t)g.ny * (uint32_t)yz);
+    const uint64_t bit = 1ull << (yx % 64);
+    if (!(p.seg_fluid[ys] & bit) || !(p.seg_prev[ys] & bit)) continue;
+    double rho = 1.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      const int sx = wrap(yx - L::cx(k), g.nx, g.perx);
+      const int sy = wrap(yy - L::cy(k), g.ny, g.pery);
+      const int sz = wrap(yz - L::cz(k), g.nz, g.perz);
+      rho += (double)St::template load<L>(pop + k * np + slot(sx, sy, sz), k);
+    }
+    tot += rho;
+    ++cnt;
+  }
+  const double rb = cnt > 0 ? tot / cnt : p.rho0;
+  double r[3], u[3];
+  rel(p, (double)s.x, (double)s.y, (double)s.z, r);
+  const double V[3] = {p.V[0], p.V[1], p.V[2]};
+  body_velocity(p, V, r, u);
+  if (L::D == 2) u[2] = 0.0;
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
+    const double h = L::w(i) * ((rb - 1.0) + rb * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    const int sx = wrap(s.x - L::cx(i), g.nx, g.perx);
+    const int sy = wrap(s.y - L::cy(i), g.ny, g.pery);
+    const int sz = wrap(s.z - L::cz(i), g.nz, g.perz);
+    St::template store<L>(pop + i * np + slot(sx, sy, sz), R(h), i);
+  }
+}
+
+}  // namespace
+
+static inline dim3 region_grid(const MovingParams& p) { return dim3((unsigned)((p.nreg + 3) / 4)); }
+
+hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s) {
+  if (p.nreg == 0) return hipSuccess;
+  if (lattice == LBM_D2Q9) classify_kernel<D2Q9><<<region_grid(p), 256, 0, s>>>(p);
+  else classify_kernel<D3Q19><<<region_grid(p), 256, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
+  exclusive_scan_kernel<<<1, 1024, 0, s>>>(in, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s) {
+  if (p.nreg == 0) return hipSuccess;
+  const bool f64 = storage == ST_F64;
+  if (lattice == LBM_D2Q9) {
+    if (f64) fill_kernel<D2Q9, double><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D2Q9, float><<<region_grid(p), 256, 0, s>>>(p);
+  } else {
+    if (f64) fill_kernel<D3Q19, double><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D3Q19, float><<<region_grid(p), 256, 0, s>>>(p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s) {
+  if (p.nreg == 0) return hipSuccess;
+#define LBM_REFILL(LAT)                                                                     \
+  switch (storage) {                                                                        \
+    case ST_F64: refill_kernel<LAT, ST_F64><<<region_grid(p), 256, 0, s>>>(p); break;       \
+    case ST_F32: refill_kernel<LAT, ST_F32><<<region_grid(p), 256, 0, s>>>(p); break;       \
+    case ST_F16S: refill_kernel<LAT, ST_F16S><<<region_grid(p), 256, 0, s>>>(p); break;     \
+    default: refill_kernel<LAT, ST_BF16S><<<region_grid(p), 256, 0, s>>>(p); break;         \
+  }
+  if (lattice == LBM_D2Q9) {
+    LBM_REFILL(D2Q9)
+  } else {
+    LBM_REFILL(D3Q19)
+  }
+#undef LBM_REFILL
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -174,6 +174,55 @@ int lbm_get_info(lbm_domain d, lbm_domain_info* info);
 /* Release every resource of the domain (does not free a caller arena). */
 int lbm_free_domain(lbm_domain d);
 
+/* ---------------------------------------------------------------------------
+ * Batched stepping: many domains of different sizes advance together.  Per
+ * step there is one persistent multi-domain launch for each group of domains
+ * that share lattice, storage and layout, followed by the batched rebuild of
+ * the moving spheres among them; the launches of two steps are captured once
+ * into a HIP graph and replayed.  Every node's arithmetic is the same as in
+ * lbm_step, so results are bit-identical to stepping each domain alone, for
+ * every launch choice.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch_s* lbm_batch;
+
+/* stream: the stream of every member domain (NULL = default stream). */
+int lbm_batch_create(void* stream, lbm_batch* out);
+
+/* Advance each of the n domains by n_steps >= 0 (asynchronous on the stream,
+ * like lbm_step).  Every domain must have its links or moving sphere set, use the
+ * batch's stream and appear once (LBM_EINVAL / LBM_ESTATE otherwise).  A call
+ * with another membership than the previous one synchronises the stream first.
+ * With LBM_BATCH_AUTOTUNE on and no tuned choice for this batch's shape class,
+ * the first 49 steps of the call run the autotuner (and still count as steps). */
+int lbm_batch_step(lbm_batch b, const lbm_domain* ds, int32_t n, int32_t n_steps);
+
+/* Launch choices (no effect on results):
+ *   LBM_BATCH_GRAPH     1 (default) replay captured step pairs, 0 eager launches
+ *   LBM_BATCH_GRID      0 one workgroup per tile of 4 row segments; k > 0 a
+ *                       persistent grid of k workgroups per compute unit; -1 tuned
+ *   LBM_BATCH_ORDER     0 tiles in call order; 1 the same, each XCD given a
+ *                       contiguous share; 2 largest domain first, XCD shares; -1 tuned
+ *   LBM_BATCH_AUTOTUNE  1 tune automatically in lbm_batch_step, 0 (default) not */
+enum { LBM_BATCH_GRAPH = 0, LBM_BATCH_GRID = 1, LBM_BATCH_ORDER = 2, LBM_BATCH_AUTOTUNE = 3 };
+int lbm_batch_set_option(lbm_batch b, int32_t option, int32_t value);
+
+/* Autotuner: one warm-up step, then every (grid in {0, 2, 4, 6}) x (order in {0,
+ * 1, 2}) candidate runs steps_per_candidate real steps (the domains advance by
+ * 1 + 12 steps_per_candidate in total) timed with HIP events; the fastest is
+ * kept for the shape class (lattice, storage, layout, log2 of the tile count)
+ * and used by later calls unless an option forces another.  Synchronises. */
+int lbm_batch_autotune(lbm_batch b, const lbm_domain* ds, int32_t n, int32_t steps_per_candidate);
+
+/* Launch choice of the first group and the autotuner's best time per step (us). */
+int lbm_batch_get_choice(lbm_batch b, int32_t* grid, int32_t* order, double* us_per_step);
+
+/* Synchronises the stream and releases the batch (not its domains). */
+int lbm_batch_free(lbm_batch b);
+
+/* One-shot form: a temporary batch on ds[0]'s stream, eager launches;
+ * synchronises. */
+int lbm_step_batch(const lbm_domain* ds, int32_t n, int32_t n_steps);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char* lbm_last_error(void);
 

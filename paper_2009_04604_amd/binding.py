@@ -31,7 +31,10 @@ EXPORTED = [
     "lbm_get_state", "lbm_set_state", "lbm_set_stream", "lbm_set_launch_option", "lbm_get_info", "lbm_free_domain",
     "lbm_last_error", "lbm_set_moving_sphere", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
+    "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
+    "lbm_batch_free", "lbm_step_batch",
 ]
+BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
 
 class LBMError(RuntimeError):
@@ -92,6 +95,13 @@ def lib():
         "lbm_geometry_build": (I32, [P, P, P]),
         "lbm_geometry_get": (I32, [P, P, P, P, P, P, P]),
         "lbm_geometry_free": (I32, [P]),
+        "lbm_batch_create": (I32, [P, P]),
+        "lbm_batch_step": (I32, [P, P, I32, I32]),
+        "lbm_batch_set_option": (I32, [P, I32, I32]),
+        "lbm_batch_autotune": (I32, [P, P, I32, I32]),
+        "lbm_batch_get_choice": (I32, [P, P, P, P]),
+        "lbm_batch_free": (I32, [P]),
+        "lbm_step_batch": (I32, [P, I32, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -287,6 +297,79 @@ class Domain:
             lbm_free_domain(self.h)
             self.h = None
             self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _handles(domains):
+    hs = [d.h if isinstance(d, Domain) else d for d in domains]
+    return (ctypes.c_void_p * max(1, len(hs)))(*hs), len(hs)
+
+
+def lbm_batch_create(stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().lbm_batch_create(stream, ctypes.byref(h)))
+    return h.value
+
+
+def lbm_batch_step(b, domains, n_steps):
+    arr, n = _handles(domains)
+    _check(lib().lbm_batch_step(b, arr, n, int(n_steps)))
+
+
+def lbm_batch_set_option(b, option, value):
+    _check(lib().lbm_batch_set_option(b, BATCH_OPTIONS.get(option, option), int(value)))
+
+
+def lbm_batch_autotune(b, domains, steps_per_candidate):
+    arr, n = _handles(domains)
+    _check(lib().lbm_batch_autotune(b, arr, n, int(steps_per_candidate)))
+
+
+def lbm_batch_get_choice(b):
+    g, o, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().lbm_batch_get_choice(b, ctypes.byref(g), ctypes.byref(o), ctypes.byref(us)))
+    return {"grid": g.value, "order": o.value, "us_per_step": us.value}
+
+
+def lbm_batch_free(b):
+    _check(lib().lbm_batch_free(b))
+
+
+def lbm_step_batch(domains, n_steps):
+    arr, n = _handles(domains)
+    _check(lib().lbm_step_batch(arr, n, int(n_steps)))
+
+
+class Batch:
+    """Many domains stepped together (lbm_batch_*); all on one stream."""
+
+    def __init__(self, stream=None):
+        if stream is None:
+            stream = _torch_stream()
+        self.h = lbm_batch_create(stream)
+
+    def step(self, domains, n_steps):
+        lbm_batch_step(self.h, domains, n_steps)
+
+    def set_option(self, option, value):
+        lbm_batch_set_option(self.h, option, value)
+
+    def autotune(self, domains, steps_per_candidate=4):
+        lbm_batch_autotune(self.h, domains, steps_per_candidate)
+        return lbm_batch_get_choice(self.h)
+
+    def choice(self):
+        return lbm_batch_get_choice(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_batch_free(self.h)
+            self.h = None
 
     def __del__(self):
         try:

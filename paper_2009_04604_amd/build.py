@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os
 # device code: gfx950 only; packed FP32 instructions disabled
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["kernels.hip", "moving.hip", "api.cpp", "geometry.cpp"]
+SOURCES = ["kernels.hip", "moving.hip", "api.cpp", "batch.cpp", "geometry.cpp"]
 
 
 def _run(cmd):

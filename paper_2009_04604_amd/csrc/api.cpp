@@ -132,12 +132,16 @@ LinkView link_view(const lbm_domain_s* d, const void* lv_in, void* lv_out) {
   return lk;
 }
 
-StepParams step_params(lbm_domain_s* d) {
+}  // namespace
+
+namespace lbm {
+
+StepParams step_params(const lbm_domain_s* d, int cur) {
   StepParams p{};
   p.g = d->g;
-  p.src = d->buf[d->cur];
-  p.dst = d->buf[1 - d->cur];
-  p.lk = link_view(d, d->lv[d->cur], d->lv[1 - d->cur]);
+  p.src = d->buf[cur];
+  p.dst = d->buf[1 - cur];
+  p.lk = link_view(d, d->lv[cur], d->lv[1 - cur]);
   p.omega = 1.0 / d->desc.tau;
   for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
   p.has_force = (d->desc.force[0] != 0.0 || d->desc.force[1] != 0.0 || d->desc.force[2] != 0.0);
@@ -146,6 +150,51 @@ StepParams step_params(lbm_domain_s* d) {
   p.outlet_face = d->desc.outlet_face;
   return p;
 }
+
+// Kinematics of the moving sphere for the geometry of time t: centre
+// x0 + A sin(2 pi t / T) e and its velocity at t and t + 1.
+MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
+  MovingKin k{};
+  const double two_pi = 2.0 * M_PI;
+  const double s = std::sin(two_pi * t / d->mv_period);
+  const double c0 = std::cos(two_pi * t / d->mv_period), c1 = std::cos(two_pi * (t + 1) / d->mv_period);
+  const double vamp = d->mv_amp * (two_pi / d->mv_period);
+  for (int a = 0; a < 3; ++a) {
+    k.c[a] = d->mv_x0[a] + d->mv_amp * s * d->mv_dir[a];
+    k.V[a] = vamp * c0 * d->mv_dir[a];
+    k.V1[a] = vamp * c1 * d->mv_dir[a];
+  }
+  if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
+  return k;
+}
+
+// Static part of the moving-sphere rebuild; `cur` names the population buffer
+// that holds the state the fresh nodes are refilled in.
+MovingParams moving_params(const lbm_domain_s* d, int cur) {
+  MovingParams mp{};
+  mp.g = d->g;
+  for (int a = 0; a < 3; ++a) mp.Om[a] = d->mv_om[a];
+  mp.r = d->mv_r;
+  mp.variant = d->variant;
+  mp.q_cut = d->q_cut;
+  mp.reg_seg = d->reg_seg;
+  mp.nreg = d->nreg;
+  mp.seg_fluid = d->seg_fluid;
+  mp.seg_prev = d->seg_prev;
+  mp.seg_bnd = d->seg_bnd;
+  mp.seg_count = d->seg_count;
+  mp.seg_lbase = d->seg_lbase;
+  mp.lld = d->lld;
+  mp.lq = d->lq;
+  mp.lg = d->lg;
+  mp.pop = d->buf[cur];
+  mp.rho0 = d->desc.rho0;
+  return mp;
+}
+
+}  // namespace lbm
+
+namespace {
 
 // Export the current state to a device [Q][N] float64 buffer.
 hipError_t export_state(lbm_domain_s* d, double* dev_f) {
@@ -176,34 +225,8 @@ hipError_t import_state(lbm_domain_s* d, const double* dev_f) {
 // Geometry of the moving sphere at time t on the device (classify, link prefix,
 // links, and with `refill` the fresh nodes of the current state).
 hipError_t rebuild_moving(lbm_domain_s* d, int64_t t, bool refill) {
-  MovingParams mp{};
-  mp.g = d->g;
-  const double two_pi = 2.0 * M_PI;
-  const double s = std::sin(two_pi * t / d->mv_period);
-  const double c0 = std::cos(two_pi * t / d->mv_period), c1 = std::cos(two_pi * (t + 1) / d->mv_period);
-  const double vamp = d->mv_amp * (two_pi / d->mv_period);
-  for (int a = 0; a < 3; ++a) {
-    mp.c[a] = d->mv_x0[a] + d->mv_amp * s * d->mv_dir[a];
-    mp.V[a] = vamp * c0 * d->mv_dir[a];
-    mp.V1[a] = vamp * c1 * d->mv_dir[a];
-    mp.Om[a] = d->mv_om[a];
-  }
-  if (d->D == 2) mp.c[2] = mp.V[2] = mp.V1[2] = 0.0;
-  mp.r = d->mv_r;
-  mp.variant = d->variant;
-  mp.q_cut = d->q_cut;
-  mp.reg_seg = d->reg_seg;
-  mp.nreg = d->nreg;
-  mp.seg_fluid = d->seg_fluid;
-  mp.seg_prev = d->seg_prev;
-  mp.seg_bnd = d->seg_bnd;
-  mp.seg_count = d->seg_count;
-  mp.seg_lbase = d->seg_lbase;
-  mp.lld = d->lld;
-  mp.lq = d->lq;
-  mp.lg = d->lg;
-  mp.pop = d->buf[d->cur];
-  mp.rho0 = d->desc.rho0;
+  MovingParams mp = moving_params(d, d->cur);
+  mp.k = moving_kin(d, t);
   hipError_t e = launch_moving_classify(d->desc.lattice, mp, d->stream);
   if (e == hipSuccess) e = launch_exclusive_scan(d->seg_count, d->g.nseg, d->seg_lbase, d->stream);
   if (e == hipSuccess) e = launch_moving_fill(d->desc.lattice, d->desc.storage, mp, d->stream);
@@ -631,7 +654,7 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
   if (n_steps < 0) return fail(LBM_EINVAL, "n_steps < 0");
   if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set: some populations would be missing");
   for (int32_t s = 0; s < n_steps; ++s) {
-    StepParams p = step_params(d);
+    StepParams p = step_params(d, d->cur);
     hipError_t e = launch_step(d->desc.lattice, d->desc.storage, p, d->stream);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step kernel: ") + hipGetErrorString(e));
     d->cur ^= 1;

@@ -134,12 +134,19 @@ struct MacroParams {
 };
 constexpr int NPART = 8;         // mass, mom x/y/z, |du|^2, |u|^2, non-finite count, pad
 
+// Kinematics of a moving sphere for the geometry of time t.
+struct MovingKin {
+  double c[3];                   // centre at t
+  double V[3], V1[3];            // translational velocity at t and t+1
+};
+
 // One moving sphere (dense layout, slot mode): the geometry of time t is rebuilt
 // on the device over a fixed region of segments (the sphere's sweep box).
 struct MovingParams {
   GridGeom g;
-  double c[3], r;                // centre at t, radius
-  double V[3], V1[3], Om[3];     // translational velocity at t and t+1, angular velocity
+  MovingKin k;                   // single-domain launches; batched launches read a table
+  double r, Om[3];               // radius, angular velocity
+  int32_t kin_slot;              // batched launches: column of this sphere in the table
   int32_t variant;
   double q_cut;
   const int32_t* reg_seg;        // region segments
@@ -156,6 +163,11 @@ struct MovingParams {
   double rho0;
 };
 
+// Tile table of a batched step: domain << TILE_SHIFT | block of that domain.
+constexpr uint32_t TILE_SHIFT = 22;
+constexpr uint32_t TILE_MASK = (1u << TILE_SHIFT) - 1u;
+constexpr uint32_t TILE_EMPTY = ~0u;
+
 // Number of workgroups of the lattice kernels (a multiple of the 8 XCDs).
 int64_t grid_blocks(const GridGeom& g);
 
@@ -170,6 +182,22 @@ hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_
 hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
+hipError_t launch_step_batch(int lattice, int storage, bool compact, const StepParams* tab, const uint32_t* tiles,
+                             uint32_t nslots, uint32_t grid, hipStream_t s);
+// Batched moving-sphere rebuild (moving.hip).  tab: one MovingParams per sphere;
+// waves: region waves as sphere << TILE_SHIFT | wave; kin: [step][nkin] table,
+// row *ctr is the geometry time being built.
+struct MovingBatch {
+  const MovingParams* tab;
+  int32_t nbox;
+  const uint32_t* waves;
+  uint32_t nwaves;
+  const MovingKin* kin;
+  int32_t nkin;
+  const int64_t* ctr;
+};
+hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s);
+hipError_t launch_advance(int64_t* ctr, hipStream_t s);
 
 }  // namespace lbm
 
@@ -217,3 +245,11 @@ struct lbm_domain_s {
   int32_t* seg_count;
   int64_t link_cap;
 };
+
+namespace lbm {
+// Kernel parameters of one domain (api.cpp), used by the single-domain calls
+// and by the batched step.  `cur` names the buffer holding the current state.
+StepParams step_params(const lbm_domain_s* d, int cur);
+MovingParams moving_params(const lbm_domain_s* d, int cur);
+MovingKin moving_kin(const lbm_domain_s* d, int64_t t);
+}  // namespace lbm

@@ -42,10 +42,10 @@ __device__ __forceinline__ uint32_t logical_block(int remap) {
   return (b & 7u) * per + (b >> 3);
 }
 
-__device__ __forceinline__ SegInfo seg_info(const GridGeom& g) {
+__device__ __forceinline__ SegInfo seg_info(const GridGeom& g, uint32_t block) {
   SegInfo s;
   s.lane = threadIdx.x & (SEG - 1);
-  const uint32_t wave = logical_block(g.xcd_remap) * WAVES_PER_BLOCK + __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
+  const uint32_t wave = block * WAVES_PER_BLOCK + __builtin_amdgcn_readfirstlane(threadIdx.x / SEG);
   s.seg = wave;
   const uint32_t row = __builtin_amdgcn_readfirstlane(fast_div(wave, g.div_nseg_x));
   const uint32_t sx = __builtin_amdgcn_readfirstlane(wave - row * (uint32_t)g.nseg_x);
@@ -56,6 +56,8 @@ __device__ __forceinline__ SegInfo seg_info(const GridGeom& g) {
   s.c.z = (int)z;
   return s;
 }
+
+__device__ __forceinline__ SegInfo seg_info(const GridGeom& g) { return seg_info(g, logical_block(g.xcd_remap)); }
 
 // Direction tables for a direction index known only at run time (the link
 // phase): velocity components packed two bits per direction, weights by shell.
@@ -317,7 +319,7 @@ __device__ __forceinline__ void patch_links(R (&h)[L::Q], R (*stage)[BLOCK], boo
 // the face layer (see axis_src).
 // ---------------------------------------------------------------------------
 template <class L, int S, bool COMPACT>
-__global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
+__device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   using St = Storage<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
   __shared__ R stage[NV][BLOCK];
   const GridGeom& g = p.g;
   const LinkView& lk = p.lk;
-  const SegInfo si = seg_info(g);
+  const SegInfo si = seg_info(g, block);
   if (si.seg >= g.nseg) return;
   const uint64_t fm = lk.seg_fluid[si.seg];
   if (fm == 0) return;
@@ -451,7 +453,26 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
     }
     for (int k = lb0 + si.lane + 2 * SEG; k < lb1; k += SEG) rebuild(k, lk.lld[k], lq[k], lg ? lg[k] : R(0));
   }
+}
 
+template <class L, int S, bool COMPACT>
+__global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
+  step_body<L, S, COMPACT>(p, logical_block(p.g.xcd_remap));
+}
+
+// Several domains in one persistent launch.  Slot k of the tile table names a
+// block of one domain (domain << TILE_SHIFT | block) or is empty; workgroup b
+// walks the slots b, b + gridDim.x, ...  The host orders the table (see
+// tile_table), so the grid size and the order are launch choices that leave
+// every result unchanged.
+template <class L, int S, bool COMPACT>
+__global__ __launch_bounds__(BLOCK) void step_batch_kernel(const StepParams* __restrict__ tab,
+                                                           const uint32_t* __restrict__ tiles, uint32_t nslots) {
+  for (uint32_t k = blockIdx.x; k < nslots; k += gridDim.x) {
+    const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[k]);
+    if (t != TILE_EMPTY) step_body<L, S, COMPACT>(tab[t >> TILE_SHIFT], t & TILE_MASK);
+    wave_lds_sync();   // the next tile reuses the wave's LDS columns
+  }
 }
 
 // Pre-collision shifted populations of one lane's node (pull + link patch).
@@ -683,26 +704,26 @@ int64_t grid_blocks(const GridGeom& g) {
   return (b + 7) / 8 * 8;   // multiple of the XCD count, see logical_block()
 }
 
-#define LBM_DISPATCH_L(KERNEL, LAT, storage, C, grid, stream, params)                             \
-  do {                                                                                            \
-    switch (storage) {                                                                            \
-      case ST_F64: KERNEL<LAT, ST_F64, C><<<grid, BLOCK, 0, stream>>>(params); break;             \
-      case ST_F32: KERNEL<LAT, ST_F32, C><<<grid, BLOCK, 0, stream>>>(params); break;             \
-      case ST_F16S: KERNEL<LAT, ST_F16S, C><<<grid, BLOCK, 0, stream>>>(params); break;           \
-      default: KERNEL<LAT, ST_BF16S, C><<<grid, BLOCK, 0, stream>>>(params); break;               \
-    }                                                                                             \
+#define LBM_DISPATCH_L(KERNEL, LAT, storage, C, grid, stream, ...)                                             \
+  do {                                                                                                         \
+    switch (storage) {                                                                                         \
+      case ST_F64: KERNEL<LAT, ST_F64, C><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                     \
+      case ST_F32: KERNEL<LAT, ST_F32, C><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                     \
+      case ST_F16S: KERNEL<LAT, ST_F16S, C><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                   \
+      default: KERNEL<LAT, ST_BF16S, C><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                       \
+    }                                                                                                          \
   } while (0)
 
 // lattice x storage x layout
-#define LBM_DISPATCH3(KERNEL, lattice, storage, compact, grid, stream, params)                    \
-  do {                                                                                            \
-    if (lattice == LBM_D2Q9) {                                                                    \
-      if (compact) LBM_DISPATCH_L(KERNEL, D2Q9, storage, true, grid, stream, params);             \
-      else LBM_DISPATCH_L(KERNEL, D2Q9, storage, false, grid, stream, params);                    \
-    } else {                                                                                      \
-      if (compact) LBM_DISPATCH_L(KERNEL, D3Q19, storage, true, grid, stream, params);            \
-      else LBM_DISPATCH_L(KERNEL, D3Q19, storage, false, grid, stream, params);                   \
-    }                                                                                             \
+#define LBM_DISPATCH3(KERNEL, lattice, storage, compact, grid, stream, ...)                                    \
+  do {                                                                                                         \
+    if (lattice == LBM_D2Q9) {                                                                                 \
+      if (compact) LBM_DISPATCH_L(KERNEL, D2Q9, storage, true, grid, stream, __VA_ARGS__);                     \
+      else LBM_DISPATCH_L(KERNEL, D2Q9, storage, false, grid, stream, __VA_ARGS__);                            \
+    } else {                                                                                                   \
+      if (compact) LBM_DISPATCH_L(KERNEL, D3Q19, storage, true, grid, stream, __VA_ARGS__);                    \
+      else LBM_DISPATCH_L(KERNEL, D3Q19, storage, false, grid, stream, __VA_ARGS__);                           \
+    }                                                                                                          \
   } while (0)
 
 // lattice x storage
@@ -727,6 +748,13 @@ int64_t grid_blocks(const GridGeom& g) {
 
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s) {
   LBM_DISPATCH3(step_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_batch(int lattice, int storage, bool compact, const StepParams* tab, const uint32_t* tiles,
+                             uint32_t nslots, uint32_t grid, hipStream_t s) {
+  if (nslots == 0 || grid == 0) return hipSuccess;
+  LBM_DISPATCH3(step_batch_kernel, lattice, storage, compact, dim3(grid), s, tab, tiles, nslots);
   return hipGetLastError();
 }
 

@@ -43,9 +43,9 @@ __device__ __forceinline__ double min_image(double d, int L, int periodic) {
 }
 
 __device__ __forceinline__ void rel(const MovingParams& p, double x, double y, double z, double (&d)[3]) {
-  d[0] = min_image(__dsub_rn(x, p.c[0]), p.g.nx, p.g.perx);
-  d[1] = min_image(__dsub_rn(y, p.c[1]), p.g.ny, p.g.pery);
-  d[2] = min_image(__dsub_rn(z, p.c[2]), p.g.nz, p.g.perz);
+  d[0] = min_image(__dsub_rn(x, p.k.c[0]), p.g.nx, p.g.perx);
+  d[1] = min_image(__dsub_rn(y, p.k.c[1]), p.g.ny, p.g.pery);
+  d[2] = min_image(__dsub_rn(z, p.k.c[2]), p.g.nz, p.g.perz);
 }
 
 __device__ __forceinline__ double norm2(const double (&d)[3]) {
@@ -102,9 +102,7 @@ __device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y
 }
 
 template <class L>
-__global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
-  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave >= p.nreg) return;
+__device__ __forceinline__ void classify_body(const MovingParams& p, int64_t wave) {
   const Site s = region_site(p, wave);
   const GridGeom& g = p.g;
   const bool in = s.x < g.nx;
@@ -124,8 +122,8 @@ __global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
   }
 }
 
-// exclusive prefix sum of n counts into out[0..n] (single workgroup, fixed order)
-__global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int32_t* in, int64_t n, int32_t* out) {
+// exclusive prefix sum of n counts into out[0..n] (one workgroup of 1024, fixed order)
+__device__ __forceinline__ void exclusive_scan_body(const int32_t* in, int64_t n, int32_t* out) {
   __shared__ int32_t part[1024];
   const int t = threadIdx.x;
   const int64_t chunk = (n + 1023) / 1024;
@@ -152,9 +150,7 @@ __global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int32_t* in,
 }
 
 template <class L, typename R>
-__global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
-  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave >= p.nreg) return;
+__device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
   const Site s = region_site(p, wave);
   const bool fluid = (p.seg_fluid[s.seg] >> s.lane) & 1ull;
   const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
@@ -179,7 +175,7 @@ __global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
     double r[3];
     rel(p, xw[0], xw[1], xw[2], r);
     double u0[3], u1[3];
-    const double V[3] = {p.V[0], p.V[1], p.V[2]}, V1[3] = {p.V1[0], p.V1[1], p.V1[2]};
+    const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]}, V1[3] = {p.k.V1[0], p.k.V1[1], p.k.V1[2]};
     body_velocity(p, V, r, u0);
     body_velocity(p, V1, r, u1);
     if (L::D == 2) u0[2] = u1[2] = 0.0;
@@ -199,12 +195,10 @@ __global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
 // fresh nodes (solid at t-1, fluid at t): f = f^eq(rho_bar, u_body(x)), rho_bar the
 // mean density of the neighbours that are fluid at t-1 and t (rho0 if none)
 template <class L, int S>
-__global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
+__device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave) {
   using St = Storage<S>;
   using T = typename St::T;
   using R = typename St::R;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave >= p.nreg) return;
   const Site s = region_site(p, wave);
   const GridGeom& g = p.g;
   const uint64_t fresh = p.seg_fluid[s.seg] & ~p.seg_prev[s.seg];
@@ -239,7 +233,7 @@ __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
   const double rb = cnt > 0 ? tot / cnt : p.rho0;
   double r[3], u[3];
   rel(p, (double)s.x, (double)s.y, (double)s.z, r);
-  const double V[3] = {p.V[0], p.V[1], p.V[2]};
+  const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
   body_velocity(p, V, r, u);
   if (L::D == 2) u[2] = 0.0;
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -252,6 +246,71 @@ __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
     const int sz = wrap(s.z - L::cz(i), g.nz, g.perz);
     St::template store<L>(pop + i * np + slot(sx, sy, sz), R(h), i);
   }
+}
+
+// Single sphere: one wave per region segment.
+template <class L>
+__global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave < p.nreg) classify_body<L>(p, wave);
+}
+
+__global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int32_t* in, int64_t n, int32_t* out) {
+  exclusive_scan_body(in, n, out);
+}
+
+template <class L, typename R>
+__global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave < p.nreg) fill_body<L, R>(p, wave);
+}
+
+template <class L, int S>
+__global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave < p.nreg) refill_body<L, S>(p, wave);
+}
+
+// Batched spheres: the wave table names (sphere, region wave); the kinematics
+// come from row *ctr of the table.
+__device__ __forceinline__ bool batch_wave(const MovingBatch& b, MovingParams& p, int64_t& wave) {
+  const uint32_t gw = blockIdx.x * 4u + threadIdx.x / 64u;
+  if (gw >= b.nwaves) return false;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(b.waves[gw]);
+  p = b.tab[w >> TILE_SHIFT];
+  p.k = b.kin[*b.ctr * b.nkin + p.kin_slot];
+  wave = (int64_t)(w & TILE_MASK);
+  return true;
+}
+
+template <class L>
+__global__ __launch_bounds__(256) void classify_batch_kernel(MovingBatch b) {
+  MovingParams p;
+  int64_t wave;
+  if (batch_wave(b, p, wave)) classify_body<L>(p, wave);
+}
+
+__global__ __launch_bounds__(1024) void exclusive_scan_batch_kernel(MovingBatch b) {
+  const MovingParams& p = b.tab[blockIdx.x];
+  exclusive_scan_body(p.seg_count, p.g.nseg, const_cast<int32_t*>(p.seg_lbase));
+}
+
+template <class L, typename R>
+__global__ __launch_bounds__(256) void fill_batch_kernel(MovingBatch b) {
+  MovingParams p;
+  int64_t wave;
+  if (batch_wave(b, p, wave)) fill_body<L, R>(p, wave);
+}
+
+template <class L, int S>
+__global__ __launch_bounds__(256) void refill_batch_kernel(MovingBatch b) {
+  MovingParams p;
+  int64_t wave;
+  if (batch_wave(b, p, wave)) refill_body<L, S>(p, wave);
+}
+
+__global__ void advance_kernel(int64_t* ctr) {
+  if (threadIdx.x == 0) ctr[0] = ctr[0] + 1;
 }
 
 }  // namespace
@@ -298,6 +357,35 @@ hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p,
     LBM_REFILL(D3Q19)
   }
 #undef LBM_REFILL
+  return hipGetLastError();
+}
+
+hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s) {
+  if (b.nbox == 0) return hipSuccess;
+  const dim3 grid((b.nwaves + 3) / 4);
+  const bool f64 = storage == ST_F64;
+#define LBM_MOVING_BATCH(LAT)                                                                  \
+  classify_batch_kernel<LAT><<<grid, 256, 0, s>>>(b);                                          \
+  exclusive_scan_batch_kernel<<<b.nbox, 1024, 0, s>>>(b);                                      \
+  if (f64) fill_batch_kernel<LAT, double><<<grid, 256, 0, s>>>(b);                             \
+  else fill_batch_kernel<LAT, float><<<grid, 256, 0, s>>>(b);                                  \
+  switch (storage) {                                                                           \
+    case ST_F64: refill_batch_kernel<LAT, ST_F64><<<grid, 256, 0, s>>>(b); break;              \
+    case ST_F32: refill_batch_kernel<LAT, ST_F32><<<grid, 256, 0, s>>>(b); break;              \
+    case ST_F16S: refill_batch_kernel<LAT, ST_F16S><<<grid, 256, 0, s>>>(b); break;            \
+    default: refill_batch_kernel<LAT, ST_BF16S><<<grid, 256, 0, s>>>(b); break;                \
+  }
+  if (lattice == LBM_D2Q9) {
+    LBM_MOVING_BATCH(D2Q9)
+  } else {
+    LBM_MOVING_BATCH(D3Q19)
+  }
+#undef LBM_MOVING_BATCH
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t* ctr, hipStream_t s) {
+  advance_kernel<<<1, 64, 0, s>>>(ctr);
   return hipGetLastError();
 }
 

@@ -64,3 +64,21 @@ def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), varian
     d = B.Domain("D3Q19", n, n, n, mask, tau, storage=storage, force=force, layout=layout)
     d.set_boundary_links(links, variant=variant)
     return d, mask, links
+
+
+def request_domain(req, storage="f16s", variant="FQ", layout="compact"):
+    """One served request (``synth.request_stream``): circular Couette L x L or
+    cylinder channel 2L x L."""
+    if req["kind"] == "couette":
+        return couette_domain(req, storage=storage, variant=variant, layout=layout)
+    return channel_domain(req, storage=storage, variant=variant, layout=layout)
+
+
+def moving_box_domain(box, storage="bf16s", variant="FQ"):
+    """One periodic box with a sphere in prescribed motion (``synth.moving_boxes``)."""
+    n = (box["nx"], box["ny"], box["nz"])
+    d = B.Domain("D3Q19", *n, np.ones(n[0] * n[1] * n[2], np.uint8), box["tau"], storage=storage,
+                 rho0=box.get("rho0", 1.0), layout="dense")
+    d.set_moving_sphere(box["x0"], box["radius"], box["amplitude"], box["period"], box["direction"], box["omega"],
+                        variant=variant)
+    return d

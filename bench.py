@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +44,15 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the measurement, run one plain device copy of this size (for counter scaling)")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-batch section")
+    ap.add_argument("--served-requests", type=int, default=256)
+    ap.add_argument("--served-steps", type=int, default=5000)
+    ap.add_argument("--served-budget-mib", type=int, default=1024)
+    ap.add_argument("--served-load", type=float, default=1.0,
+                    help="arrival rate as a multiple of the measured plain FP32 service rate")
+    ap.add_argument("--no-moving", action="store_true", help="skip the batched moving-boxes section")
+    ap.add_argument("--moving-boxes", type=int, default=32)
+    ap.add_argument("--moving-steps", type=int, default=4000)
     return ap.parse_args()
 
 
@@ -126,6 +139,139 @@ def cpu_baseline(name, seconds):
             ctx.__exit__(None, None, None)
 
 
+def served_section(a, log):
+    """Served D2Q9 requests (circular Couette L x L and cylinder channel 2L x L,
+    L ~ U{64..1024}, Poisson arrivals): continuously batched FP16-shifted form
+    against the plain FP32 one-request-at-a-time form on the same arrivals."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2009_04604_amd import serve
+    reqs = synth.request_stream(n_requests=a.served_requests, rate=1.0, steps=a.served_steps)
+    sample = sorted(set(range(0, len(reqs), max(1, len(reqs) // 16))))
+    # plain service rate from a sample of requests run alone in FP32
+    log(f"served: {len(reqs)} requests; plain service-time sample")
+    ex = serve.GpuExecutor(storage="f32")
+    t_serv = []
+    for k in sample[:8]:
+        q = dict(reqs[k])
+        t0 = time.perf_counter()
+        h = ex.admit(ex.prepare(q))
+        ex.step_alone(h, q["steps"])
+        ex.sync()
+        ex.finish(h, q)
+        ex.free(h)
+        t_serv.append(time.perf_counter() - t0)
+    ex.close()
+    mu = 1.0 / float(np.mean(t_serv))
+    lam = a.served_load * mu
+    for r in reqs:
+        r["arrival"] = r["arrival"] / lam          # unit-rate Poisson times scaled to rate lam
+    log(f"served: plain sample service {np.mean(t_serv):.4f} s/request, arrival rate {lam:.2f}/s")
+    budget = a.served_budget_mib * 2**20
+    ids = [reqs[k]["id"] for k in sample]
+    exs = serve.GpuExecutor(storage="f16s", keep_fields=ids, autotune=True)
+    srv = serve.Server(exs, hbm_budget=budget, chunk=100)
+    log("served: batched run")
+    served = srv.run(reqs)
+    exs.close()
+    log("served: done")
+    exp = serve.GpuExecutor(storage="f32", keep_fields=ids)
+    plain = serve.run_plain(exp, reqs)
+    exp.close()
+    log("served: plain done")
+    # velocity error of each sampled request against the same request in FP64
+    log("served: FP64 references")
+    ref = serve.GpuExecutor(storage="f64", keep_fields=ids)
+    e_s, e_p = [], []
+    for k in sample:
+        q = reqs[k]
+        h = ref.admit(ref.prepare(q))
+        ref.step_alone(h, q["steps"])
+        u = ref.finish(h, q)["u"]
+        ref.free(h)
+        nrm = np.linalg.norm(u)
+        e_s.append(float(np.linalg.norm(served[k]["result"]["u"] - u) / nrm))
+        e_p.append(float(np.linalg.norm(plain[k]["result"]["u"] - u) / nrm))
+    ref.close()
+    torch.cuda.synchronize()
+    ss, sp = serve.summarize(served), serve.summarize(plain)
+    nodes = sum(r["nx"] * r["ny"] for r in reqs)
+    return {
+        "workload": f"{len(reqs)} D2Q9 requests (circular Couette LxL / cylinder channel 2LxL, L~U{{64..1024}}), "
+                    f"{a.served_steps} steps each, Poisson arrivals",
+        "arrival_rate_per_s": round(lam, 3), "load_vs_plain_rate": a.served_load, "hbm_budget_bytes": budget,
+        "lattice_nodes_total": nodes,
+        "served": {"storage": "f16s (f - w, FP32 compute, FP64 reductions)", "solves_per_s": round(ss["solves_per_s"], 3),
+                   "p50_s": round(ss["p50_s"], 4), "p99_s": round(ss["p99_s"], 4), "makespan_s": round(ss["makespan_s"], 3),
+                   "peak_resident": srv.peak_active, "peak_bytes": srv.peak_bytes, "chunks": srv.chunks,
+                   "E_vs_f64_max": max(e_s), "E_vs_f64_median": float(np.median(e_s))},
+        "plain": {"storage": "f32, one request at a time (FIFO)", "solves_per_s": round(sp["solves_per_s"], 3),
+                  "p50_s": round(sp["p50_s"], 4), "p99_s": round(sp["p99_s"], 4), "makespan_s": round(sp["makespan_s"], 3),
+                  "E_vs_f64_max": max(e_p), "E_vs_f64_median": float(np.median(e_p))},
+        "speedup_solves_per_s": round(ss["solves_per_s"] / sp["solves_per_s"], 3),
+        "p99_ratio_plain_over_served": round(sp["p99_s"] / ss["p99_s"], 3),
+        "error_sample": f"{len(sample)} requests (every {max(1, len(reqs) // 16)}th) against the FP64 GPU path",
+    }
+
+
+def moving_section(a, log):
+    """Batched D3Q19 BF16 periodic boxes, each with a sphere in prescribed
+    motion, links rebuilt on the device every step."""
+    import torch
+    import synth
+    from paper_2009_04604_amd import binding as B, workloads as W
+    boxes = synth.moving_boxes(n_boxes=a.moving_boxes, steps=a.moving_steps)
+    log(f"moving: {len(boxes)} boxes, building")
+    ds = [W.moving_box_domain(b, storage="bf16s") for b in boxes]
+    bt = B.Batch()
+    log("moving: autotune")
+    choice = bt.autotune(ds, steps_per_candidate=4)
+    log(f"moving: choice {choice}; timed run of {a.moving_steps} steps")
+    torch.cuda.synchronize()
+    nodes = sum(b["nx"] * b["ny"] * b["nz"] for b in boxes)
+    fluid0 = sum(d.info()["n_fluid"] for d in ds)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    bt.step(ds, a.moving_steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    fluid1 = sum(d.info()["n_fluid"] for d in ds)
+    links = sum(d.info()["n_links"] for d in ds)
+    unstable = False
+    for d in ds:
+        unstable = unstable or d.macros(fields=False)[3]
+    log("moving: batched done")
+    # the same boxes one after another with lbm_step, a few steps each
+    k = 50
+    log("moving: one box at a time")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for d in ds:
+        d.step(k)
+    torch.cuda.synchronize()
+    one = (time.perf_counter() - t1) / k
+    bt.close()
+    for d in ds:
+        d.close()
+    fl = 0.5 * (fluid0 + fluid1)
+    mlups = fl * a.moving_steps / wall / 1e6
+    achieved = 2 * 19 * 2 * fl * a.moving_steps / gpu_s / 1e9
+    return {
+        "workload": f"{len(boxes)} periodic D3Q19 boxes, side U{{96..192}}, moving sphere r U[10,16], BF16 shifted, "
+                    f"{a.moving_steps} steps, links rebuilt on the GPU every step",
+        "lattice_nodes": nodes, "fluid_nodes_mean": int(fl), "cut_links_final": links, "unstable": bool(unstable),
+        "mlups": round(mlups, 1), "ms_per_step": round(wall * 1e3 / a.moving_steps, 4),
+        "boxes_per_s": round(len(boxes) * a.moving_steps / wall / a.moving_steps, 3),
+        "hbm_frac_population_bytes": round(achieved / HBM_PEAK_GBS, 4), "achieved_GBps": round(achieved, 1),
+        "autotune_choice": choice, "one_at_a_time_ms_per_step": round(one * 1e3, 4),
+        "batched_speedup_vs_one_at_a_time": round(one / (wall / a.moving_steps), 3),
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -136,7 +282,9 @@ def main():
     from paper_2009_04604_amd import binding as B
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    log(f"main: building {a.workload} ({a.storage}, {a.layout})")
     d, cfg = build_workload(a.workload, a.storage, a.layout)
+    log("main: timed steps")
     info = d.info()
     nfl = info["n_fluid"]
     Q = info["q"]
@@ -176,6 +324,11 @@ def main():
         "data": "synthetic", "config": cfg, "roofline": roof,
     }
     d.close()
+
+    if not a.no_moving:
+        out["moving_batch"] = moving_section(a, log)
+    if not a.no_served:
+        out["served_batch"] = served_section(a, log)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,6 +22,8 @@ using namespace lbm;
 
 namespace lbm {
 thread_local std::string g_err;
+std::atomic<uint64_t> g_uid{1};
+uint64_t next_uid() { return g_uid.fetch_add(1); }
 int set_error(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -403,15 +406,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   dm->red_blocks = grid_blocks(g);
   if (int e = dalloc(dm->partials, dm->red_blocks * NPART * 8)) return cleanup(e);
   if (int e = dalloc(dm->sums, NPART * 8)) return cleanup(e);
-  if (int e = dalloc(dm->uprev, N * L.D * 8)) return cleanup(e);
-  {
-    std::vector<double> up((size_t)N * L.D, 0.0);
-    for (int64_t n = 0; n < N; ++n)
-      if (dm->mask[n])
-        for (int a = 0; a < L.D; ++a) up[n * L.D + a] = d.u0[a] + 0.5 * d.force[a] / d.rho0;
-    he = hipMemcpy(dm->uprev, up.data(), up.size() * 8, hipMemcpyHostToDevice);
-    if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
-  }
+  dm->uprev = nullptr;   // the residual's snapshot is allocated by the first lbm_macros call
 
   dm->cur = 0;
   he = import_state(dm, nullptr);
@@ -419,6 +414,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   dm->cur = 0;
   int bad_dir = 0;
   dm->links_ok = first_uncovered(dm, {}, &bad_dir) < 0;
+  dm->uid = next_uid();
   *out = dm;
   clear_error();
   return LBM_OK;
@@ -567,6 +563,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   d->variant = variant;
   d->q_cut = q_cutoff;
   d->links_ok = true;
+  d->uid = next_uid();
   clear_error();
   return LBM_OK;
 }
@@ -645,6 +642,7 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   HIP_TRY(import_state(d, nullptr));
   HIP_TRY(hipStreamSynchronize(d->stream));
   d->links_ok = true;
+  d->uid = next_uid();
   clear_error();
   return LBM_OK;
 }
@@ -670,6 +668,15 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
 int lbm_macros(lbm_domain d, double* rho, double* u, double* sums) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   const int64_t N = d->N;
+  if (!d->uprev) {   // first call: the previous field is the initial one, u0 + F / (2 rho0) on fluid nodes
+    if (int e = dalloc(d->uprev, N * d->D * 8)) return e;
+    std::vector<double> up((size_t)N * d->D, 0.0);
+    for (int64_t n = 0; n < N; ++n)
+      if (d->mask[n])
+        for (int a = 0; a < d->D; ++a) up[n * d->D + a] = d->desc.u0[a] + 0.5 * d->desc.force[a] / d->desc.rho0;
+    HIP_TRY(hipMemcpyAsync(d->uprev, up.data(), up.size() * 8, hipMemcpyHostToDevice, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+  }
   if (rho && !d->rho_tmp)
     if (int e = dalloc(d->rho_tmp, N * 8)) return e;
   if (u && !d->u_tmp)
@@ -732,6 +739,7 @@ int lbm_set_state(lbm_domain d, const double* f) {
 int lbm_set_stream(lbm_domain d, void* stream) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   d->stream = static_cast<hipStream_t>(stream);
+  d->uid = next_uid();
   d->desc.stream = stream;
   return LBM_OK;
 }

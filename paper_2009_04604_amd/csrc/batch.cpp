@@ -78,6 +78,7 @@ struct lbm_batch_s {
   std::map<std::tuple<int, int, int, int>, double> tuned_us;
   // composition
   std::vector<lbm_domain> members;
+  std::vector<uint64_t> member_uid;  // identity of each member when the tables were built
   std::vector<int> cur_up;           // members' buffer parity the tables were written for
   std::vector<Group> groups;
   std::vector<Choice> group_choice;
@@ -320,6 +321,7 @@ hipError_t enqueue_step(lbm_batch_s* b, int p, hipStream_t s) {
 
 int capture(lbm_batch_s* b) {
   if (b->exec) {
+    BHIP(hipStreamSynchronize(b->stream));   // no replay of the old graph in flight
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
   }
@@ -355,19 +357,25 @@ void release_groups(lbm_batch_s* b) {
   }
   b->groups.clear();
   b->cur_up.clear();
+  b->members.clear();
+  b->member_uid.clear();
 }
 
 // Set the membership: group the domains, pick each group's launch choice and
 // write the tables when anything changed.
 int prepare(lbm_batch_s* b, const lbm_domain* ds, int32_t n) {
-  bool same = (int32_t)b->members.size() == n;
-  for (int32_t k = 0; same && k < n; ++k) same = b->members[k] == ds[k];
+  // a domain is the same member only if both its address and its uid match:
+  // a new domain can be allocated at a freed one's address
+  bool same = (int32_t)b->members.size() == n && b->member_uid.size() == b->members.size();
+  for (int32_t k = 0; same && k < n; ++k) same = b->members[k] == ds[k] && b->member_uid[k] == ds[k]->uid;
   if (!same) {
     if (!b->groups.empty()) {   // pending launches may still read the old tables
       BHIP(hipStreamSynchronize(b->stream));
       release_groups(b);
     }
     b->members.assign(ds, ds + n);
+    b->member_uid.clear();
+    for (int32_t k = 0; k < n; ++k) b->member_uid.push_back(ds[k]->uid);
     for (int32_t k = 0; k < n; ++k) {
       const lbm_domain_s* d = ds[k];
       Group* g = nullptr;

@@ -203,6 +203,7 @@ hipError_t launch_advance(int64_t* ctr, hipStream_t s);
 
 struct lbm_domain_s {
   lbm_domain_desc desc;
+  uint64_t uid;                  // unique per domain, renewed when its device layout changes
   int Q, D;
   lbm::GridGeom g;
   int64_t N;                     // nx * ny * nz
@@ -252,4 +253,7 @@ namespace lbm {
 StepParams step_params(const lbm_domain_s* d, int cur);
 MovingParams moving_params(const lbm_domain_s* d, int cur);
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t);
+// Identity for caches of kernel parameters (a freed domain's address can be
+// reused by a new one; links or a stream set anew also change the uid).
+uint64_t next_uid();
 }  // namespace lbm

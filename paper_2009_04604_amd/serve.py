@@ -1,0 +1,288 @@
+"""Serving loop: continuous batching of simulation requests on one GPU.
+
+A request is a lattice-Boltzmann run (geometry, tau, step count).  Requests
+arrive over time; each is admitted, in arrival order, as soon as its device
+footprint fits under a configured HBM budget beside the requests already
+resident.  All resident requests advance together in chunks of steps through
+one batched launch per step (``lbm_batch_step``: one multi-domain kernel per
+lattice/storage group, replayed from a HIP graph), so requests that arrive
+while others run join the running set at the next chunk boundary, and finished
+ones leave it and free their memory.  The chunk is cut at the nearest
+completion, so every request runs exactly its own step count.  While a chunk
+runs on the device the host builds the geometry of newly arrived requests.
+
+``Server`` holds only the scheduling; an executor object does the work:
+
+    prepare(req)          -> job payload with .footprint (bytes); host only
+    admit(payload)        -> resident handle (allocates device memory)
+    step(handles, n)      -> launch n steps of every handle (asynchronous)
+    sync()                -> wait for launched work
+    finish(handle, req)   -> result of a finished request (reads it back)
+    free(handle)
+
+``GpuExecutor`` is the executor of the product path; tests substitute a fake
+one with a fake clock.  ``run_plain`` is the reference form: one request at a
+time, in arrival order, stepped with lbm_step.
+"""
+import collections
+import time
+
+import numpy as np
+
+
+def percentile(xs, p):
+    """Nearest-rank percentile (p in [0, 100]) of a non-empty list."""
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = max(0, min(len(xs) - 1, int(np.ceil(p / 100.0 * len(xs))) - 1))
+    return float(xs[k])
+
+
+class Job:
+    __slots__ = ("req", "payload", "handle", "footprint", "arrival", "admitted", "finished", "steps_left",
+                 "result", "error")
+
+    def __init__(self, req):
+        self.req = req
+        self.payload = None
+        self.handle = None
+        self.footprint = 0
+        self.arrival = float(req["arrival"])
+        self.admitted = None
+        self.finished = None
+        self.steps_left = int(req["steps"])
+        self.result = None
+        self.error = None
+
+    def record(self):
+        tts = None if self.finished is None else self.finished - self.arrival
+        return {"id": self.req["id"], "arrival": self.arrival, "admitted": self.admitted, "finished": self.finished,
+                "time_to_solution": tts, "footprint": self.footprint, "steps": int(self.req["steps"]),
+                "result": self.result, "error": self.error}
+
+
+class Server:
+    """Continuous-batching scheduler (see the module docstring).
+
+    hbm_budget  bytes of device memory the resident requests may hold together
+    chunk       most steps launched between two scheduling points
+    max_active  optional cap on the number of resident requests
+    clock/sleep wall clock and wait (injectable for tests)
+    trace       optional callable(event, time, info) for every scheduling event
+    """
+
+    def __init__(self, executor, hbm_budget, chunk=100, max_active=None, clock=time.perf_counter, sleep=time.sleep,
+                 trace=None):
+        if hbm_budget <= 0 or chunk < 1:
+            raise ValueError("hbm_budget and chunk must be positive")
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.chunk = int(chunk)
+        self.max_active = max_active
+        self.clock = clock
+        self.sleep = sleep
+        self.trace = trace
+        self.peak_bytes = 0
+        self.peak_active = 0
+        self.chunks = 0
+
+    def _event(self, what, now, **info):
+        if self.trace:
+            self.trace(what, now, info)
+
+    def run(self, requests):
+        """Serve the requests (arrival times in seconds from the start of the
+        call); returns one record per request, in request order."""
+        jobs = [Job(r) for r in requests]
+        pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.req["id"])))
+        waiting = collections.deque()          # arrived, geometry built, not admitted (FIFO)
+        active = []
+        used = 0
+        t0 = self.clock()
+
+        def now():
+            return self.clock() - t0
+
+        def take_arrivals():
+            while pending and pending[0].arrival <= now():
+                j = pending.popleft()
+                j.payload = self.ex.prepare(j.req)
+                j.footprint = int(j.payload.footprint)
+                waiting.append(j)
+                self._event("arrive", now(), id=j.req["id"], footprint=j.footprint)
+
+        while pending or waiting or active:
+            take_arrivals()
+            # admission: arrival order, as long as the head fits
+            while waiting:
+                j = waiting[0]
+                if j.footprint > self.budget:
+                    waiting.popleft()
+                    j.error = f"footprint {j.footprint} B exceeds the HBM budget {self.budget} B"
+                    j.finished = now()
+                    self._event("reject", now(), id=j.req["id"])
+                    continue
+                if used + j.footprint > self.budget:
+                    break
+                if self.max_active is not None and len(active) >= self.max_active:
+                    break
+                waiting.popleft()
+                j.handle = self.ex.admit(j.payload)
+                j.payload = None
+                j.admitted = now()
+                used += j.footprint
+                active.append(j)
+                self._event("admit", now(), id=j.req["id"], used=used)
+            self.peak_bytes = max(self.peak_bytes, used)
+            self.peak_active = max(self.peak_active, len(active))
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival - now()))
+                continue
+            n = min(self.chunk, min(j.steps_left for j in active))
+            self.ex.step([j.handle for j in active], n)
+            self.chunks += 1
+            take_arrivals()                     # host work overlaps the chunk on the device
+            self.ex.sync()
+            done = []
+            for j in active:
+                j.steps_left -= n
+                if j.steps_left == 0:
+                    done.append(j)
+            for j in done:
+                j.result = self.ex.finish(j.handle, j.req)
+                self.ex.free(j.handle)
+                j.handle = None
+                used -= j.footprint
+                j.finished = now()
+                self._event("finish", now(), id=j.req["id"], used=used)
+            active = [j for j in active if j.steps_left > 0]
+        return [j.record() for j in jobs]
+
+
+def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep):
+    """Reference form: one request at a time in arrival order (FIFO), each
+    stepped alone to completion."""
+    jobs = [Job(r) for r in requests]
+    t0 = clock()
+    for j in sorted(jobs, key=lambda j: (j.arrival, j.req["id"])):
+        wait = j.arrival - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        payload = executor.prepare(j.req)
+        j.footprint = int(payload.footprint)
+        h = executor.admit(payload)
+        j.admitted = clock() - t0
+        executor.step_alone(h, j.steps_left)
+        executor.sync()
+        j.result = executor.finish(h, j.req)
+        executor.free(h)
+        j.steps_left = 0
+        j.finished = clock() - t0
+    return [j.record() for j in jobs]
+
+
+def summarize(records, makespan=None):
+    """solves/s over the makespan (first arrival to last completion) and
+    p50 / p99 time to solution."""
+    ok = [r for r in records if r["error"] is None and r["finished"] is not None]
+    tts = [r["time_to_solution"] for r in ok]
+    if makespan is None:
+        first = min(r["arrival"] for r in records)
+        last = max(r["finished"] for r in ok)
+        makespan = last - first
+    return {"requests": len(records), "solved": len(ok), "makespan_s": makespan,
+            "solves_per_s": len(ok) / makespan if makespan > 0 else float("inf"),
+            "p50_s": percentile(tts, 50), "p99_s": percentile(tts, 99), "max_s": max(tts) if tts else float("nan")}
+
+
+# ---------------------------------------------------------------------------
+# Executor of the product path
+# ---------------------------------------------------------------------------
+class _Prepared:
+    __slots__ = ("req", "mask", "links", "footprint")
+
+
+class GpuExecutor:
+    """Requests as lbm domains on the current torch device and stream.
+
+    storage      population storage of every request ("f16s" for the served
+                 form, "f32" for the plain one)
+    keep_fields  ids of requests whose final velocity field is returned
+    autotune     run the batch autotuner once per shape class
+    """
+
+    def __init__(self, storage="f16s", keep_fields=(), autotune=False, graph=True):
+        from . import binding as B
+        self.B = B
+        self.storage = storage
+        self.keep = set(keep_fields)
+        self.batch = B.Batch()
+        self.batch.set_option("graph", int(bool(graph)))
+        self.batch.set_option("autotune", int(bool(autotune)))
+
+    def footprint(self, req, mask, n_links):
+        """Device bytes a request holds while resident, plus what reading its
+        result back allocates: both population buffers, the segment and link
+        records, the reduction partials, and at the end the residual snapshot and
+        the velocity field (8 bytes per node and component each)."""
+        B = self.B
+        nx, ny = int(req["nx"]), int(req["ny"])
+        periodic = (True, True, True) if req["kind"] == "couette" else (False, False, True)
+        desc = B.make_desc("D2Q9", nx, ny, 1, req["tau"], self.storage, periodic,
+                           outlet_face=None if req["kind"] == "couette" else "+x")
+        pop = B.lbm_arena_bytes(desc, mask)
+        rs = 8 if self.storage == "f64" else 4
+        nseg = ny * ((nx + 63) // 64)
+        links = n_links * (2 + 4 + 4 * rs) + nseg * 24 + 8 * 8 * (nseg // 4 + 8)
+        fields = nx * ny * 2 * 8 * 2
+        return int(pop + links + fields)
+
+    def prepare(self, req):
+        from . import workloads as W
+        p = _Prepared()
+        p.req = req
+        if req["kind"] == "couette":
+            p.mask, p.links = W.annulus_geometry(req)
+        else:
+            p.mask, p.links = W.channel_geometry(req)
+        p.footprint = self.footprint(req, p.mask, len(p.links["node"]))
+        return p
+
+    def admit(self, p):
+        B = self.B
+        req = p.req
+        if req["kind"] == "couette":
+            d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage)
+        else:
+            d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage,
+                         periodic=(False, False, True), outlet_face="+x")
+        d.set_boundary_links(p.links)
+        d._req_mask = p.mask
+        return d
+
+    def step(self, handles, n):
+        self.batch.step(handles, n)
+
+    def step_alone(self, h, n):
+        h.step(n)
+
+    def sync(self):
+        import torch
+        torch.cuda.synchronize()
+
+    def finish(self, h, req):
+        keep = req["id"] in self.keep
+        rho, u, sums, unstable = h.macros(fields=keep)
+        out = {"mass": float(sums[0]), "momentum": [float(x) for x in sums[1:3]], "unstable": bool(unstable)}
+        if keep:
+            fl = np.asarray(h._req_mask, bool).reshape(-1)
+            out["u"] = u[fl].astype(np.float64)
+        return out
+
+    def free(self, h):
+        h.close()
+
+    def close(self):
+        self.batch.close()

@@ -152,3 +152,37 @@ def test_batch_validation(gpu_lib):
     b.close()
     for d in (d1, d2, nolinks):
         d.close()
+
+
+def test_member_replaced_by_new_domain(gpu_lib):
+    """A batch whose member is freed and replaced by a new domain (which the
+    allocator may place at the freed one's address) must rebuild its tables."""
+    from paper_2009_04604_amd import workloads as W
+    B = gpu_lib
+    _say("case batch member replaced")
+    reqs = synth.request_stream(n_requests=4, l_min=64, l_max=96, seed=21)
+    mk = [lambda r=r: W.request_domain(r, storage="f32")[0] for r in reqs]
+    b = B.Batch()
+    a0 = mk[0]()
+    b.step([a0], 6)
+    a0.close()
+    a1 = mk[1]()                 # alone after a lone member was freed
+    t1 = mk[1]()
+    b.step([a1], 6)
+    t1.step(6)
+    _same_state([t1], [a1])
+    x = mk[2]()
+    tx = mk[2]()
+    b.step([x, a1], 4)
+    tx.step(4)
+    t1.step(4)
+    a1.close()
+    a3 = mk[3]()                 # same position, possibly the same address
+    t3 = mk[3]()
+    b.step([x, a3], 5)
+    tx.step(5)
+    t3.step(5)
+    _same_state([tx, t3], [x, a3])
+    b.close()
+    for d in (t1, x, tx, a3, t3):
+        d.close()

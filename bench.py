@@ -170,8 +170,8 @@ def served_section(a, log):
     log(f"served: plain sample service {np.mean(t_serv):.4f} s/request, arrival rate {lam:.2f}/s")
     budget = a.served_budget_mib * 2**20
     ids = [reqs[k]["id"] for k in sample]
-    exs = serve.GpuExecutor(storage="f16s", keep_fields=ids, autotune=True)
-    srv = serve.Server(exs, hbm_budget=budget, chunk=100)
+    exs = serve.GpuExecutor(storage="f16s", keep_fields=ids)
+    srv = serve.Server(exs, hbm_budget=budget, chunk=100, prepare_workers=4)
     log("served: batched run")
     served = srv.run(reqs)
     exs.close()
@@ -205,6 +205,7 @@ def served_section(a, log):
         "served": {"storage": "f16s (f - w, FP32 compute, FP64 reductions)", "solves_per_s": round(ss["solves_per_s"], 3),
                    "p50_s": round(ss["p50_s"], 4), "p99_s": round(ss["p99_s"], 4), "makespan_s": round(ss["makespan_s"], 3),
                    "peak_resident": srv.peak_active, "peak_bytes": srv.peak_bytes, "chunks": srv.chunks,
+                   "host_phase_s": {k: round(v, 3) for k, v in sorted(srv.phase.items())},
                    "E_vs_f64_max": max(e_s), "E_vs_f64_median": float(np.median(e_s))},
         "plain": {"storage": "f32, one request at a time (FIFO)", "solves_per_s": round(sp["solves_per_s"], 3),
                   "p50_s": round(sp["p50_s"], 4), "p99_s": round(sp["p99_s"], 4), "makespan_s": round(sp["makespan_s"], 3),

@@ -91,11 +91,10 @@ bool pull_source(const lbm_domain_s* d, const int c[3], int x, int y, int z, int
   const int p[3] = {x, y, z};
   bool inside = true;
   for (int a = 0; a < 3; ++a) {
-    int v = p[a] - c[a];
-    if (per[a]) {
-      v = (v % n[a] + n[a]) % n[a];
-    } else if (v < 0 || v >= n[a]) {
-      inside = false;
+    int v = p[a] - c[a];   // |c| <= 1: one wrap at most
+    if (v < 0 || v >= n[a]) {
+      if (per[a]) v += v < 0 ? n[a] : -n[a];
+      else inside = false;
     }
     s[a] = v;
   }
@@ -185,7 +184,7 @@ MovingParams moving_params(const lbm_domain_s* d, int cur) {
   mp.seg_fluid = d->seg_fluid;
   mp.seg_prev = d->seg_prev;
   mp.seg_bnd = d->seg_bnd;
-  mp.seg_count = d->seg_count;
+  mp.reg_count = d->reg_count;
   mp.seg_lbase = d->seg_lbase;
   mp.lld = d->lld;
   mp.lq = d->lq;
@@ -231,7 +230,7 @@ hipError_t rebuild_moving(lbm_domain_s* d, int64_t t, bool refill) {
   MovingParams mp = moving_params(d, d->cur);
   mp.k = moving_kin(d, t);
   hipError_t e = launch_moving_classify(d->desc.lattice, mp, d->stream);
-  if (e == hipSuccess) e = launch_exclusive_scan(d->seg_count, d->g.nseg, d->seg_lbase, d->stream);
+  if (e == hipSuccess) e = launch_region_scan(mp, d->stream);
   if (e == hipSuccess) e = launch_moving_fill(d->desc.lattice, d->desc.storage, mp, d->stream);
   if (e == hipSuccess && refill) e = launch_moving_refill(d->desc.lattice, d->desc.storage, mp, d->stream);
   return e;
@@ -517,12 +516,16 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
       }
     }
   }
-  // the current state (pulled with the old links) survives the replacement
+  // the current state (pulled with the old links) survives the replacement; a
+  // domain still in its initial state is simply initialised again
+  const bool initial = d->steps == 0 && !d->state_set;
   double* fstate = nullptr;
-  if (int e = dalloc(fstate, (size_t)N * d->Q * 8)) return e;
-  if (hipError_t he = export_state(d, fstate); he != hipSuccess) {
-    (void)hipFree(fstate);
-    return fail(LBM_EDEVICE, std::string("export: ") + hipGetErrorString(he));
+  if (!initial) {
+    if (int e = dalloc(fstate, (size_t)N * d->Q * 8)) return e;
+    if (hipError_t he = export_state(d, fstate); he != hipSuccess) {
+      (void)hipFree(fstate);
+      return fail(LBM_EDEVICE, std::string("export: ") + hipGetErrorString(he));
+    }
   }
   // upload (replace previous arrays)
   HIP_TRY(hipStreamSynchronize(d->stream));
@@ -557,7 +560,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
     return LBM_OK;
   };
   const int code = up();
-  (void)hipFree(fstate);
+  if (fstate) (void)hipFree(fstate);
   if (code != LBM_OK) return code;
   d->nl = n_links;
   d->variant = variant;
@@ -620,13 +623,13 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   d->link_cap = d->nreg * SEG * (d->Q - 1);
   if (int e = dalloc(d->reg_seg, reg.size() * 4)) return e;
   if (int e = dalloc(d->seg_prev, g.nseg * 8)) return e;
-  if (int e = dalloc(d->seg_count, g.nseg * 4)) return e;
+  if (int e = dalloc(d->reg_count, reg.size() * 4)) return e;
   if (int e = dalloc(d->lld, d->link_cap * 2)) return e;
   if (int e = dalloc(d->lq, d->link_cap * rs)) return e;
   if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
   HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
-  HIP_TRY(hipMemset(d->seg_count, 0, g.nseg * 4));
+  HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));
   for (int a = 0; a < 3; ++a) {
     d->mv_x0[a] = x0[a];
     d->mv_dir[a] = direction[a];
@@ -730,6 +733,7 @@ int lbm_set_state(lbm_domain d, const double* f) {
   if (int e = dalloc(tmp, bytes)) return e;
   hipError_t e = hipMemcpyAsync(tmp, f, bytes, hipMemcpyHostToDevice, d->stream);
   if (e == hipSuccess) e = import_state(d, tmp);
+  d->state_set = true;
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
@@ -799,7 +803,7 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->uprev);
   dfree(d->reg_seg);
   dfree(d->seg_prev);
-  dfree(d->seg_count);
+  dfree(d->reg_count);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

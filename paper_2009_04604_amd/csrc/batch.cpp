@@ -3,8 +3,8 @@
 // persistent launch of the multi-domain step kernel, which walks a tile table
 // naming (domain, block of that domain); moving spheres of the group are then
 // rebuilt by batched kernels that read their kinematics from a device table
-// indexed by a device step counter.  The launches of two consecutive steps are
-// captured once into a HIP graph and replayed; the tables live in device
+// indexed by a device step counter.  The launches of two consecutive steps (and
+// of sixteen) are captured once into HIP graphs and replayed; the tables live in device
 // memory, so a new state parity or new kinematics only need new table
 // contents, not a new graph.  The arithmetic per node is the single-domain
 // kernel's, so results are bit-identical to lbm_step for any launch choice.
@@ -42,6 +42,7 @@ int bfail(int code, const std::string& msg) { return set_error(code, msg); }
   } while (0)
 
 constexpr int KIN_ROWS = 256;        // steps of kinematics uploaded at a time
+constexpr int LONG_PAIRS = 8;        // step pairs in the long graph (16 steps per replay)
 constexpr int MAX_GROUP_DOMAINS = 1 << (32 - TILE_SHIFT);
 
 struct Choice {
@@ -89,8 +90,9 @@ struct lbm_batch_s {
   size_t stage_cap = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
-  // graph of a step pair
+  // graphs of one step pair and of LONG_PAIRS pairs
   hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec_long = nullptr;
   std::vector<int64_t> sig;
   Choice last{-1, -1};
   double last_us = 0.0;
@@ -319,34 +321,50 @@ hipError_t enqueue_step(lbm_batch_s* b, int p, hipStream_t s) {
   return hipSuccess;
 }
 
-int capture(lbm_batch_s* b) {
-  if (b->exec) {
-    BHIP(hipStreamSynchronize(b->stream));   // no replay of the old graph in flight
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
+int capture_pairs(lbm_batch_s* b, int pairs, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
   BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-  hipError_t e = enqueue_step(b, 0, b->cap);
-  if (e == hipSuccess) e = enqueue_step(b, 1, b->cap);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < pairs && e == hipSuccess; ++k) {
+    e = enqueue_step(b, 0, b->cap);
+    if (e == hipSuccess) e = enqueue_step(b, 1, b->cap);
+  }
   hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return bfail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    b->exec = nullptr;
+    *out = nullptr;
     return bfail(LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+void destroy_graphs(lbm_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec_long) (void)hipGraphExecDestroy(b->exec_long);
+  b->exec = b->exec_long = nullptr;
+}
+
+int capture(lbm_batch_s* b) {
+  if (b->exec || b->exec_long) {
+    BHIP(hipStreamSynchronize(b->stream));   // no replay of the old graphs in flight
+    destroy_graphs(b);
+  }
+  if (int e = capture_pairs(b, 1, &b->exec)) return e;
+  if (int e = capture_pairs(b, LONG_PAIRS, &b->exec_long)) {
+    destroy_graphs(b);
+    return e;
   }
   b->sig = launch_signature(b);
   return LBM_OK;
 }
 
 void release_groups(lbm_batch_s* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  b->exec = nullptr;
+  destroy_graphs(b);
   for (Group& g : b->groups) {
     drop(g.tab[0]);
     drop(g.tab[1]);
@@ -438,8 +456,10 @@ int run(lbm_batch_s* b, int32_t n, bool graph) {
     const int rows = (int)std::min<int64_t>(n - done, KIN_ROWS);
     if (int e = upload_kin(b, done, rows)) return e;
     int r = 0;
-    if (graph)
+    if (graph) {
+      for (; r + 2 * LONG_PAIRS <= rows; r += 2 * LONG_PAIRS) BHIP(hipGraphLaunch(b->exec_long, b->stream));
       for (; r + 1 < rows; r += 2) BHIP(hipGraphLaunch(b->exec, b->stream));
+    }
     for (; r < rows; ++r) BHIP(enqueue_step(b, r & 1, b->stream));
     done += rows;
   }

@@ -283,9 +283,11 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
           const int* c = g->c[i];
           int s[3] = {x - c[0], y - c[1], z - c[2]};
           bool inside = true;
-          for (int a = 0; a < 3; ++a) {
-            if (g->per[a]) s[a] = ((s[a] % g->n[a]) + g->n[a]) % g->n[a];
-            else if (s[a] < 0 || s[a] >= g->n[a]) inside = false;
+          for (int a = 0; a < 3; ++a) {   // |c| <= 1: one wrap at most
+            if (s[a] < 0 || s[a] >= g->n[a]) {
+              if (g->per[a]) s[a] += s[a] < 0 ? g->n[a] : -g->n[a];
+              else inside = false;
+            }
           }
           if (inside && g->mask[idx(s[0], s[1], s[2])]) continue;
           if (!inside && g->outlet >= 0) {

@@ -19,8 +19,10 @@
 //              its upstream neighbour (read-only sharing).
 // segments     one wave (64 lanes) handles 64 consecutive x of one row (y, z):
 //              seg_fluid / seg_bnd are 64-bit lane masks of fluid and boundary
-//              nodes; the segment's cut links are links[seg_lbase[s] ..
-//              seg_lbase[s+1]) (nseg + 1 entries).
+//              nodes; a segment with boundary nodes has its cut links in
+//              links[seg_lbase[s] .. seg_lbase[s+1]) (nseg + 1 entries; entry
+//              nseg is the link count).  Segments without boundary nodes never
+//              read seg_lbase.
 // links        ordered by (node, dir), so each segment's links are contiguous:
 //              ld (uint16) = lane of the boundary node in its segment | dir << 8,
 //              q and, when any wall moves, the wall term Gw (see elibb.hpp),
@@ -154,8 +156,8 @@ struct MovingParams {
   uint64_t* seg_fluid;           // fluid mask at t (written by classify)
   uint64_t* seg_prev;            // fluid mask at t-1 (written by classify)
   uint64_t* seg_bnd;
-  int32_t* seg_count;            // cut links per segment
-  const int32_t* seg_lbase;      // exclusive prefix of seg_count
+  int32_t* reg_count;            // cut links per region segment
+  int32_t* seg_lbase;            // link starts: written around the region segments
   uint16_t* lld;
   void* lq;
   void* lg;
@@ -179,7 +181,7 @@ hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStr
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);
-hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, hipStream_t s);
+hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_step_batch(int lattice, int storage, bool compact, const StepParams* tab, const uint32_t* tiles,
@@ -237,13 +239,14 @@ struct lbm_domain_s {
   double* u_tmp;
   int64_t red_blocks;
   int64_t steps;
+  bool state_set;                // lbm_set_state was called (the state is not the initial one)
   // moving sphere (lbm_set_moving_sphere)
   bool moving;
   double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
   int32_t* reg_seg;
   int64_t nreg;
   uint64_t* seg_prev;
-  int32_t* seg_count;
+  int32_t* reg_count;
   int64_t link_cap;
 };
 

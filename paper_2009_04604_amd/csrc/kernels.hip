@@ -349,8 +349,13 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   col.Fz = R(p.force[2]);
   col.force = p.has_force != 0;
 
-  const int lb0 = lk.seg_lbase[si.seg];
-  const int lb1 = lk.seg_lbase[si.seg + 1];
+  // segments without boundary nodes have no links (and need not read seg_lbase)
+  const uint64_t bmask = lk.seg_bnd[si.seg];
+  int lb0 = 0, lb1 = 0;
+  if (bmask) {
+    lb0 = lk.seg_lbase[si.seg];
+    lb1 = lk.seg_lbase[si.seg + 1];
+  }
   const bool has_links = lb1 > lb0;
   const R* __restrict__ lq = static_cast<const R*>(lk.lq);
   const R* __restrict__ lg = static_cast<const R*>(lk.lg);
@@ -377,7 +382,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * np + ix.template src<L>(i), i);
   }
-  const bool bnd = fluid && ((lk.seg_bnd[si.seg] >> si.lane) & 1ull);
+  const bool bnd = fluid && ((bmask >> si.lane) & 1ull);
   if (has_links && list_mode) patch_links<L, R, 2>(h, stage, bnd, tid, wbase, lb0, lb1, si.lane, lk.lld, lvi, ldp, vp);
 
   Moments<R> m;

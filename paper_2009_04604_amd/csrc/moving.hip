@@ -91,6 +91,13 @@ template <class L>
 __device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y, int z) {
   const GridGeom& g = p.g;
   uint32_t m = 0u;
+  // a node farther than r + 2 from the centre has no neighbour (|c_i| <= sqrt 2) in the sphere
+  {
+    double d[3];
+    rel(p, (double)x, (double)y, (double)z, d);
+    const double far = p.r + 2.0;
+    if (norm2(d) > far * far) return m;
+  }
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const int sx = wrap(x - L::cx(i), g.nx, g.perx);
@@ -118,39 +125,56 @@ __device__ __forceinline__ void classify_body(const MovingParams& p, int64_t wav
     p.seg_prev[s.seg] = p.seg_fluid[s.seg];
     p.seg_fluid[s.seg] = fm;
     p.seg_bnd[s.seg] = bm;
-    p.seg_count[s.seg] = tot;
+    p.reg_count[wave] = tot;
   }
 }
 
-// exclusive prefix sum of n counts into out[0..n] (one workgroup of 1024, fixed order)
-__device__ __forceinline__ void exclusive_scan_body(const int32_t* in, int64_t n, int32_t* out) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
+// Link starts of the region segments: an exclusive prefix sum of the region
+// counts (one workgroup of 1024: per-thread chunks, wave scans, wave offsets),
+// written at seg_lbase[seg] and seg_lbase[seg + 1] of every region segment
+// (neighbouring region segments write the same value at their shared entry),
+// and the total at seg_lbase[nseg].
+__device__ __forceinline__ void region_scan_body(const MovingParams& p) {
+  __shared__ int32_t wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t n = p.nreg;
   const int64_t chunk = (n + 1023) / 1024;
   const int64_t b = t * chunk, e = min(n, b + chunk);
-  int32_t acc = 0;
-  for (int64_t k = b; k < e; ++k) acc += in[k];
-  part[t] = acc;
+  int32_t own = 0;
+  for (int64_t k = b; k < e; ++k) own += p.reg_count[k];
+  int32_t inc = own;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t v = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
   __syncthreads();
-  if (t == 0) {
-    int32_t run = 0;
-    for (int k = 0; k < 1024; ++k) {
-      const int32_t v = part[k];
-      part[k] = run;
-      run += v;
+  if (w == 0) {
+    const int32_t x = lane < 16 ? wsum[lane] : 0;
+    int32_t xi = x;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int32_t v = __shfl_up(xi, off, 64);
+      if (lane >= off) xi += v;
     }
-    out[n] = run;
+    if (lane < 16) wsum[lane] = xi - x;
+    if (lane == 15) p.seg_lbase[p.g.nseg] = xi;
   }
   __syncthreads();
-  int32_t run = part[t];
+  int32_t run = wsum[w] + inc - own;
   for (int64_t k = b; k < e; ++k) {
-    out[k] = run;
-    run += in[k];
+    const int32_t c = p.reg_count[k];
+    const int32_t sg = p.reg_seg[k];
+    p.seg_lbase[sg] = run;
+    p.seg_lbase[sg + 1] = run + c;
+    run += c;
   }
 }
 
 template <class L, typename R>
 __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
+  if (p.reg_count[wave] == 0) return;   // wave-uniform: no cut link in this segment
   const Site s = region_site(p, wave);
   const bool fluid = (p.seg_fluid[s.seg] >> s.lane) & 1ull;
   const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
@@ -255,9 +279,7 @@ __global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
   if (wave < p.nreg) classify_body<L>(p, wave);
 }
 
-__global__ __launch_bounds__(1024) void exclusive_scan_kernel(const int32_t* in, int64_t n, int32_t* out) {
-  exclusive_scan_body(in, n, out);
-}
+__global__ __launch_bounds__(1024) void region_scan_kernel(MovingParams p) { region_scan_body(p); }
 
 template <class L, typename R>
 __global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
@@ -290,10 +312,7 @@ __global__ __launch_bounds__(256) void classify_batch_kernel(MovingBatch b) {
   if (batch_wave(b, p, wave)) classify_body<L>(p, wave);
 }
 
-__global__ __launch_bounds__(1024) void exclusive_scan_batch_kernel(MovingBatch b) {
-  const MovingParams& p = b.tab[blockIdx.x];
-  exclusive_scan_body(p.seg_count, p.g.nseg, const_cast<int32_t*>(p.seg_lbase));
-}
+__global__ __launch_bounds__(1024) void region_scan_batch_kernel(MovingBatch b) { region_scan_body(b.tab[blockIdx.x]); }
 
 template <class L, typename R>
 __global__ __launch_bounds__(256) void fill_batch_kernel(MovingBatch b) {
@@ -324,8 +343,8 @@ hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, hipStream_t s) {
-  exclusive_scan_kernel<<<1, 1024, 0, s>>>(in, n, out);
+hipError_t launch_region_scan(const MovingParams& p, hipStream_t s) {
+  region_scan_kernel<<<1, 1024, 0, s>>>(p);
   return hipGetLastError();
 }
 
@@ -366,7 +385,7 @@ hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, h
   const bool f64 = storage == ST_F64;
 #define LBM_MOVING_BATCH(LAT)                                                                  \
   classify_batch_kernel<LAT><<<grid, 256, 0, s>>>(b);                                          \
-  exclusive_scan_batch_kernel<<<b.nbox, 1024, 0, s>>>(b);                                      \
+  region_scan_batch_kernel<<<b.nbox, 1024, 0, s>>>(b);                                         \
   if (f64) fill_batch_kernel<LAT, double><<<grid, 256, 0, s>>>(b);                             \
   else fill_batch_kernel<LAT, float><<<grid, 256, 0, s>>>(b);                                  \
   switch (storage) {                                                                           \

@@ -8,8 +8,11 @@ one batched launch per step (``lbm_batch_step``: one multi-domain kernel per
 lattice/storage group, replayed from a HIP graph), so requests that arrive
 while others run join the running set at the next chunk boundary, and finished
 ones leave it and free their memory.  The chunk is cut at the nearest
-completion, so every request runs exactly its own step count.  While a chunk
-runs on the device the host builds the geometry of newly arrived requests.
+completion, so every request runs exactly its own step count.  The next chunk
+is launched before the host reads back the requests the last one completed and
+creates the newly admitted ones, so that host work overlaps device work; a
+finished request's memory returns to the budget at the chunk boundary after its
+read-back.
 
 ``Server`` holds only the scheduling; an executor object does the work:
 
@@ -21,7 +24,10 @@ runs on the device the host builds the geometry of newly arrived requests.
     free(handle)
 
 ``GpuExecutor`` is the executor of the product path; tests substitute a fake
-one with a fake clock.  ``run_plain`` is the reference form: one request at a
+one with a fake clock.  With ``prepare_workers`` > 0 the geometry of arriving
+requests is built on a thread pool (the host builder releases the GIL), so the
+scheduling thread only waits for it when the request reaches the head of the
+queue.  ``Server.phase`` accumulates the host seconds spent in each phase.  ``run_plain`` is the reference form: one request at a
 time, in arrival order, stepped with lbm_step.
 """
 import collections
@@ -73,7 +79,7 @@ class Server:
     """
 
     def __init__(self, executor, hbm_budget, chunk=100, max_active=None, clock=time.perf_counter, sleep=time.sleep,
-                 trace=None):
+                 trace=None, prepare_workers=0):
         if hbm_budget <= 0 or chunk < 1:
             raise ValueError("hbm_budget and chunk must be positive")
         self.ex = executor
@@ -83,9 +89,18 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.trace = trace
+        self.workers = int(prepare_workers)
         self.peak_bytes = 0
         self.peak_active = 0
         self.chunks = 0
+        self.phase = collections.defaultdict(float)   # host seconds per scheduling phase
+
+    def _timed(self, name, fn, *args):
+        t = time.perf_counter()
+        try:
+            return fn(*args)
+        finally:
+            self.phase[name] += time.perf_counter() - t
 
     def _event(self, what, now, **info):
         if self.trace:
@@ -96,9 +111,12 @@ class Server:
         call); returns one record per request, in request order."""
         jobs = [Job(r) for r in requests]
         pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.req["id"])))
-        waiting = collections.deque()          # arrived, geometry built, not admitted (FIFO)
+        waiting = collections.deque()          # arrived, not admitted (FIFO)
         active = []
-        used = 0
+        pool = None
+        if self.workers > 0:
+            import concurrent.futures
+            pool = concurrent.futures.ThreadPoolExecutor(max_workers=self.workers)
         t0 = self.clock()
 
         def now():
@@ -107,16 +125,40 @@ class Server:
         def take_arrivals():
             while pending and pending[0].arrival <= now():
                 j = pending.popleft()
-                j.payload = self.ex.prepare(j.req)
-                j.footprint = int(j.payload.footprint)
+                # geometry is built on the host, in the pool when there is one
+                j.payload = pool.submit(self.ex.prepare, j.req) if pool else self._timed("prepare", self.ex.prepare, j.req)
                 waiting.append(j)
-                self._event("arrive", now(), id=j.req["id"], footprint=j.footprint)
+                self._event("arrive", now(), id=j.req["id"])
 
-        while pending or waiting or active:
+        def ready(j):
+            if pool is not None and not isinstance(j.payload, _Done):
+                j.payload = _Done(self._timed("prepare_wait", j.payload.result))
+            p = j.payload.value if isinstance(j.payload, _Done) else j.payload
+            j.footprint = int(p.footprint)
+            return p
+
+        try:
+            self._loop(pending, waiting, active, jobs, take_arrivals, ready, now)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
+        return [j.record() for j in jobs]
+
+    def _loop(self, pending, waiting, active, jobs, take_arrivals, ready, now):
+        """One iteration per chunk: wait for the chunk in flight, free what was
+        read back during it, launch the next chunk, and while it runs read back
+        the requests it completed and admit new ones (they join the chunk
+        after)."""
+        used = 0
+        inflight = None           # (jobs, n) of the chunk on the device
+        done = []                 # completed in the last chunk, not read back yet
+        to_free = []              # read back, memory not released yet
+        while pending or waiting or active or inflight or done or to_free:
             take_arrivals()
             # admission: arrival order, as long as the head fits
             while waiting:
                 j = waiting[0]
+                payload = ready(j)
                 if j.footprint > self.budget:
                     waiting.popleft()
                     j.error = f"footprint {j.footprint} B exceeds the HBM budget {self.budget} B"
@@ -128,37 +170,51 @@ class Server:
                 if self.max_active is not None and len(active) >= self.max_active:
                     break
                 waiting.popleft()
-                j.handle = self.ex.admit(j.payload)
+                j.handle = self._timed("admit", self.ex.admit, payload)
                 j.payload = None
                 j.admitted = now()
                 used += j.footprint
                 active.append(j)
                 self._event("admit", now(), id=j.req["id"], used=used)
             self.peak_bytes = max(self.peak_bytes, used)
-            self.peak_active = max(self.peak_active, len(active))
-            if not active:
-                if pending:
-                    self.sleep(max(0.0, pending[0].arrival - now()))
-                continue
-            n = min(self.chunk, min(j.steps_left for j in active))
-            self.ex.step([j.handle for j in active], n)
-            self.chunks += 1
-            take_arrivals()                     # host work overlaps the chunk on the device
-            self.ex.sync()
-            done = []
-            for j in active:
-                j.steps_left -= n
-                if j.steps_left == 0:
-                    done.append(j)
-            for j in done:
-                j.result = self.ex.finish(j.handle, j.req)
-                self.ex.free(j.handle)
+            if inflight is not None:
+                self._timed("sync", self.ex.sync)
+                run, n = inflight
+                inflight = None
+                for j in run:
+                    j.steps_left -= n
+                    if j.steps_left == 0:
+                        done.append(j)
+                active[:] = [j for j in active if j.steps_left > 0]
+            for j in to_free:
+                self._timed("free", self.ex.free, j.handle)
                 j.handle = None
                 used -= j.footprint
+                self._event("free", now(), id=j.req["id"], used=used)
+            to_free = []
+            if active:
+                n = min(self.chunk, min(j.steps_left for j in active))
+                run = list(active)
+                self._timed("step_launch", self.ex.step, [j.handle for j in run], n)
+                self.chunks += 1
+                self.peak_active = max(self.peak_active, len(run))
+                inflight = (run, n)
+            # while the chunk runs: read back finished requests
+            for j in done:
+                j.result = self._timed("finish", self.ex.finish, j.handle, j.req)
                 j.finished = now()
-                self._event("finish", now(), id=j.req["id"], used=used)
-            active = [j for j in active if j.steps_left > 0]
-        return [j.record() for j in jobs]
+                to_free.append(j)
+                self._event("finish", now(), id=j.req["id"])
+            done = []
+            if inflight is None and not to_free and pending and not (waiting and used + waiting[0].footprint <= self.budget):
+                self.sleep(max(0.0, pending[0].arrival - now()))
+
+
+class _Done:
+    __slots__ = ("value",)
+
+    def __init__(self, v):
+        self.value = v
 
 
 def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep):
@@ -214,11 +270,16 @@ class GpuExecutor:
     """
 
     def __init__(self, storage="f16s", keep_fields=(), autotune=False, graph=True):
+        import torch
         from . import binding as B
         self.B = B
         self.storage = storage
         self.keep = set(keep_fields)
-        self.batch = B.Batch()
+        # steps run on `stream`; domains are created and read back on `side`,
+        # so that this host work overlaps the steps in flight
+        self.stream = torch.cuda.Stream()
+        self.side = torch.cuda.Stream()
+        self.batch = B.Batch(stream=self.stream.cuda_stream)
         self.batch.set_option("graph", int(bool(graph)))
         self.batch.set_option("autotune", int(bool(autotune)))
 
@@ -253,12 +314,14 @@ class GpuExecutor:
     def admit(self, p):
         B = self.B
         req = p.req
+        side = self.side.cuda_stream
         if req["kind"] == "couette":
-            d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage)
+            d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage, stream=side)
         else:
             d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage,
-                         periodic=(False, False, True), outlet_face="+x")
-        d.set_boundary_links(p.links)
+                         periodic=(False, False, True), outlet_face="+x", stream=side)
+        d.set_boundary_links(p.links)          # returns with the side stream drained
+        d.set_stream(self.stream.cuda_stream)
         d._req_mask = p.mask
         return d
 
@@ -266,14 +329,18 @@ class GpuExecutor:
         self.batch.step(handles, n)
 
     def step_alone(self, h, n):
+        """Plain form: n steps of one domain, waited for."""
         h.step(n)
+        self.stream.synchronize()
 
     def sync(self):
-        import torch
-        torch.cuda.synchronize()
+        self.stream.synchronize()
 
     def finish(self, h, req):
+        """Read back a request whose steps have all completed (the caller has
+        synchronised the step stream since its last launch), on the side stream."""
         keep = req["id"] in self.keep
+        h.set_stream(self.side.cuda_stream)
         rho, u, sums, unstable = h.macros(fields=keep)
         out = {"mass": float(sums[0]), "momentum": [float(x) for x in sums[1:3]], "unstable": bool(unstable)}
         if keep:
@@ -286,3 +353,5 @@ class GpuExecutor:
 
     def close(self):
         self.batch.close()
+        self.stream.synchronize()
+        self.side.synchronize()

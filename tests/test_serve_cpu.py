@@ -170,3 +170,16 @@ def test_idle_server_waits_for_arrivals():
     recs = serve.Server(ex, hbm_budget=10**9, clock=clk, sleep=clk.sleep).run(reqs)
     assert recs[0]["admitted"] >= 5.0
     assert recs[0]["time_to_solution"] == pytest.approx(10 * (1e-3 + 1e-8 * 64 * 64))
+
+
+def test_prepare_pool_gives_the_same_schedule():
+    reqs = _reqs(n=20, rate=200.0)
+    out = []
+    for workers in (0, 3):
+        clk = FakeClock()
+        ex = FakeExecutor(clk)
+        srv = serve.Server(ex, hbm_budget=2_000_000, chunk=40, clock=clk, sleep=clk.sleep, prepare_workers=workers)
+        recs = srv.run(reqs)
+        out.append(([(r["admitted"], r["finished"]) for r in recs], ex.admit_order))
+        assert set(srv.phase) >= {"admit", "step_launch", "sync", "finish", "free"}
+    assert out[0] == out[1]

@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the measurement, run one plain device copy of this size (for counter scaling)")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the device-copy bandwidth measurement (counter runs use their own calibration copy)")
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch section")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=5000)
@@ -92,6 +94,27 @@ def build_workload(name, storage, layout):
                "reynolds": 100, "tau": p["tau"], "variant": "ELIBB-FQ", "storage": storage}
     cfg["layout"] = layout
     return d, cfg
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """Read + write bandwidth of a plain device-to-device copy (torch), for
+    context beside the published peak."""
+    import torch
+    n = gib * 2**30 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return round(2.0 * gib * 2**30 / (ms * 1e-3) / 1e9, 1)
 
 
 def cpu_baseline(name, seconds):
@@ -310,11 +333,14 @@ def main():
 
     mlups = nfl * a.steps / wall / 1e6
     achieved = bytes_per_update * nfl / (kernel_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(a.workload, a.storage)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(a.workload, a.storage),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_fluid_update": bytes_per_update,
             "link_bytes_per_fluid_update": round(info["link_bytes"] / nfl, 2),
-            "kernel_ms": round(kernel_ms, 4)}
+            "kernel_ms": round(kernel_ms, 4),
+            "traffic_GBps": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
+            "device_copy_GBps": None if a.no_copy_probe else copy_bandwidth()}
     cfg.update({"fluid_nodes": nfl, "cut_links": info["n_links"], "boundary_nodes": info["n_boundary_nodes"],
                 "unstable": bool(unstable), "mass": sums[0]})
     out = {

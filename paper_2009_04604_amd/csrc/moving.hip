@@ -35,10 +35,13 @@ __device__ __forceinline__ Site region_site(const MovingParams& p, int64_t wave)
   return s;
 }
 
-// minimum image on a periodic axis: d - L rint(d / L) (round half to even)
+// minimum image on a periodic axis: d - L rint(d / L) (round half to even).
+// Within |d| < 0.49 L the quotient rounds to 0 and the result is d itself, so
+// the division is only evaluated outside that band (same result either way).
 __device__ __forceinline__ double min_image(double d, int L, int periodic) {
   if (!periodic) return d;
   const double Ld = (double)L;
+  if (fabs(d) < 0.49 * Ld) return d;
   return __dsub_rn(d, __dmul_rn(Ld, rint(__ddiv_rn(d, Ld))));
 }
 

@@ -43,6 +43,11 @@ enum {
 
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 
+/* Collision models (Sec. II.A): BGK (eq. LB-BGK) or TRT (TRT models paragraph).
+ * With a body force, Guo's source term is split like the populations under TRT:
+ * (1 - omega+/2) on its symmetric and (1 - omega-/2) on its antisymmetric part. */
+enum { LBM_BGK = 0, LBM_TRT = 1 };
+
 /* Storage of the populations.  Collision arithmetic is FP64 for LBM_F64 and
  * FP32 for the others; the 16-bit forms store h_i = f_i - w_i rounded to
  * nearest even and convert back to FP32 on load. */
@@ -76,6 +81,11 @@ typedef struct {
   int32_t layout;        /* LBM_LAYOUT_COMPACT (default): only fluid nodes are stored;
                             LBM_LAYOUT_DENSE: every node (plus a halo layer on
                             non-periodic axes)                                          */
+  int32_t collision;     /* LBM_BGK (default) or LBM_TRT                               */
+  double magic;          /* TRT magic parameter Lambda > 0 (eq. magic-parameter):
+                            omega+ = 1/tau relaxes the symmetric parts,
+                            omega- with (1/omega+ - 1/2)(1/omega- - 1/2) = Lambda the
+                            antisymmetric parts; the paper uses 3/16.  Ignored by BGK. */
 } lbm_domain_desc;
 
 enum { LBM_LAYOUT_COMPACT = 0, LBM_LAYOUT_DENSE = 1 };

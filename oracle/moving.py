@@ -38,10 +38,10 @@ class Kinematics:
 
 
 class MovingSphereSim:
-    def __init__(self, dom, radius, kin, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0)):
+    def __init__(self, dom, radius, kin, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
         self.dom, self.radius, self.kin = dom, float(radius), kin
         self.variant, self.q_cut = variant, q_cut
-        self.sim = Simulation(dom, tau, rho0=rho0, u0=u0)
+        self.sim = Simulation(dom, tau, rho0=rho0, u0=u0, magic=magic)
         self.t = 0
         self._install(first=True)
         self.sim.init_equilibrium()

@@ -9,7 +9,8 @@ nodes, so that a read of solid data poisons the result).  One step t -> t+1
    body force);
 2. collision: f*_i = f_i - omega (f_i - f^eq_i(rho, u)) + (1 - omega/2) S_i with
    omega = 1/tau (eq. LB-BGK, tau = taubar + 1/2) and the second-order
-   equilibrium (eq. Eq2ndOrder); S_i is Guo's source term;
+   equilibrium (eq. Eq2ndOrder); S_i is Guo's source term; or the TRT model
+   (see collide);
 3. streaming: f_i(x, t+1) = f*_i(x - c_i, t) for every pair that is not a cut
    link, wrapping on periodic axes (eq. LBE);
 4. zero-gradient outlet (a reading: open boundaries are outside the paper);
@@ -61,24 +62,51 @@ def guo_source(lat, u, force):
     return lat.w[:, None] * ((cF[:, None] - uF[None, :]) / cs2 + cu * cF[:, None] / (cs2 * cs2))
 
 
-def collide(lat, f, tau, force):
-    """BGK collision with Guo forcing. Returns f*, rho, u, f^eq (all on the given nodes)."""
+def trt_omega_minus(tau, magic):
+    """omega^- of the TRT model from the magic parameter (eq. magic-parameter):
+    Lambda = (1/omega^+ - 1/2)(1/omega^- - 1/2) with omega^+ = 1/tau."""
+    return 1.0 / (magic / (tau - 0.5) + 0.5)
+
+
+def collide(lat, f, tau, force, magic=None):
+    """Collision with Guo forcing. Returns f*, rho, u, f^eq (all on the given nodes).
+
+    magic None: BGK (eq. LB-BGK), f* = f - omega (f - f^eq) + (1 - omega/2) S.
+    magic = Lambda: TRT (Sec. II.A, TRT models): the symmetric parts
+    g^+ = (g_i + g_ibar)/2 relax with omega^+ = 1/tau, the antisymmetric parts
+    g^- = (g_i - g_ibar)/2 with omega^- (eq. magic-parameter),
+      f* = f - omega^+ (f^+ - f^eq+) - omega^- (f^- - f^eq-)
+             + (1 - omega^+/2) S^+ + (1 - omega^-/2) S^-,
+    Guo's source split the same way (the paper has no body force).
+    """
     omega = 1.0 / tau
     rho, u = moments(lat, f, force)
     feq = equilibrium(lat, rho, u)
-    fstar = f - omega * (f - feq)
-    if np.any(np.asarray(force) != 0.0):
-        fstar = fstar + (1.0 - 0.5 * omega) * guo_source(lat, u, force)
+    has_force = np.any(np.asarray(force) != 0.0)
+    if magic is None:
+        fstar = f - omega * (f - feq)
+        if has_force:
+            fstar = fstar + (1.0 - 0.5 * omega) * guo_source(lat, u, force)
+        return fstar, rho, u, feq
+    om_m = trt_omega_minus(tau, magic)
+    o = lat.opp
+    sym = lambda g: 0.5 * (g + g[o])
+    asym = lambda g: 0.5 * (g - g[o])
+    fstar = f - omega * (sym(f) - sym(feq)) - om_m * (asym(f) - asym(feq))
+    if has_force:
+        S = guo_source(lat, u, force)
+        fstar = fstar + (1.0 - 0.5 * omega) * sym(S) + (1.0 - 0.5 * om_m) * asym(S)
     return fstar, rho, u, feq
 
 
 class Simulation:
     """A lattice with a fixed (or externally updated) geometry and link list."""
 
-    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0)):
+    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
         self.dom = dom
         self.lat = dom.lat
         self.tau = float(tau)
+        self.magic = None if magic is None else float(magic)   # TRT magic parameter, None = BGK
         self.force = np.asarray(force, dtype=np.float64).reshape(3)
         self.rho0 = float(rho0)
         self.u0 = np.asarray(u0, dtype=np.float64).reshape(3)
@@ -152,7 +180,7 @@ class Simulation:
         feq = np.full_like(f, np.nan)
         rho = np.full(f.shape[1], np.nan)
         u = np.full((3, f.shape[1]), np.nan)
-        fs, r, uu, fe = collide(lat, f[:, nodes], self.tau, self.force)
+        fs, r, uu, fe = collide(lat, f[:, nodes], self.tau, self.force, self.magic)
         fstar[:, nodes], rho[nodes], u[:, nodes], feq[:, nodes] = fs, r, uu, fe
         fnew = np.full_like(f, np.nan)
         for i in range(lat.q):
@@ -210,7 +238,7 @@ class Simulation:
         return idx
 
 
-def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01):
+def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01, magic=None):
     """f(x, t+1) at the given fluid nodes only, from the full state f (Q, N) at t.
 
     The same step as Simulation.step, evaluated node by node: every pulled
@@ -228,7 +256,7 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
     out = np.full((lat.q, nodes.size), np.nan)
     force = np.asarray(force, dtype=np.float64)
     # the nodes' own collision (needed by their links)
-    fs_self, rho_s, u_s, feq_s = collide(lat, f[:, nodes], tau, force)
+    fs_self, rho_s, u_s, feq_s = collide(lat, f[:, nodes], tau, force, magic)
     L = {k: np.asarray(v) for k, v in links.items()}
     key = L["node"] * lat.q + L["dir"]
     order = np.argsort(key)
@@ -240,7 +268,7 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
         is_cut = (key.size > 0) & (key[order][k] == nodes * lat.q + i) if key.size else np.zeros(nodes.size, bool)
         stream = inside & fl[sidx] & ~is_cut
         if stream.any():
-            fs_src, _, _, _ = collide(lat, f[:, sidx[stream]], tau, force)
+            fs_src, _, _, _ = collide(lat, f[:, sidx[stream]], tau, force, magic)
             out[i, stream] = fs_src[i]
         rest = ~stream & ~is_cut
         if rest.any() and dom.outlet_face is not None:
@@ -248,7 +276,7 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
             prod = outlet_producer(dom, fl, xs[:, rest], lat.c[i])
             good = bo & (prod >= 0)
             if good.any():
-                fs_p, _, _, _ = collide(lat, f[:, prod[good]], tau, force)
+                fs_p, _, _, _ = collide(lat, f[:, prod[good]], tau, force, magic)
                 idx = np.flatnonzero(rest)[good]
                 out[i, idx] = fs_p[i]
         if is_cut.any():

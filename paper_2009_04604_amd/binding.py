@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 LAYOUTS = {"compact": 0, "dense": 1}
+COLLISIONS = {"BGK": 0, "TRT": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
 FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
@@ -49,7 +50,8 @@ class DomainDesc(ctypes.Structure):
         ("periodic", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
         ("force", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 3),
         ("outlet_face", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
-        ("arena_bytes", ctypes.c_size_t), ("layout", ctypes.c_int32),
+        ("arena_bytes", ctypes.c_size_t), ("layout", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("magic", ctypes.c_double),
     ]
 
 
@@ -132,7 +134,8 @@ def _torch_stream():
 
 
 def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, True), force=(0, 0, 0),
-              rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, arena=None, arena_bytes=0, layout="compact"):
+              rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, arena=None, arena_bytes=0, layout="compact",
+              collision="BGK", magic=3.0 / 16.0):
     d = DomainDesc()
     d.lattice = LATTICES[lattice]
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
@@ -148,6 +151,8 @@ def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, Tru
     d.arena = arena
     d.arena_bytes = int(arena_bytes)
     d.layout = LAYOUTS[layout]
+    d.collision = COLLISIONS[collision] if isinstance(collision, str) else int(collision)
+    d.magic = float(magic)
     return d
 
 
@@ -241,7 +246,7 @@ class Domain:
 
     def __init__(self, lattice, nx, ny, nz, fluid_mask, tau, storage="f32", periodic=(True, True, True),
                  force=(0, 0, 0), rho0=1.0, u0=(0, 0, 0), outlet_face=None, stream=None, torch_arena=True,
-                 layout="compact"):
+                 layout="compact", collision="BGK", magic=3.0 / 16.0):
         self.lattice, self.storage = lattice, storage
         self.n = (int(nx), int(ny), int(nz))
         self.N = int(nx) * int(ny) * int(nz)
@@ -249,7 +254,7 @@ class Domain:
         if stream is None:
             stream = _torch_stream()
         desc = make_desc(lattice, nx, ny, nz, tau, storage, periodic, force, rho0, u0, outlet_face, stream,
-                         layout=layout)
+                         layout=layout, collision=collision, magic=magic)
         self._arena = None
         if torch_arena:
             import torch

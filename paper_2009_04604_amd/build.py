@@ -31,8 +31,10 @@ def _run(cmd):
 
 
 def build(verbose=False):
+    """Compile every source (in parallel) and link liblbm.so."""
+    import concurrent.futures
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD_DIR, src + ".o")
@@ -41,10 +43,12 @@ def build(verbose=False):
             # host builder: no FMA contraction, so that the geometry arithmetic
             # rounds exactly like the plain double-precision definition
             cmd.insert(1, "-ffp-contract=off")
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
+        cmds.append(cmd)
         objs.append(obj)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+        for out in pool.map(_run, cmds):
+            if verbose and out.strip():
+                print(out)
     tmp = OUT + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
     os.replace(tmp, OUT)

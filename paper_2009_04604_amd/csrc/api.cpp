@@ -145,6 +145,9 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.dst = d->buf[1 - cur];
   p.lk = link_view(d, d->lv[cur], d->lv[1 - cur]);
   p.omega = 1.0 / d->desc.tau;
+  p.trt = d->desc.collision == LBM_TRT;
+  // eq. magic-parameter: (1/omega+ - 1/2)(1/omega- - 1/2) = Lambda
+  p.omega_minus = p.trt ? 1.0 / (d->desc.magic / (d->desc.tau - 0.5) + 0.5) : p.omega;
   for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
   p.has_force = (d->desc.force[0] != 0.0 || d->desc.force[1] != 0.0 || d->desc.force[2] != 0.0);
   p.variant = d->variant;
@@ -316,6 +319,9 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (d.outlet_face >= 0 && ((per >> (d.outlet_face >> 1)) & 1)) return fail(LBM_EINVAL, "outlet face lies on a periodic axis");
   const int64_t N = (int64_t)d.nx * d.ny * d.nz;
   if (d.layout != LBM_LAYOUT_COMPACT && d.layout != LBM_LAYOUT_DENSE) return fail(LBM_EINVAL, "invalid layout");
+  if (d.collision != LBM_BGK && d.collision != LBM_TRT) return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
+  if (d.collision == LBM_TRT && !(d.magic > 0.0 && std::isfinite(d.magic)))
+    return fail(LBM_EINVAL, "TRT magic parameter must be finite and > 0");
   const size_t need = lbm_arena_bytes(desc, fluid_mask);
   if (d.arena && d.arena_bytes < need) return fail(LBM_EINVAL, "arena too small: need " + std::to_string(need) + " bytes");
   if (d.arena && ((uintptr_t)d.arena & 255)) return fail(LBM_EINVAL, "arena must be 256-byte aligned");

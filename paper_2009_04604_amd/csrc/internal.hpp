@@ -100,7 +100,9 @@ struct StepParams {
   const void* src;
   void* dst;
   LinkView lk;
-  double omega;
+  double omega;                  // omega+ = 1/tau
+  double omega_minus;            // TRT: omega-; BGK: omega
+  int32_t trt;                   // 1: TRT collision
   double force[3];
   int32_t has_force;
   int32_t variant;
@@ -184,8 +186,8 @@ hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_
 hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
-hipError_t launch_step_batch(int lattice, int storage, bool compact, const StepParams* tab, const uint32_t* tiles,
-                             uint32_t nslots, uint32_t grid, hipStream_t s);
+hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, const StepParams* tab,
+                             const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s);
 // Batched moving-sphere rebuild (moving.hip).  tab: one MovingParams per sphere;
 // waves: region waves as sphere << TILE_SHIFT | wave; kin: [step][nkin] table,
 // row *ctr is the geometry time being built.

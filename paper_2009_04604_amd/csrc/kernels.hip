@@ -103,27 +103,47 @@ struct Moments {
   R drho, rho, ux, uy, uz, uu;
 };
 
-// Post-collision shifted population h*_i = h_i - omega (h_i - h^eq_i) + (1 - omega/2) S_i
-// with h^eq_i = f^eq_i - w_i = w_i [ (rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 uu) ]
-// (eq. LB-BGK, eq. Eq2ndOrder with c_s^2 = 1/3) and Guo's source term S_i.
-template <typename R>
+// Post-collision shifted population, with h^eq_i = f^eq_i - w_i =
+// w_i [ (rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 uu) ] (eq. Eq2ndOrder, c_s^2 = 1/3)
+// and Guo's source S_i = w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]:
+//   BGK (eq. LB-BGK)  h*_i = h_i - omega (h_i - h^eq_i) + (1 - omega/2) S_i
+//   TRT (TRT models)  h*_i = h_i - omega+ (h+_i - h^eq+_i) - omega- (h-_i - h^eq-_i)
+//                            + (1 - omega+/2) S+_i + (1 - omega-/2) S-_i
+// where g+-_i = (g_i +- g_ibar)/2: h^eq+ = w [(rho - 1) + rho (4.5 cu^2 - 1.5 uu)],
+// h^eq- = 3 w rho cu, S+ = w [9 cu cF - 3 u.F], S- = 3 w cF.  `hopp` is the
+// population of the opposite direction (TRT only).
+template <typename R, bool TRT>
 struct Collider {
   R omega, kf, Fx, Fy, Fz;
+  R omega_m, kf_m;               // TRT: omega- and 1 - omega-/2
   bool force;
   __device__ __forceinline__ R heq(R cx, R cy, R cz, R w, const Moments<R>& m) const {
     const R cu = cx * m.ux + cy * m.uy + cz * m.uz;
     return w * ((m.drho - R(1.5) * m.rho * m.uu) + m.rho * cu * (R(3) + R(4.5) * cu));
   }
-  __device__ __forceinline__ R post(R cx, R cy, R cz, R w, R h, const Moments<R>& m) const {
+  __device__ __forceinline__ R post(R cx, R cy, R cz, R w, R h, R hopp, const Moments<R>& m) const {
     const R cu = cx * m.ux + cy * m.uy + cz * m.uz;
-    const R he = w * ((m.drho - R(1.5) * m.rho * m.uu) + m.rho * cu * (R(3) + R(4.5) * cu));
-    R v = h + omega * (he - h);
-    if (force) {
-      const R cF = cx * Fx + cy * Fy + cz * Fz;
-      const R uF = m.ux * Fx + m.uy * Fy + m.uz * Fz;
-      v += (kf * w) * (R(3) * (cF - uF) + R(9) * cu * cF);
+    if constexpr (!TRT) {
+      const R he = w * ((m.drho - R(1.5) * m.rho * m.uu) + m.rho * cu * (R(3) + R(4.5) * cu));
+      R v = h + omega * (he - h);
+      if (force) {
+        const R cF = cx * Fx + cy * Fy + cz * Fz;
+        const R uF = m.ux * Fx + m.uy * Fy + m.uz * Fz;
+        v += (kf * w) * (R(3) * (cF - uF) + R(9) * cu * cF);
+      }
+      return v;
+    } else {
+      const R hep = w * ((m.drho - R(1.5) * m.rho * m.uu) + R(4.5) * m.rho * cu * cu);
+      const R hem = w * (R(3) * m.rho * cu);
+      const R hp = R(0.5) * (h + hopp), hm = R(0.5) * (h - hopp);
+      R v = h - omega * (hp - hep) - omega_m * (hm - hem);
+      if (force) {
+        const R cF = cx * Fx + cy * Fy + cz * Fz;
+        const R uF = m.ux * Fx + m.uy * Fy + m.uz * Fz;
+        v += (kf * w) * (R(9) * cu * cF - R(3) * uF) + (kf_m * w) * (R(3) * cF);
+      }
+      return v;
     }
-    return v;
   }
 };
 
@@ -318,7 +338,7 @@ __device__ __forceinline__ void patch_links(R (&h)[L::Q], R (*stage)[BLOCK], boo
 // The zero-gradient outlet needs no work of its own: its pulls are clamped onto
 // the face layer (see axis_src).
 // ---------------------------------------------------------------------------
-template <class L, int S, bool COMPACT>
+template <class L, int S, bool COMPACT, bool TRT>
 __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   using St = Storage<S>;
   using T = typename St::T;
@@ -341,9 +361,11 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   const int wbase = tid & ~(SEG - 1);
   const bool list_mode = lk.lv_out != nullptr;
 
-  Collider<R> col;
+  Collider<R, TRT> col;
   col.omega = R(p.omega);
   col.kf = R(1) - R(0.5) * col.omega;
+  col.omega_m = R(p.omega_minus);
+  col.kf_m = R(1) - R(0.5) * col.omega_m;
   col.Fx = R(p.force[0]);
   col.Fy = R(p.force[1]);
   col.Fz = R(p.force[2]);
@@ -397,7 +419,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   if (fluid || (!COMPACT && list_mode && inrow)) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-      const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], m);
+      const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], h[L::opp(i)], m);
       St::template store<L>(dst + i * np + ix.self, fluid ? v : R(0), i);
     }
   }
@@ -438,11 +460,11 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       const Coef<R> a = elibb_coefficients_fast<R>(p.variant, q, qc);
       // bounced direction: c_ibar = -c_i, w_ibar = w_i
       const R he_b = col.heq(-cx, -cy, -cz, w, mb);
-      const R hs_b = col.post(-cx, -cy, -cz, w, hb, mb);
+      const R hs_b = col.post(-cx, -cy, -cz, w, hb, hi, mb);
       const R n_pre = hb - he_b;         // bounced pre-collision non-equilibrium (eq. neqbb-s)
       const R n_post = hs_b - he_b;      // bounced post-collision non-equilibrium
       R v = a.a4 * n_pre + a.a5 * n_post + a.a2 * hs_b + w * (mb.drho * (a.a4 + a.a5) + mb.rho * gw);
-      v += a.a3 * col.post(cx, cy, cz, w, hi, mb);
+      v += a.a3 * col.post(cx, cy, cz, w, hi, hb, mb);
       if (list_mode) {
         lvo[k] = v;
       } else {
@@ -460,9 +482,9 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   }
 }
 
-template <class L, int S, bool COMPACT>
+template <class L, int S, bool COMPACT, bool TRT>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
-  step_body<L, S, COMPACT>(p, logical_block(p.g.xcd_remap));
+  step_body<L, S, COMPACT, TRT>(p, logical_block(p.g.xcd_remap));
 }
 
 // Several domains in one persistent launch.  Slot k of the tile table names a
@@ -470,12 +492,12 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
 // walks the slots b, b + gridDim.x, ...  The host orders the table (see
 // tile_table), so the grid size and the order are launch choices that leave
 // every result unchanged.
-template <class L, int S, bool COMPACT>
+template <class L, int S, bool COMPACT, bool TRT>
 __global__ __launch_bounds__(BLOCK) void step_batch_kernel(const StepParams* __restrict__ tab,
                                                            const uint32_t* __restrict__ tiles, uint32_t nslots) {
   for (uint32_t k = blockIdx.x; k < nslots; k += gridDim.x) {
     const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[k]);
-    if (t != TILE_EMPTY) step_body<L, S, COMPACT>(tab[t >> TILE_SHIFT], t & TILE_MASK);
+    if (t != TILE_EMPTY) step_body<L, S, COMPACT, TRT>(tab[t >> TILE_SHIFT], t & TILE_MASK);
     wave_lds_sync();   // the next tile reuses the wave's LDS columns
   }
 }
@@ -751,15 +773,40 @@ int64_t grid_blocks(const GridGeom& g) {
     }                                                                                             \
   } while (0)
 
+// step kernels: lattice x storage x layout x collision
+#define LBM_STEP_L(KERNEL, LAT, storage, C, T, grid, stream, ...)                                      \
+  do {                                                                                              \
+    switch (storage) {                                                                              \
+      case ST_F64: KERNEL<LAT, ST_F64, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;       \
+      case ST_F32: KERNEL<LAT, ST_F32, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;       \
+      case ST_F16S: KERNEL<LAT, ST_F16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;     \
+      default: KERNEL<LAT, ST_BF16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;         \
+    }                                                                                               \
+  } while (0)
+
+#define LBM_STEP_T(KERNEL, lattice, storage, compact, T, grid, stream, ...)                            \
+  do {                                                                                              \
+    if (lattice == LBM_D2Q9) {                                                                      \
+      if (compact) LBM_STEP_L(KERNEL, D2Q9, storage, true, T, grid, stream, __VA_ARGS__);           \
+      else LBM_STEP_L(KERNEL, D2Q9, storage, false, T, grid, stream, __VA_ARGS__);                  \
+    } else {                                                                                        \
+      if (compact) LBM_STEP_L(KERNEL, D3Q19, storage, true, T, grid, stream, __VA_ARGS__);          \
+      else LBM_STEP_L(KERNEL, D3Q19, storage, false, T, grid, stream, __VA_ARGS__);                 \
+    }                                                                                               \
+  } while (0)
+
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s) {
-  LBM_DISPATCH3(step_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
+  const dim3 grid((unsigned)grid_blocks(p.g));
+  if (p.trt) LBM_STEP_T(step_kernel, lattice, storage, p.g.compact, true, grid, s, p);
+  else LBM_STEP_T(step_kernel, lattice, storage, p.g.compact, false, grid, s, p);
   return hipGetLastError();
 }
 
-hipError_t launch_step_batch(int lattice, int storage, bool compact, const StepParams* tab, const uint32_t* tiles,
-                             uint32_t nslots, uint32_t grid, hipStream_t s) {
+hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, const StepParams* tab,
+                             const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s) {
   if (nslots == 0 || grid == 0) return hipSuccess;
-  LBM_DISPATCH3(step_batch_kernel, lattice, storage, compact, dim3(grid), s, tab, tiles, nslots);
+  if (trt) LBM_STEP_T(step_batch_kernel, lattice, storage, compact, true, dim3(grid), s, tab, tiles, nslots);
+  else LBM_STEP_T(step_batch_kernel, lattice, storage, compact, false, dim3(grid), s, tab, tiles, nslots);
   return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@ import synth
 from oracle import geometry as G, lattice, solver
 
 
-def annulus(scale=1.0, u_inner=0.01, tau=0.8, variant="FQ", omega_outer=0.0):
+def annulus(scale=1.0, u_inner=0.01, tau=0.8, variant="FQ", omega_outer=0.0, magic=None):
     p = synth.couette_annulus(scale, u_inner=u_inner, tau=tau)
     dom = G.Domain(lattice.D2Q9, p["nx"], p["ny"], 1)
     om1 = p["u_inner"] / p["r1"]
@@ -13,14 +13,14 @@ def annulus(scale=1.0, u_inner=0.01, tau=0.8, variant="FQ", omega_outer=0.0):
     outer = G.Sphere(p["centre"], p["r2"], False, Omega=(0, 0, omega_outer))
     fluid = G.classify(dom, [inner, outer])
     links = G.cut_links(dom, fluid, [inner, outer])
-    sim = solver.Simulation(dom, p["tau"])
+    sim = solver.Simulation(dom, p["tau"], magic=magic)
     sim.set_geometry(fluid, links, variant)
     sim.init_equilibrium()
     return sim, p, om1
 
 
 def channel(nx, ny, walls=("-y", "+y"), q=0.5, u_top=(0.0, 0.0, 0.0), tau=0.8, force=(0, 0, 0),
-            variant="FQ", periodic_x=True, lat=lattice.D2Q9, nz=1):
+            variant="FQ", periodic_x=True, lat=lattice.D2Q9, nz=1, magic=None):
     per = (periodic_x, False, True)
     dom = G.Domain(lat, nx, ny, nz, periodic=per)
     faces = []
@@ -29,7 +29,7 @@ def channel(nx, ny, walls=("-y", "+y"), q=0.5, u_top=(0.0, 0.0, 0.0), tau=0.8, f
         faces.append(G.FaceWall(f, q, u_top if w == "+y" else None))
     fluid = np.ones(dom.shape, dtype=bool)
     links = G.cut_links(dom, fluid, [], faces)
-    sim = solver.Simulation(dom, tau, force=force)
+    sim = solver.Simulation(dom, tau, force=force, magic=magic)
     sim.set_geometry(fluid, links, variant)
     sim.init_equilibrium()
     return sim

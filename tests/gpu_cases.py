@@ -7,7 +7,7 @@ from oracle import geometry as G, lattice as OL, solver
 
 class Case:
     def __init__(self, lat, n, periodic=(True, True, True), outlet=None, spheres=(), faces=(), tau=0.8,
-                 force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0)):
+                 force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
         self.lat = lat
         self.n = tuple(n)
         self.periodic = tuple(periodic)
@@ -15,6 +15,7 @@ class Case:
         self.spheres = list(spheres)     # (centre, r, inside, V, Omega)
         self.faces = list(faces)         # (face, q, uw, profile)
         self.tau, self.force, self.rho0, self.u0 = tau, tuple(force), rho0, tuple(u0)
+        self.magic = magic               # TRT magic parameter, None = BGK
 
     # -- oracle ---------------------------------------------------------------
     def oracle_geometry(self):
@@ -35,7 +36,7 @@ class Case:
 
     def oracle(self, variant="FQ", q_cut=0.01):
         dom, fluid, sh, fcs = self.oracle_geometry()
-        sim = solver.Simulation(dom, self.tau, force=self.force, rho0=self.rho0, u0=self.u0)
+        sim = solver.Simulation(dom, self.tau, force=self.force, rho0=self.rho0, u0=self.u0, magic=self.magic)
         sim.set_geometry(fluid, G.cut_links(dom, fluid, sh, fcs), variant, q_cut)
         sim.init_equilibrium()
         return sim
@@ -50,8 +51,9 @@ class Case:
             g.add_face_wall(f, q, uw=uw, profile=prof)
         mask, links = g.build()
         g.close()
+        trt = {} if self.magic is None else {"collision": "TRT", "magic": self.magic}
         d = B.Domain(self.lat, nx, ny, nz, mask, self.tau, storage=storage, periodic=self.periodic,
-                     force=self.force, rho0=self.rho0, u0=self.u0, outlet_face=self.outlet, layout=layout)
+                     force=self.force, rho0=self.rho0, u0=self.u0, outlet_face=self.outlet, layout=layout, **trt)
         d.set_boundary_links(links, variant=variant, q_cutoff=q_cut)
         return d, mask, links
 
@@ -67,15 +69,15 @@ def fluid_velocity_error(d, sim):
     return err, rho_g[fl], rho_o[fl], sums, unstable
 
 
-def annulus_case(scale=1.0, tau=0.8, u_inner=0.01):
+def annulus_case(scale=1.0, tau=0.8, u_inner=0.01, magic=None):
     n = int(round(48 * scale))
     c = (n / 2.0, n / 2.0, 0.0)
     om1 = u_inner / (8.0 * scale)
     return Case("D2Q9", (n, n, 1), spheres=[(c, 8.0 * scale, True, None, (0, 0, om1)), (c, 20.0 * scale, False, None, None)],
-                tau=tau)
+                tau=tau, magic=magic)
 
 
-def channel_case(nx=200, ny=80, radius=6.0, centre=(40.3, 40.6), u_max=0.05, tau=0.6):
+def channel_case(nx=200, ny=80, radius=6.0, centre=(40.3, 40.6), u_max=0.05, tau=0.6, magic=None):
     return Case("D2Q9", (nx, ny, 1), periodic=(False, False, True), outlet=1,
                 spheres=[((centre[0], centre[1], 0.0), radius, True, None, None)],
-                faces=[(0, 0.5, (u_max, 0.0, 0.0), 1), (2, 0.5, None, 0), (3, 0.5, None, 0)], tau=tau)
+                faces=[(0, 0.5, (u_max, 0.0, 0.0), 1), (2, 0.5, None, 0), (3, 0.5, None, 0)], tau=tau, magic=magic)

@@ -161,6 +161,25 @@ int lbm_macros(lbm_domain d, double* rho, double* u, double* sums);
 int lbm_get_state(lbm_domain d, double* f);
 int lbm_set_state(lbm_domain d, const double* f);
 
+/* Groups of cut links for lbm_momentum_exchange (e.g. one per object): group[k]
+ * in [0, n_groups) for the k-th link in the order given to
+ * lbm_set_boundary_links; group NULL with n_groups = 1 puts every link in one
+ * group (the default).  Host array copied.  LBM_ESTATE without a static link
+ * list (moving sphere), LBM_EINVAL for ids out of range or n_groups outside
+ * [1, 4096].  Installing new links resets the grouping. */
+int lbm_set_link_groups(lbm_domain d, const int32_t* group, int32_t n_groups);
+
+/* Force exerted by the fluid on each group of walls during the last step (Sec.
+ * II "Force computation": the Galilean-invariant momentum exchange), summed in
+ * FP64 in a fixed order over the group's links (x_F, i):
+ *   F = (c_ibar - u_w) f*_ibar(x_F, t-1) - (c_i - u_w) f_i(x_F, t),
+ * t the current time, u_w the link's wall velocity at t (uw_t of the links),
+ * f*_ibar the post-collision population leaving x_F towards the wall and f_i the
+ * rebuilt one.  force: n_groups x 3 doubles (z = 0 for D2Q9), caller-owned.
+ * Synchronises the stream.  LBM_ESTATE for a moving-sphere domain, without
+ * links, or before the first step after the links were installed. */
+int lbm_momentum_exchange(lbm_domain d, double* force);
+
 /* Change the stream used by later calls. */
 int lbm_set_stream(lbm_domain d, void* stream);
 
@@ -264,6 +283,9 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links);
  * uw_t, uw_t1 [3*n_links] (any may be NULL). Links are ordered by node, dir. */
 int lbm_geometry_get(lbm_geometry g, uint8_t* mask, int64_t* node, int8_t* dir, double* q,
                      double* uw_t, double* uw_t1);
+/* Owner of each link (n_links int32, same order): the index of the sphere in
+ * order of addition, or (number of spheres + index of the face wall). */
+int lbm_geometry_get_shapes(lbm_geometry g, int32_t* shape);
 int lbm_geometry_free(lbm_geometry g);
 
 #ifdef __cplusplus

@@ -182,3 +182,29 @@ def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1):
 def reconstruct(coef, P):
     """f_i(x_F, t+1) = sum_k a_k P_k  (eq. interpolated_bb_equation)."""
     return (coef.T * P).sum(axis=0)
+
+
+def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups):
+    """Force exerted by the fluid on the walls during one step, per link group
+    (Sec. II "Force computation", the Galilean-invariant momentum exchange of
+    Wen et al.).  For a cut link (x_F, i) the population f*_ibar(x_F, t) leaves
+    towards the wall and comes back as f_i(x_F, t+1):
+        F_link = (c_ibar - u_w) f*_ibar(x_F, t) - (c_i - u_w) f_i(x_F, t+1).
+    (The printed formula writes the outgoing post-collision population with the
+    index i; it is read as ibar, the direction pointing into the wall.)
+
+    i: (n,) missing directions; fstar_F: (Q, n) post-collision populations of the
+    links' nodes at t; f_new: (n,) rebuilt f_i(x_F, t+1); uw_t: (3, n) wall
+    velocity at x_W; group: (n,) group ids.  Returns (n_groups, 3).
+    """
+    ib = lat.opp[i]
+    n = np.arange(i.size)
+    c = lat.c.astype(np.float64)
+    out_ = fstar_F[ib, n]
+    contrib = (c[ib].T - uw_t) * out_[None, :] - (c[i].T - uw_t) * f_new[None, :]   # (3, n)
+    F = np.zeros((n_groups, 3))
+    for g in range(n_groups):
+        sel = group == g
+        F[g] = contrib[:, sel].sum(axis=1)
+    return F
+

@@ -261,7 +261,7 @@ def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None, nodes=None):
         assert fl[nodes].all() and np.all(np.diff(nodes) > 0)
     X = dom.coords(nodes)
     xs = X
-    out = {"node": [], "dir": [], "q": [], "uw_t": [], "uw_t1": []}
+    out = {"node": [], "dir": [], "q": [], "uw_t": [], "uw_t1": [], "shape": []}
     for i in range(1, lat.q):
         c = lat.c[i]
         src, inside = _source(dom, xs.copy(), c)
@@ -315,9 +315,10 @@ def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None, nodes=None):
         out["q"].append(best)
         out["uw_t"].append(uw)
         out["uw_t1"].append(uw1)
+        out["shape"].append(owner)
     if not out["node"]:
         return {"node": np.zeros(0, np.int64), "dir": np.zeros(0, np.int64), "q": np.zeros(0),
-                "uw_t": np.zeros((3, 0)), "uw_t1": np.zeros((3, 0))}
+                "uw_t": np.zeros((3, 0)), "uw_t1": np.zeros((3, 0)), "shape": np.zeros(0, np.int64)}
     node = np.concatenate(out["node"])
     d = np.concatenate(out["dir"])
     order = np.lexsort((d, node))
@@ -327,4 +328,5 @@ def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None, nodes=None):
         "q": np.concatenate(out["q"])[order],
         "uw_t": np.concatenate(out["uw_t"], axis=1)[:, order],
         "uw_t1": np.concatenate(out["uw_t1"], axis=1)[:, order],
+        "shape": np.concatenate(out["shape"])[order].astype(np.int64),   # spheres first, then faces
     }

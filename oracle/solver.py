@@ -113,6 +113,9 @@ class Simulation:
         self.f = None
         self.fluid = None
         self.t = 0
+        self.last_force = None     # (n_groups, 3): wall forces of the last step
+        self.link_group = None
+        self.n_groups = 1
 
     # -- geometry -----------------------------------------------------------------
     def set_geometry(self, fluid, links, variant="FQ", q_cut=0.01):
@@ -193,8 +196,18 @@ class Simulation:
             n, d = L["node"], L["dir"]
             P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"])
             fnew[d, n] = boundary.reconstruct(self.coef, P)
+            grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
+            self.last_force = boundary.momentum_exchange(lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp,
+                                                         self.n_groups)
         self.f = fnew
         self.t += 1
+
+    def set_link_groups(self, group, n_groups):
+        """Group ids (one per link, in the link list's order) for the forces."""
+        g = np.asarray(group, dtype=np.int64).reshape(-1)
+        if g.size != self.links["node"].size or (g.size and (g.min() < 0 or g.max() >= n_groups)):
+            raise ValueError("bad link groups")
+        self.link_group, self.n_groups = g, int(n_groups)
 
     def run(self, n):
         for _ in range(int(n)):

@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_last_error", "lbm_set_moving_sphere", "lbm_geometry_create", "lbm_geometry_add_sphere", "lbm_geometry_add_spheres",
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
-    "lbm_batch_free", "lbm_step_batch",
+    "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -104,6 +104,9 @@ def lib():
         "lbm_batch_get_choice": (I32, [P, P, P, P]),
         "lbm_batch_free": (I32, [P]),
         "lbm_step_batch": (I32, [P, I32, I32]),
+        "lbm_set_link_groups": (I32, [P, P, I32]),
+        "lbm_momentum_exchange": (I32, [P, P]),
+        "lbm_geometry_get_shapes": (I32, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -291,6 +294,17 @@ class Domain:
     def set_stream(self, stream):
         _check(lib().lbm_set_stream(self.h, stream))
 
+    def set_link_groups(self, group=None, n_groups=1):
+        g = None if group is None else np.ascontiguousarray(group, dtype=np.int32)
+        _check(lib().lbm_set_link_groups(self.h, _ptr(g), int(n_groups)))
+        self._n_groups = int(n_groups)
+
+    def force(self):
+        """(n_groups, 3) momentum-exchange force of the last step (FP64)."""
+        out = np.zeros((getattr(self, "_n_groups", 1), 3))
+        _check(lib().lbm_momentum_exchange(self.h, _ptr(out)))
+        return out
+
     def set_launch_option(self, option, value):
         lbm_set_launch_option(self.h, option, value)
 
@@ -422,8 +436,11 @@ class Geometry:
         q = np.empty(n)
         uw = np.empty((n, 3))
         uw1 = np.empty((n, 3))
+        shape = np.empty(n, dtype=np.int32)
         _check(lib().lbm_geometry_get(self.h, _ptr(mask), _ptr(node), _ptr(d), _ptr(q), _ptr(uw), _ptr(uw1)))
-        return mask, {"node": node, "dir": d.astype(np.int64), "q": q, "uw_t": uw, "uw_t1": uw1}
+        _check(lib().lbm_geometry_get_shapes(self.h, _ptr(shape)))
+        return mask, {"node": node, "dir": d.astype(np.int64), "q": q, "uw_t": uw, "uw_t1": uw1,
+                      "shape": shape.astype(np.int64)}
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -269,6 +269,12 @@ void free_links(lbm_domain_s* d) {
   dfree(d->lv[1]);
   dfree(d->lq);
   dfree(d->lg);
+  dfree(d->luw);
+  dfree(d->lgrp);
+  dfree(d->lforce);
+  dfree(d->gforce);
+  d->link_order.clear();
+  d->n_groups = 1;
   d->nb = d->nl = 0;
 }
 
@@ -419,6 +425,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   dm->cur = 0;
   int bad_dir = 0;
   dm->links_ok = first_uncovered(dm, {}, &bad_dir) < 0;
+  dm->n_groups = 1;
   dm->uid = next_uid();
   *out = dm;
   clear_error();
@@ -559,6 +566,16 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
     if (moving) HIP_TRY(upload_real(d->lg, gd));
     HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d->seg_lbase, slb.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice));
+    // wall velocities at t, for the momentum-exchange force (only when a wall moves)
+    bool uw_any = false;
+    for (int64_t k = 0; uw_t && k < 3 * n_links && !uw_any; ++k) uw_any = uw_t[k] != 0.0;
+    if (uw_any) {
+      std::vector<double> uv(3 * n_links);
+      for (int64_t k = 0; k < n_links; ++k)
+        for (int a = 0; a < 3; ++a) uv[3 * k + a] = uw_t[3 * order[k] + a];
+      if (int e = dalloc(d->luw, uv.size() * 8)) return e;
+      HIP_TRY(hipMemcpy(d->luw, uv.data(), uv.size() * 8, hipMemcpyHostToDevice));
+    }
     d->nb = nb;
     d->nl = n_links;
     HIP_TRY(import_state(d, fstate));
@@ -568,6 +585,8 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   const int code = up();
   if (fstate) (void)hipFree(fstate);
   if (code != LBM_OK) return code;
+  d->link_order = order;
+  d->links_step = d->steps;
   d->nl = n_links;
   d->variant = variant;
   d->q_cut = q_cutoff;
@@ -743,6 +762,55 @@ int lbm_set_state(lbm_domain d, const double* f) {
   if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_set_link_groups(lbm_domain d, const int32_t* group, int32_t n_groups) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (d->moving || !d->links_ok) return fail(LBM_ESTATE, "link groups need an installed static link list");
+  if (n_groups < 1 || n_groups > 4096) return fail(LBM_EINVAL, "n_groups must lie in [1, 4096]");
+  if (!group && n_groups != 1) return fail(LBM_EINVAL, "group ids are required for more than one group");
+  std::vector<int32_t> sorted(d->nl, 0);
+  if (group) {
+    for (int64_t k = 0; k < d->nl; ++k) {
+      const int32_t v = group[d->link_order[k]];
+      if (v < 0 || v >= n_groups)
+        return fail(LBM_EINVAL, "link " + std::to_string(d->link_order[k]) + ": group out of range");
+      sorted[k] = v;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  dfree(d->lgrp);
+  dfree(d->gforce);
+  if (group && d->nl > 0) {
+    if (int e = dalloc(d->lgrp, sorted.size() * 4)) return e;
+    HIP_TRY(hipMemcpy(d->lgrp, sorted.data(), sorted.size() * 4, hipMemcpyHostToDevice));
+  }
+  d->n_groups = n_groups;
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_momentum_exchange(lbm_domain d, double* force) {
+  if (!d || !force) return fail(LBM_EINVAL, "null argument");
+  if (d->moving) return fail(LBM_ESTATE, "the force of a moving sphere is not available (its links are rebuilt every step)");
+  if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set");
+  if (d->steps == d->links_step) return fail(LBM_ESTATE, "no step taken since the links were installed");
+  if (!d->lforce && d->nl > 0)
+    if (int e = dalloc(d->lforce, (size_t)d->nl * 3 * 8)) return e;
+  if (!d->gforce)
+    if (int e = dalloc(d->gforce, (size_t)d->n_groups * 3 * 8)) return e;
+  ForceParams p{};
+  p.g = d->g;
+  p.pop = d->buf[d->cur];
+  p.lk = link_view(d, d->lv[d->cur], nullptr);
+  p.luw = d->luw;
+  p.contrib = d->lforce;
+  p.nl = d->nl;
+  HIP_TRY(launch_force(d->desc.lattice, d->desc.storage, p, d->n_groups, d->lgrp, d->gforce, d->stream));
+  HIP_TRY(hipMemcpyAsync(force, d->gforce, (size_t)d->n_groups * 3 * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  clear_error();
   return LBM_OK;
 }
 

@@ -48,6 +48,7 @@ struct lbm_geometry_s {
   std::vector<int64_t> node;
   std::vector<int8_t> dir;
   std::vector<double> q, uw;
+  std::vector<int32_t> shape;    // owner of each link: spheres in order of addition, then faces
   int c[19][3];
 };
 
@@ -268,6 +269,7 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
 
   g->node.clear();
   g->dir.clear();
+  g->shape.clear();
   g->q.clear();
   g->uw.clear();
   std::vector<int> cand;
@@ -347,6 +349,7 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
           if (g->D == 2) u[2] = 0.0;
           g->node.push_back(n);
           g->dir.push_back((int8_t)i);
+          g->shape.push_back(owner);
           g->q.push_back(best);
           g->uw.insert(g->uw.end(), u, u + 3);
         }
@@ -366,6 +369,13 @@ int lbm_geometry_get(lbm_geometry g, uint8_t* mask, int64_t* node, int8_t* dir, 
   if (q) std::copy(g->q.begin(), g->q.end(), q);
   if (uw_t) std::copy(g->uw.begin(), g->uw.end(), uw_t);
   if (uw_t1) std::copy(g->uw.begin(), g->uw.end(), uw_t1);
+  return LBM_OK;
+}
+
+int lbm_geometry_get_shapes(lbm_geometry g, int32_t* shape) {
+  if (!g || !shape) return gfail(LBM_EINVAL, "null argument");
+  if (!g->built) return gfail(LBM_ESTATE, "geometry not built");
+  std::copy(g->shape.begin(), g->shape.end(), shape);
   return LBM_OK;
 }
 

@@ -138,6 +138,15 @@ struct MacroParams {
 };
 constexpr int NPART = 8;         // mass, mom x/y/z, |du|^2, |u|^2, non-finite count, pad
 
+struct ForceParams {
+  GridGeom g;
+  const void* pop;               // current population buffer
+  LinkView lk;                   // lv_in: the link values of the current time
+  const double* luw;             // [3 nl] wall velocity per link, or null (walls at rest)
+  double* contrib;               // [3 nl] per-link force
+  int64_t nl;
+};
+
 // Kinematics of a moving sphere for the geometry of time t.
 struct MovingKin {
   double c[3];                   // centre at t
@@ -182,6 +191,8 @@ hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipS
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s);
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
+hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, const int32_t* group,
+                        double* out, hipStream_t s);
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);
 hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
@@ -250,6 +261,14 @@ struct lbm_domain_s {
   uint64_t* seg_prev;
   int32_t* reg_count;
   int64_t link_cap;
+  // momentum-exchange force (static link list)
+  std::vector<int64_t> link_order;   // position in the caller's list of each stored link
+  double* luw;                       // [3 nl] wall velocity at t, or null
+  int32_t* lgrp;                     // [nl] group of each stored link, or null (one group)
+  int32_t n_groups;
+  double* lforce;                    // [3 nl] scratch
+  double* gforce;                    // [3 n_groups]
+  int64_t links_step;                // steps when the links were installed
 };
 
 namespace lbm {

@@ -724,6 +724,63 @@ __global__ __launch_bounds__(BLOCK) void reduce_kernel(const double* partials, i
 }
 
 // ---------------------------------------------------------------------------
+// Momentum-exchange force of the last step (Sec. II "Force computation",
+// Galilean-invariant form): per cut link (x_F, i)
+//   F = (c_ibar - u_w) f*_ibar(x_F, t-1) - (c_i - u_w) f_i(x_F, t),
+// with f*_ibar(x_F, t-1) the post-collision value the step left in x_F's own
+// slot of direction ibar, and f_i(x_F, t) the link value it rebuilt.
+// ---------------------------------------------------------------------------
+template <class L, int S, bool COMPACT>
+__global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams p) {
+  using St = Storage<S>;
+  using T = typename St::T;
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= p.nl) return;
+  const GridGeom& g = p.g;
+  const int ld = p.lk.lld[k];
+  const int i = ld >> 8;
+  const int ib = dyn_opp<L>(i);
+  const int64_t node = p.lk.lnode[k];
+  const int64_t row = node / g.nx;
+  const int x = (int)(node - row * g.nx);
+  int64_t slot;
+  if constexpr (COMPACT) {
+    const int64_t seg = row * g.nseg_x + x / SEG;
+    const uint64_t below = p.lk.seg_fluid[seg] & ((1ull << (x % SEG)) - 1ull);
+    slot = 1 + (int64_t)p.lk.seg_fbase[seg] + __popcll(below);
+  } else {
+    const int64_t y = row % g.ny, z = row / g.ny;
+    slot = (x + g.px) + (int64_t)g.NX * ((y + g.py) + (int64_t)g.NY * (z + g.pz));
+  }
+  const double w = dyn_w<L, double>(i);
+  const double fs = (double)St::template load<L>(static_cast<const T*>(p.pop) + (size_t)ib * g.npad + slot, ib) + w;
+  const double fn = (S == ST_F64 ? static_cast<const double*>(p.lk.lv_in)[k]
+                                 : (double)static_cast<const float*>(p.lk.lv_in)[k]) + w;
+  const double c[3] = {(double)dyn_c<L, 0>(i), (double)dyn_c<L, 1>(i), (double)dyn_c<L, 2>(i)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = p.luw ? p.luw[3 * k + a] : 0.0;
+    p.contrib[3 * k + a] = (-c[a] - u) * fs - (c[a] - u) * fn;
+  }
+}
+
+// Sum of the contributions of the links of group blockIdx.x (all links when
+// group is null), in a fixed order.
+__global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib, const int32_t* group, int64_t nl,
+                                                          double* out) {
+  __shared__ double sh[NPART][BLOCK];
+  double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int gid = blockIdx.x;
+  for (int64_t k = threadIdx.x; k < nl; k += BLOCK) {
+    if (group && group[k] != gid) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] += contrib[3 * k + a];
+  }
+  block_sum_fixed(sh, v, threadIdx.x);
+  if (threadIdx.x < 3) out[3 * gid + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 int64_t grid_blocks(const GridGeom& g) {
@@ -828,6 +885,18 @@ hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStr
 
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s) {
   LBM_DISPATCH3(macros_kernel, lattice, storage, p.g.compact, dim3((unsigned)nblocks), s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, const int32_t* group,
+                        double* out, hipStream_t s) {
+  if (p.nl > 0) {
+    const dim3 grid((unsigned)((p.nl + BLOCK - 1) / BLOCK));
+    LBM_DISPATCH3(force_kernel, lattice, storage, p.g.compact, grid, s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  group_sum_kernel<<<n_groups, BLOCK, 0, s>>>(p.contrib, group, p.nl, out);
   return hipGetLastError();
 }
 

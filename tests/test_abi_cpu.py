@@ -49,6 +49,7 @@ def _compare(mask, links, fluid, ol):
     assert np.array_equal(links["dir"], ol["dir"])
     assert np.abs(links["q"] - ol["q"]).max(initial=0) <= 1e-12
     assert np.abs(links["uw_t"].T - ol["uw_t"]).max(initial=0) <= 1e-14
+    assert np.array_equal(links["shape"], ol["shape"])
 
 
 def test_builder_matches_oracle_annulus(B):

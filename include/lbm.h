@@ -8,10 +8,12 @@
  * ------------------------------
  * - Lattice units throughout.  Node index n = x + nx * (y + ny * z),
  *   0 <= x < nx, 0 <= y < ny, 0 <= z < nz (nz == 1 for D2Q9).
- * - Direction order (both lattices; Sec. II.A uses the standard velocity sets):
+ * - Direction order (Sec. II.A uses the standard velocity sets):
  *     D2Q9   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(1,-1) 7:(-1,1) 8:(-1,-1)
  *     D3Q19  0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..10 = (+-1,+-1,0); 11..14 = (+-1,0,+-1);
  *            15..18 = (0,+-1,+-1); each group in sign order (+,+),(+,-),(-,+),(-,-).
+ *     D3Q27  0..18 as D3Q19; 19..26 = the corners (+-1,+-1,+-1) in sign order
+ *            (+,+,+),(+,+,-),(+,-,+),(+,-,-),(-,+,+),(-,+,-),(-,-,+),(-,-,-).
  * - Population arrays exchanged with the host are [Q][N] float64, N = nx*ny*nz.
  * - Host pointers passed in are caller-owned and only read (or written) during
  *   the call.  Device memory is library-owned unless the caller hands an arena.
@@ -41,7 +43,7 @@ enum {
   LBM_ESTATE = -5     /* call not valid in the domain's current state           */
 };
 
-enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 };
 
 /* Collision models (Sec. II.A): BGK (eq. LB-BGK) or TRT (TRT models paragraph).
  * With a body force, Guo's source term is split like the populations under TRT:
@@ -64,7 +66,7 @@ enum { LBM_FACE_NONE = -1 };
 typedef struct lbm_domain_s* lbm_domain;
 
 typedef struct {
-  int32_t lattice;       /* LBM_D2Q9 or LBM_D3Q19                                     */
+  int32_t lattice;       /* LBM_D2Q9, LBM_D3Q19 or LBM_D3Q27                          */
   int32_t nx, ny, nz;    /* lattice size; nz must be 1 for D2Q9                       */
   int32_t periodic;      /* bit0 x, bit1 y, bit2 z                                    */
   int32_t storage;       /* LBM_F64 / LBM_F32 / LBM_F16_SHIFTED / LBM_BF16_SHIFTED    */

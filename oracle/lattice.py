@@ -1,13 +1,15 @@
 """Discrete velocity sets used by the oracle (Sec. II.A).
 
 The paper fixes c_s^2 = 1/3 for the standard velocity sets (Sec. II.A, after
-eq. Maxwellian); the velocities and weights of D2Q9 and D3Q19 are the textbook
+eq. Maxwellian); the velocities and weights of D2Q9, D3Q19 and D3Q27 are the textbook
 Gauss-Hermite quadratures.  Direction order (shared by contract with the C-ABI,
 so that a (node, dir) pair means the same thing on both sides):
 
 D2Q9   0:(0,0) 1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1) 5:(1,1) 6:(1,-1) 7:(-1,1) 8:(-1,-1)
 D3Q19  0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..10 = (+-1,+-1,0); 11..14 = (+-1,0,+-1);
        15..18 = (0,+-1,+-1); each pair group in sign order (+,+),(+,-),(-,+),(-,-).
+D3Q27  0..18 as D3Q19; 19..26 = the corners (+-1,+-1,+-1), sign order
+       (+,+,+),(+,+,-),(+,-,+),(+,-,-),(-,+,+),(-,+,-),(-,-,+),(-,-,-).
 
 Status: pinned (moment identities and isotropy, tests/test_oracle_lattice.py).
 """
@@ -54,9 +56,17 @@ def _d3q19():
     return Lattice("D3Q19", 3, c, w)
 
 
+def _d3q27():
+    c = [tuple(v) for v in _d3q19().c.tolist()]
+    c += [(a, b, g) for a in (1, -1) for b in (1, -1) for g in (1, -1)]
+    w = ["8/27"] + ["2/27"] * 6 + ["1/54"] * 12 + ["1/216"] * 8
+    return Lattice("D3Q27", 3, c, w)
+
+
 D2Q9 = _d2q9()
 D3Q19 = _d3q19()
+D3Q27 = _d3q27()
 
 
 def get(name):
-    return {"D2Q9": D2Q9, "D3Q19": D3Q19}[name]
+    return {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q27": D3Q27}[name]

@@ -18,14 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LATTICES = {"D2Q9": 0, "D3Q19": 1}
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 LAYOUTS = {"compact": 0, "dense": 1}
 COLLISIONS = {"BGK": 0, "TRT": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
 FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
-Q_OF = {"D2Q9": 9, "D3Q19": 19}
-D_OF = {"D2Q9": 2, "D3Q19": 3}
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+D_OF = {"D2Q9": 2, "D3Q19": 3, "D3Q27": 3}
 
 EXPORTED = [
     "lbm_arena_bytes", "lbm_init_domain", "lbm_set_boundary_links", "lbm_step", "lbm_macros",

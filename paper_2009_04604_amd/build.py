@@ -19,7 +19,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I" + os
 # device code: gfx950 only; packed FP32 instructions disabled
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["kernels.hip", "moving.hip", "api.cpp", "batch.cpp", "geometry.cpp"]
+# (source, object name, extra flags): the lattice kernels are built once per
+# lattice; the D2Q9 build also holds the lattice-independent kernels and the
+# lattice dispatch
+SOURCES = [
+    ("kernels.hip", "kernels_d2q9.o", ["-DLBM_LATTICE=D2Q9", "-DLBM_COMMON"]),
+    ("kernels.hip", "kernels_d3q19.o", ["-DLBM_LATTICE=D3Q19"]),
+    ("kernels.hip", "kernels_d3q27.o", ["-DLBM_LATTICE=D3Q27"]),
+    ("moving.hip", "moving.o", []),
+    ("api.cpp", "api.o", []),
+    ("batch.cpp", "batch.o", []),
+    ("geometry.cpp", "geometry.o", []),
+]
 
 
 def _run(cmd):
@@ -35,10 +46,10 @@ def build(verbose=False):
     import concurrent.futures
     os.makedirs(BUILD_DIR, exist_ok=True)
     cmds, objs = [], []
-    for src in SOURCES:
+    for src, oname, extra in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(BUILD_DIR, src + ".o")
-        cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", "-o", obj, path]
+        obj = os.path.join(BUILD_DIR, oname)
+        cmd = [HIPCC, *COMMON, *DEVICE, *extra, "-x", "hip", "-c", "-o", obj, path]
         if src.endswith(".cpp"):
             # host builder: no FMA contraction, so that the geometry arithmetic
             # rounds exactly like the plain double-precision definition

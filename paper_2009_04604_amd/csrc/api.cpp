@@ -43,8 +43,8 @@ int fail(int code, const std::string& msg) { return set_error(code, msg); }
 
 struct Lat {
   int Q, D;
-  int c[19][3];
-  double w[19];
+  int c[27][3];
+  double w[27];
 };
 
 template <class L>
@@ -62,8 +62,8 @@ Lat make_lat() {
 }
 
 const Lat& lat_of(int lattice) {
-  static const Lat a = make_lat<D2Q9>(), b = make_lat<D3Q19>();
-  return lattice == LBM_D2Q9 ? a : b;
+  static const Lat a = make_lat<D2Q9>(), b = make_lat<D3Q19>(), c = make_lat<D3Q27>();
+  return lattice == LBM_D2Q9 ? a : (lattice == LBM_D3Q19 ? b : c);
 }
 
 template <typename P>
@@ -300,8 +300,8 @@ int64_t population_stride(const lbm_domain_desc* d, const uint8_t* mask) {
 }  // namespace
 
 size_t lbm_arena_bytes(const lbm_domain_desc* d, const uint8_t* fluid_mask) {
-  if (!d || (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19)) return 0;
-  const int Q = d->lattice == LBM_D2Q9 ? 9 : 19;
+  if (!d || (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19 && d->lattice != LBM_D3Q27)) return 0;
+  const int Q = d->lattice == LBM_D2Q9 ? 9 : (d->lattice == LBM_D3Q19 ? 19 : 27);
   const size_t one = (size_t)population_stride(d, fluid_mask) * Q * storage_bytes(d->storage);
   const size_t aligned = (one + 255) / 256 * 256;
   return 2 * aligned;
@@ -310,7 +310,8 @@ size_t lbm_arena_bytes(const lbm_domain_desc* d, const uint8_t* fluid_mask) {
 int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_domain* out) {
   if (!desc || !fluid_mask || !out) return fail(LBM_EINVAL, "null argument");
   const lbm_domain_desc& d = *desc;
-  if (d.lattice != LBM_D2Q9 && d.lattice != LBM_D3Q19) return fail(LBM_EINVAL, "lattice must be LBM_D2Q9 or LBM_D3Q19");
+  if (d.lattice != LBM_D2Q9 && d.lattice != LBM_D3Q19 && d.lattice != LBM_D3Q27)
+    return fail(LBM_EINVAL, "lattice must be LBM_D2Q9, LBM_D3Q19 or LBM_D3Q27");
   if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(LBM_EINVAL, "nx, ny, nz must be >= 1");
   if (d.lattice == LBM_D2Q9 && d.nz != 1) return fail(LBM_EINVAL, "nz must be 1 for D2Q9");
   if (d.storage < LBM_F64 || d.storage > LBM_BF16_SHIFTED) return fail(LBM_EINVAL, "invalid storage");

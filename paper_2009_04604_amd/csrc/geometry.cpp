@@ -49,7 +49,7 @@ struct lbm_geometry_s {
   std::vector<int8_t> dir;
   std::vector<double> q, uw;
   std::vector<int32_t> shape;    // owner of each link: spheres in order of addition, then faces
-  int c[19][3];
+  int c[27][3];
 };
 
 namespace {
@@ -118,15 +118,17 @@ extern "C" {
 int lbm_geometry_create(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, int32_t periodic, int32_t outlet_face,
                         lbm_geometry* out) {
   if (!out) return gfail(LBM_EINVAL, "null output");
-  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return gfail(LBM_EINVAL, "invalid lattice");
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q27) return gfail(LBM_EINVAL, "invalid lattice");
   if (nx < 1 || ny < 1 || nz < 1 || (lattice == LBM_D2Q9 && nz != 1)) return gfail(LBM_EINVAL, "invalid size");
   auto* g = new lbm_geometry_s();
   g->lattice = lattice;
   if (lattice == LBM_D2Q9) {
     fill_c<D2Q9>(g);
     periodic |= 4;
-  } else {
+  } else if (lattice == LBM_D3Q19) {
     fill_c<D3Q19>(g);
+  } else {
+    fill_c<D3Q27>(g);
   }
   g->n[0] = nx;
   g->n[1] = ny;

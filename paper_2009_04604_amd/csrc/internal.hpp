@@ -46,6 +46,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lattice.hpp"
 
 namespace lbm {
 
@@ -183,6 +184,23 @@ constexpr uint32_t TILE_EMPTY = ~0u;
 
 // Number of workgroups of the lattice kernels (a multiple of the 8 XCDs).
 int64_t grid_blocks(const GridGeom& g);
+
+// Per-lattice launchers (kernels.hip, compiled once per lattice and explicitly
+// instantiated there); the entry points below dispatch on the lattice.
+template <class L>
+struct Launch {
+  static hipError_t step(int storage, const StepParams& p, hipStream_t s);
+  static hipError_t step_batch(int storage, bool compact, bool trt, const StepParams* tab, const uint32_t* tiles,
+                               uint32_t nslots, uint32_t grid, hipStream_t s);
+  static hipError_t init(int storage, const InitParams& p, hipStream_t s);
+  static hipError_t init_links(int storage, const InitParams& p, hipStream_t s);
+  static hipError_t export_state(int storage, const ExportParams& p, hipStream_t s);
+  static hipError_t macros(int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
+  static hipError_t force(int storage, const ForceParams& p, hipStream_t s);
+};
+extern template struct Launch<D2Q9>;
+extern template struct Launch<D3Q19>;
+extern template struct Launch<D3Q27>;
 
 // Launchers (kernels.hip); dispatch on lattice and storage.
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s);

@@ -15,6 +15,10 @@
 #include "lattice.hpp"
 #include "storage.hpp"
 
+#ifndef LBM_LATTICE
+#error "kernels.hip is compiled once per lattice: -DLBM_LATTICE=D2Q9 | D3Q19 | D3Q27"
+#endif
+
 namespace lbm {
 
 struct Coords {
@@ -74,6 +78,7 @@ __device__ __forceinline__ int dyn_c(int i) {
 }
 template <class L, typename R>
 __device__ __forceinline__ R dyn_w(int i) {
+  if (L::Q == 27 && i >= 19) return R(L::w(19));
   return i == 0 ? R(L::w(0)) : (i <= 2 * L::D ? R(L::w(1)) : R(L::w(2 * L::D + 1)));
 }
 // opposite direction: axis pairs (1,2),(3,4),...; then groups of four sign pairs
@@ -81,21 +86,23 @@ template <class L>
 __device__ __forceinline__ int dyn_opp(int i) {
   if (i == 0) return 0;
   if (i <= 2 * L::D) return (i & 1) ? i + 1 : i - 1;
+  if (L::Q == 27 && i >= 19) return 45 - i;   // corners: every sign flips
   const int r = (i - 2 * L::D - 1) & 3;
   return i - r + (3 - r);
 }
 template <class L>
 constexpr bool dyn_tables_ok() {
   for (int i = 0; i < L::Q; ++i) {
+    const bool corner = L::Q == 27 && i >= 19;
     const int r = (i - 2 * L::D - 1) & 3;
-    const int o = i == 0 ? 0 : (i <= 2 * L::D ? ((i & 1) ? i + 1 : i - 1) : i - r + (3 - r));
+    const int o = i == 0 ? 0 : (i <= 2 * L::D ? ((i & 1) ? i + 1 : i - 1) : (corner ? 45 - i : i - r + (3 - r)));
     if (o != L::opp(i)) return false;
-    const double w = i == 0 ? L::w(0) : (i <= 2 * L::D ? L::w(1) : L::w(2 * L::D + 1));
+    const double w = corner ? L::w(19) : (i == 0 ? L::w(0) : (i <= 2 * L::D ? L::w(1) : L::w(2 * L::D + 1)));
     if (w != L::w(i)) return false;
   }
   return true;
 }
-static_assert(dyn_tables_ok<D2Q9>() && dyn_tables_ok<D3Q19>(), "run-time direction tables");
+static_assert(dyn_tables_ok<D2Q9>() && dyn_tables_ok<D3Q19>() && dyn_tables_ok<D3Q27>(), "run-time direction tables");
 
 // Moments of the shifted populations at one node.
 template <typename R>
@@ -712,6 +719,7 @@ __global__ __launch_bounds__(BLOCK) void macros_kernel(MacroParams p) {
   }
 }
 
+#ifdef LBM_COMMON
 __global__ __launch_bounds__(BLOCK) void reduce_kernel(const double* partials, int64_t nblocks, double* out) {
   __shared__ double sh[NPART][BLOCK];
   double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -722,6 +730,7 @@ __global__ __launch_bounds__(BLOCK) void reduce_kernel(const double* partials, i
   block_sum_fixed(sh, v, threadIdx.x);
   if (threadIdx.x < NPART) out[threadIdx.x] = sh[threadIdx.x][0];
 }
+#endif  // LBM_COMMON
 
 // ---------------------------------------------------------------------------
 // Momentum-exchange force of the last step (Sec. II "Force computation",
@@ -766,6 +775,7 @@ __global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams p) {
 
 // Sum of the contributions of the links of group blockIdx.x (all links when
 // group is null), in a fixed order.
+#ifdef LBM_COMMON
 __global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib, const int32_t* group, int64_t nl,
                                                           double* out) {
   __shared__ double sh[NPART][BLOCK];
@@ -779,15 +789,13 @@ __global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib,
   block_sum_fixed(sh, v, threadIdx.x);
   if (threadIdx.x < 3) out[3 * gid + threadIdx.x] = sh[threadIdx.x][0];
 }
+#endif  // LBM_COMMON
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launchers.  This file is compiled once per lattice (LBM_LATTICE names it);
+// Launch<LBM_LATTICE> is instantiated here.  The build defining LBM_COMMON
+// also holds the lattice-independent kernels and the lattice dispatch.
 // ---------------------------------------------------------------------------
-int64_t grid_blocks(const GridGeom& g) {
-  const int64_t b = (g.nseg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  return (b + 7) / 8 * 8;   // multiple of the XCD count, see logical_block()
-}
-
 #define LBM_DISPATCH_L(KERNEL, LAT, storage, C, grid, stream, ...)                                             \
   do {                                                                                                         \
     switch (storage) {                                                                                         \
@@ -798,102 +806,137 @@ int64_t grid_blocks(const GridGeom& g) {
     }                                                                                                          \
   } while (0)
 
-// lattice x storage x layout
-#define LBM_DISPATCH3(KERNEL, lattice, storage, compact, grid, stream, ...)                                    \
+// storage x layout
+#define LBM_DISPATCH_SC(KERNEL, LAT, storage, compact, grid, stream, ...)                                      \
   do {                                                                                                         \
-    if (lattice == LBM_D2Q9) {                                                                                 \
-      if (compact) LBM_DISPATCH_L(KERNEL, D2Q9, storage, true, grid, stream, __VA_ARGS__);                     \
-      else LBM_DISPATCH_L(KERNEL, D2Q9, storage, false, grid, stream, __VA_ARGS__);                            \
-    } else {                                                                                                   \
-      if (compact) LBM_DISPATCH_L(KERNEL, D3Q19, storage, true, grid, stream, __VA_ARGS__);                    \
-      else LBM_DISPATCH_L(KERNEL, D3Q19, storage, false, grid, stream, __VA_ARGS__);                           \
+    if (compact) LBM_DISPATCH_L(KERNEL, LAT, storage, true, grid, stream, __VA_ARGS__);                        \
+    else LBM_DISPATCH_L(KERNEL, LAT, storage, false, grid, stream, __VA_ARGS__);                               \
+  } while (0)
+
+// step kernels: storage x layout x collision
+#define LBM_STEP_L(KERNEL, LAT, storage, C, T, grid, stream, ...)                                              \
+  do {                                                                                                         \
+    switch (storage) {                                                                                         \
+      case ST_F64: KERNEL<LAT, ST_F64, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                  \
+      case ST_F32: KERNEL<LAT, ST_F32, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                  \
+      case ST_F16S: KERNEL<LAT, ST_F16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                \
+      default: KERNEL<LAT, ST_BF16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                    \
     }                                                                                                          \
   } while (0)
 
-// lattice x storage
-#define LBM_DISPATCH(KERNEL, lattice, storage, grid, stream, params)                              \
-  do {                                                                                            \
-    if (lattice == LBM_D2Q9) {                                                                    \
-      switch (storage) {                                                                          \
-        case ST_F64: KERNEL<D2Q9, ST_F64><<<grid, BLOCK, 0, stream>>>(params); break;             \
-        case ST_F32: KERNEL<D2Q9, ST_F32><<<grid, BLOCK, 0, stream>>>(params); break;             \
-        case ST_F16S: KERNEL<D2Q9, ST_F16S><<<grid, BLOCK, 0, stream>>>(params); break;           \
-        default: KERNEL<D2Q9, ST_BF16S><<<grid, BLOCK, 0, stream>>>(params); break;               \
-      }                                                                                           \
-    } else {                                                                                      \
-      switch (storage) {                                                                          \
-        case ST_F64: KERNEL<D3Q19, ST_F64><<<grid, BLOCK, 0, stream>>>(params); break;            \
-        case ST_F32: KERNEL<D3Q19, ST_F32><<<grid, BLOCK, 0, stream>>>(params); break;            \
-        case ST_F16S: KERNEL<D3Q19, ST_F16S><<<grid, BLOCK, 0, stream>>>(params); break;          \
-        default: KERNEL<D3Q19, ST_BF16S><<<grid, BLOCK, 0, stream>>>(params); break;              \
-      }                                                                                           \
-    }                                                                                             \
+#define LBM_STEP_SCT(KERNEL, LAT, storage, compact, trt, grid, stream, ...)                                    \
+  do {                                                                                                         \
+    if (compact) {                                                                                             \
+      if (trt) LBM_STEP_L(KERNEL, LAT, storage, true, true, grid, stream, __VA_ARGS__);                        \
+      else LBM_STEP_L(KERNEL, LAT, storage, true, false, grid, stream, __VA_ARGS__);                           \
+    } else {                                                                                                   \
+      if (trt) LBM_STEP_L(KERNEL, LAT, storage, false, true, grid, stream, __VA_ARGS__);                       \
+      else LBM_STEP_L(KERNEL, LAT, storage, false, false, grid, stream, __VA_ARGS__);                          \
+    }                                                                                                          \
   } while (0)
 
-// step kernels: lattice x storage x layout x collision
-#define LBM_STEP_L(KERNEL, LAT, storage, C, T, grid, stream, ...)                                      \
-  do {                                                                                              \
-    switch (storage) {                                                                              \
-      case ST_F64: KERNEL<LAT, ST_F64, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;       \
-      case ST_F32: KERNEL<LAT, ST_F32, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;       \
-      case ST_F16S: KERNEL<LAT, ST_F16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;     \
-      default: KERNEL<LAT, ST_BF16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;         \
-    }                                                                                               \
-  } while (0)
+template <class L>
+hipError_t Launch<L>::step(int storage, const StepParams& p, hipStream_t s) {
+  const dim3 grid((unsigned)grid_blocks(p.g));
+  LBM_STEP_SCT(step_kernel, L, storage, p.g.compact, p.trt, grid, s, p);
+  return hipGetLastError();
+}
 
-#define LBM_STEP_T(KERNEL, lattice, storage, compact, T, grid, stream, ...)                            \
-  do {                                                                                              \
-    if (lattice == LBM_D2Q9) {                                                                      \
-      if (compact) LBM_STEP_L(KERNEL, D2Q9, storage, true, T, grid, stream, __VA_ARGS__);           \
-      else LBM_STEP_L(KERNEL, D2Q9, storage, false, T, grid, stream, __VA_ARGS__);                  \
-    } else {                                                                                        \
-      if (compact) LBM_STEP_L(KERNEL, D3Q19, storage, true, T, grid, stream, __VA_ARGS__);          \
-      else LBM_STEP_L(KERNEL, D3Q19, storage, false, T, grid, stream, __VA_ARGS__);                 \
-    }                                                                                               \
-  } while (0)
+template <class L>
+hipError_t Launch<L>::step_batch(int storage, bool compact, bool trt, const StepParams* tab, const uint32_t* tiles,
+                                 uint32_t nslots, uint32_t grid, hipStream_t s) {
+  LBM_STEP_SCT(step_batch_kernel, L, storage, compact, trt, dim3(grid), s, tab, tiles, nslots);
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t Launch<L>::init(int storage, const InitParams& p, hipStream_t s) {
+  LBM_DISPATCH_SC(init_kernel, L, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t Launch<L>::init_links(int storage, const InitParams& p, hipStream_t s) {
+  const dim3 grid((unsigned)((p.nlinks + BLOCK - 1) / BLOCK));
+  switch (storage) {
+    case ST_F64: init_links_kernel<L, ST_F64><<<grid, BLOCK, 0, s>>>(p); break;
+    case ST_F32: init_links_kernel<L, ST_F32><<<grid, BLOCK, 0, s>>>(p); break;
+    case ST_F16S: init_links_kernel<L, ST_F16S><<<grid, BLOCK, 0, s>>>(p); break;
+    default: init_links_kernel<L, ST_BF16S><<<grid, BLOCK, 0, s>>>(p); break;
+  }
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t Launch<L>::export_state(int storage, const ExportParams& p, hipStream_t s) {
+  LBM_DISPATCH_SC(export_kernel, L, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t Launch<L>::macros(int storage, const MacroParams& p, int64_t nblocks, hipStream_t s) {
+  LBM_DISPATCH_SC(macros_kernel, L, storage, p.g.compact, dim3((unsigned)nblocks), s, p);
+  return hipGetLastError();
+}
+
+template <class L>
+hipError_t Launch<L>::force(int storage, const ForceParams& p, hipStream_t s) {
+  const dim3 grid((unsigned)((p.nl + BLOCK - 1) / BLOCK));
+  LBM_DISPATCH_SC(force_kernel, L, storage, p.g.compact, grid, s, p);
+  return hipGetLastError();
+}
+
+template struct Launch<LBM_LATTICE>;
+
+#ifdef LBM_COMMON
+int64_t grid_blocks(const GridGeom& g) {
+  const int64_t b = (g.nseg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  return (b + 7) / 8 * 8;   // multiple of the XCD count, see logical_block()
+}
+
+#define LBM_BY_LATTICE(lattice, CALL)                \
+  switch (lattice) {                                 \
+    case LBM_D2Q9: return Launch<D2Q9>::CALL;        \
+    case LBM_D3Q19: return Launch<D3Q19>::CALL;      \
+    default: return Launch<D3Q27>::CALL;             \
+  }
 
 hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_t s) {
-  const dim3 grid((unsigned)grid_blocks(p.g));
-  if (p.trt) LBM_STEP_T(step_kernel, lattice, storage, p.g.compact, true, grid, s, p);
-  else LBM_STEP_T(step_kernel, lattice, storage, p.g.compact, false, grid, s, p);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, step(storage, p, s));
 }
 
 hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, const StepParams* tab,
                              const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s) {
   if (nslots == 0 || grid == 0) return hipSuccess;
-  if (trt) LBM_STEP_T(step_batch_kernel, lattice, storage, compact, true, dim3(grid), s, tab, tiles, nslots);
-  else LBM_STEP_T(step_batch_kernel, lattice, storage, compact, false, dim3(grid), s, tab, tiles, nslots);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, step_batch(storage, compact, trt, tab, tiles, nslots, grid, s));
 }
 
 hipError_t launch_init(int lattice, int storage, const InitParams& p, hipStream_t s) {
-  LBM_DISPATCH3(init_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, init(storage, p, s));
 }
 
 hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipStream_t s) {
   if (p.nlinks == 0 || p.lk.lv_out == nullptr) return hipSuccess;
-  LBM_DISPATCH(init_links_kernel, lattice, storage, dim3((unsigned)((p.nlinks + BLOCK - 1) / BLOCK)), s, p);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, init_links(storage, p, s));
 }
 
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s) {
-  LBM_DISPATCH3(export_kernel, lattice, storage, p.g.compact, dim3((unsigned)grid_blocks(p.g)), s, p);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, export_state(storage, p, s));
 }
 
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s) {
-  LBM_DISPATCH3(macros_kernel, lattice, storage, p.g.compact, dim3((unsigned)nblocks), s, p);
-  return hipGetLastError();
+  LBM_BY_LATTICE(lattice, macros(storage, p, nblocks, s));
 }
 
 hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, const int32_t* group,
                         double* out, hipStream_t s) {
   if (p.nl > 0) {
-    const dim3 grid((unsigned)((p.nl + BLOCK - 1) / BLOCK));
-    LBM_DISPATCH3(force_kernel, lattice, storage, p.g.compact, grid, s, p);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    switch (lattice) {
+      case LBM_D2Q9: e = Launch<D2Q9>::force(storage, p, s); break;
+      case LBM_D3Q19: e = Launch<D3Q19>::force(storage, p, s); break;
+      default: e = Launch<D3Q27>::force(storage, p, s); break;
+    }
     if (e != hipSuccess) return e;
   }
   group_sum_kernel<<<n_groups, BLOCK, 0, s>>>(p.contrib, group, p.nl, out);
@@ -904,5 +947,6 @@ hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, h
   reduce_kernel<<<1, BLOCK, 0, s>>>(partials, nblocks, out);
   return hipGetLastError();
 }
+#endif  // LBM_COMMON
 
 }  // namespace lbm

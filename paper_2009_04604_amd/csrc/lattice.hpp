@@ -1,4 +1,4 @@
-// Velocity sets (D2Q9, D3Q19) as compile-time tables usable in host and device
+// Velocity sets (D2Q9, D3Q19, D3Q27) as compile-time tables usable in host and device
 // code.  c_s^2 = 1/3 (Sec. II.A).  Every loop over directions in the kernels is
 // fully unrolled, so the switch statements below fold to constants.
 #pragma once
@@ -50,6 +50,22 @@ struct D3Q19 {
   LBM_HD static constexpr double w(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 };
 
+struct D3Q27 {
+  static constexpr int Q = 27;
+  static constexpr int D = 3;
+  static constexpr int ID = 2;
+  // 0..18 as D3Q19; 19..26 the corners (+-1,+-1,+-1) in sign order
+  // (+,+,+),(+,+,-),(+,-,+),(+,-,-),(-,+,+),(-,+,-),(-,-,+),(-,-,-)
+  LBM_HD static constexpr int corner(int i, int bit) { return ((i - 19) >> bit) & 1 ? -1 : 1; }
+  LBM_HD static constexpr int cx(int i) { return i >= 19 ? corner(i, 2) : D3Q19::cx(i); }
+  LBM_HD static constexpr int cy(int i) { return i >= 19 ? corner(i, 1) : D3Q19::cy(i); }
+  LBM_HD static constexpr int cz(int i) { return i >= 19 ? corner(i, 0) : D3Q19::cz(i); }
+  LBM_HD static constexpr int opp(int i) { return i >= 19 ? 45 - i : D3Q19::opp(i); }
+  LBM_HD static constexpr double w(int i) {
+    return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+  }
+};
+
 // Compile-time self-checks of the tables.
 template <class L>
 constexpr bool lattice_tables_ok() {
@@ -63,3 +79,4 @@ constexpr bool lattice_tables_ok() {
 }
 static_assert(lattice_tables_ok<D2Q9>(), "D2Q9 table");
 static_assert(lattice_tables_ok<D3Q19>(), "D3Q19 table");
+static_assert(lattice_tables_ok<D3Q27>(), "D3Q27 table");

@@ -94,7 +94,7 @@ template <class L>
 __device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y, int z) {
   const GridGeom& g = p.g;
   uint32_t m = 0u;
-  // a node farther than r + 2 from the centre has no neighbour (|c_i| <= sqrt 2) in the sphere
+  // a node farther than r + 2 from the centre has no neighbour (|c_i| <= sqrt 3) in the sphere
   {
     double d[3];
     rel(p, (double)x, (double)y, (double)z, d);
@@ -342,7 +342,8 @@ static inline dim3 region_grid(const MovingParams& p) { return dim3((unsigned)((
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s) {
   if (p.nreg == 0) return hipSuccess;
   if (lattice == LBM_D2Q9) classify_kernel<D2Q9><<<region_grid(p), 256, 0, s>>>(p);
-  else classify_kernel<D3Q19><<<region_grid(p), 256, 0, s>>>(p);
+  else if (lattice == LBM_D3Q19) classify_kernel<D3Q19><<<region_grid(p), 256, 0, s>>>(p);
+  else classify_kernel<D3Q27><<<region_grid(p), 256, 0, s>>>(p);
   return hipGetLastError();
 }
 
@@ -357,9 +358,12 @@ hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, h
   if (lattice == LBM_D2Q9) {
     if (f64) fill_kernel<D2Q9, double><<<region_grid(p), 256, 0, s>>>(p);
     else fill_kernel<D2Q9, float><<<region_grid(p), 256, 0, s>>>(p);
-  } else {
+  } else if (lattice == LBM_D3Q19) {
     if (f64) fill_kernel<D3Q19, double><<<region_grid(p), 256, 0, s>>>(p);
     else fill_kernel<D3Q19, float><<<region_grid(p), 256, 0, s>>>(p);
+  } else {
+    if (f64) fill_kernel<D3Q27, double><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D3Q27, float><<<region_grid(p), 256, 0, s>>>(p);
   }
   return hipGetLastError();
 }
@@ -375,8 +379,10 @@ hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p,
   }
   if (lattice == LBM_D2Q9) {
     LBM_REFILL(D2Q9)
-  } else {
+  } else if (lattice == LBM_D3Q19) {
     LBM_REFILL(D3Q19)
+  } else {
+    LBM_REFILL(D3Q27)
   }
 #undef LBM_REFILL
   return hipGetLastError();
@@ -399,8 +405,10 @@ hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, h
   }
   if (lattice == LBM_D2Q9) {
     LBM_MOVING_BATCH(D2Q9)
-  } else {
+  } else if (lattice == LBM_D3Q19) {
     LBM_MOVING_BATCH(D3Q19)
+  } else {
+    LBM_MOVING_BATCH(D3Q27)
   }
 #undef LBM_MOVING_BATCH
   return hipGetLastError();

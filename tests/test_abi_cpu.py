@@ -84,3 +84,18 @@ def test_builder_matches_oracle_packing(B):
     fluid = G.classify(dom, sh)
     _compare(mask, links, fluid, G.cut_links(dom, fluid, sh))
     assert 0.55 < fluid.mean() < 0.65
+
+
+def test_builder_matches_oracle_packing_d3q27(B):
+    n = 40
+    c, r = synth.sphere_packing(n=n, r_min=3.0, r_max=6.0, solid_fraction=0.4, seed=12)
+    g = B.Geometry("D3Q27", n, n, n)
+    g.add_spheres(c, r)
+    mask, links = g.build()
+    g.close()
+    dom = G.Domain(lattice.D3Q27, n, n, n)
+    sh = [G.Sphere(cc, rr, True) for cc, rr in zip(c, r)]
+    fluid = G.classify(dom, sh)
+    _compare(mask, links, fluid, G.cut_links(dom, fluid, sh))
+    assert (links["dir"] >= 19).any()          # corner links exist
+

@@ -32,7 +32,7 @@ def _sphere_box(lat, variant, V=(0.0, 0.0, 0.0), rho=1.0, U=(0.0, 0.0, 0.0), tau
     return sim
 
 
-@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19], ids=lambda l: l.name)
+@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
 @pytest.mark.parametrize("variant", boundary.VARIANTS)
 def test_rest_state_is_fixed_point(lat, variant):
     sim = _sphere_box(lat, variant)
@@ -42,7 +42,7 @@ def test_rest_state_is_fixed_point(lat, variant):
     np.testing.assert_allclose(sim.f[:, fl], f0[:, fl], rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19], ids=lambda l: l.name)
+@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
 @pytest.mark.parametrize("variant", boundary.VARIANTS)
 def test_comoving_uniform_flow_is_fixed_point(lat, variant):
     U = (0.03, -0.02, 0.015 if lat.d == 3 else 0.0)
@@ -72,7 +72,7 @@ def _wrong_ladd(orig, lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1):
     return P
 
 
-@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19], ids=lambda l: l.name)
+@pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
 def test_periodic_conservation_and_guo_momentum(lat):
     rng = np.random.default_rng(3)
     nz = 1 if lat.d == 2 else 5

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import lattice, solver
 
-LATS = [lattice.D2Q9, lattice.D3Q19]
+LATS = [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27]
 
 
 @pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
@@ -38,7 +38,7 @@ def test_moment_identities_exact(lat):
 
 @pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
 def test_direction_table(lat):
-    assert lat.q == (9 if lat.name == "D2Q9" else 19)
+    assert lat.q == {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[lat.name]
     assert (lat.c[0] == 0).all()
     assert len({tuple(v) for v in lat.c}) == lat.q
     for i in range(lat.q):
@@ -51,6 +51,9 @@ def test_direction_table(lat):
         assert [tuple(v) for v in lat.c[7:11]] == [(1, 1, 0), (1, -1, 0), (-1, 1, 0), (-1, -1, 0)]
         assert [tuple(v) for v in lat.c[11:15]] == [(1, 0, 1), (1, 0, -1), (-1, 0, 1), (-1, 0, -1)]
         assert [tuple(v) for v in lat.c[15:19]] == [(0, 1, 1), (0, 1, -1), (0, -1, 1), (0, -1, -1)]
+        if lat.name == "D3Q27":
+            assert [tuple(v) for v in lat.c[19:]] == [(1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
+                                                     (-1, 1, 1), (-1, 1, -1), (-1, -1, 1), (-1, -1, -1)]
 
 
 @pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)

@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--workload", default="packing256", choices=["packing256", "channel2048"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
     ap.add_argument("--layout", default="compact", choices=["compact", "dense"])
+    ap.add_argument("--lattice", default="D3Q19", choices=["D3Q19", "D3Q27"],
+                    help="lattice of the packing workload")
+    ap.add_argument("--collision", default="BGK", choices=["BGK", "TRT"],
+                    help="collision model (TRT with the magic parameter 3/16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -79,14 +83,15 @@ def traffic_from_profile(workload, storage):
         return None
 
 
-def build_workload(name, storage, layout):
+def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK"):
     import synth
     from paper_2009_04604_amd import workloads as W
     if name == "packing256":
         n = 256
-        d, mask, links = W.packing_domain(n, storage, layout=layout)
-        cfg = {"workload": "sphere_packing_256^3_D3Q19", "lattice": "D3Q19", "n": [n, n, n], "porosity_target": 0.6,
-               "tau": 0.9, "force": [1e-6, 0, 0], "variant": "ELIBB-FQ", "storage": storage}
+        d, mask, links = W.packing_domain(n, storage, layout=layout, lattice=lattice, collision=collision)
+        cfg = {"workload": f"sphere_packing_256^3_{lattice}", "lattice": lattice, "n": [n, n, n],
+               "porosity_target": 0.6, "tau": 0.9, "force": [1e-6, 0, 0], "variant": "ELIBB-FQ", "storage": storage,
+               "collision": collision if collision == "BGK" else "TRT (Lambda 3/16)"}
     else:
         p = synth.cylinder_channel()
         d, mask, links = W.channel_domain(p, storage, layout=layout)
@@ -307,7 +312,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     log(f"main: building {a.workload} ({a.storage}, {a.layout})")
-    d, cfg = build_workload(a.workload, a.storage, a.layout)
+    d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision)
     log("main: timed steps")
     info = d.info()
     nfl = info["n_fluid"]
@@ -333,7 +338,7 @@ def main():
 
     mlups = nfl * a.steps / wall / 1e6
     achieved = bytes_per_update * nfl / (kernel_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(a.workload, a.storage)
+    traffic = traffic_from_profile(a.workload, a.storage) if (a.lattice, a.collision) == ("D3Q19", "BGK") else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_fluid_update": bytes_per_update,

@@ -34,8 +34,8 @@ def channel_geometry(p):
     return mask, links
 
 
-def packing_geometry(n, centres, radii):
-    g = B.Geometry("D3Q19", n, n, n)
+def packing_geometry(n, centres, radii, lattice="D3Q19"):
+    g = B.Geometry(lattice, n, n, n)
     g.add_spheres(centres, radii)
     mask, links = g.build()
     g.close()
@@ -58,10 +58,11 @@ def channel_domain(p, storage="f32", variant="FQ", layout="compact"):
 
 
 def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), variant="FQ", spheres=None,
-                   layout="compact"):
+                   layout="compact", lattice="D3Q19", collision="BGK", magic=3.0 / 16.0):
     centres, radii = synth.sphere_packing(n=n) if spheres is None else spheres
-    mask, links = packing_geometry(n, centres, radii)
-    d = B.Domain("D3Q19", n, n, n, mask, tau, storage=storage, force=force, layout=layout)
+    mask, links = packing_geometry(n, centres, radii, lattice)
+    d = B.Domain(lattice, n, n, n, mask, tau, storage=storage, force=force, layout=layout, collision=collision,
+                 magic=magic)
     d.set_boundary_links(links, variant=variant)
     return d, mask, links
 

@@ -47,7 +47,7 @@ def percentile(xs, p):
 
 class Job:
     __slots__ = ("req", "payload", "handle", "footprint", "arrival", "admitted", "finished", "steps_left",
-                 "result", "error")
+                 "result", "error", "started")
 
     def __init__(self, req):
         self.req = req
@@ -60,12 +60,13 @@ class Job:
         self.steps_left = int(req["steps"])
         self.result = None
         self.error = None
+        self.started = None                # plain form: when the server began working on it
 
     def record(self):
         tts = None if self.finished is None else self.finished - self.arrival
         return {"id": self.req["id"], "arrival": self.arrival, "admitted": self.admitted, "finished": self.finished,
                 "time_to_solution": tts, "footprint": self.footprint, "steps": int(self.req["steps"]),
-                "result": self.result, "error": self.error}
+                "result": self.result, "error": self.error, "started": self.started}
 
 
 class Server:
@@ -226,6 +227,7 @@ def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep):
         wait = j.arrival - (clock() - t0)
         if wait > 0:
             sleep(wait)
+        j.started = clock() - t0
         payload = executor.prepare(j.req)
         j.footprint = int(payload.footprint)
         h = executor.admit(payload)
@@ -237,6 +239,14 @@ def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep):
         j.steps_left = 0
         j.finished = clock() - t0
     return [j.record() for j in jobs]
+
+
+def busy_capacity(records):
+    """Solves per second of server busy time (plain form: one request at a time,
+    from when it started on a request to its read-back)."""
+    busy = sum(r["finished"] - r["started"] for r in records if r["started"] is not None and r["error"] is None)
+    n = sum(1 for r in records if r["started"] is not None and r["error"] is None)
+    return n / busy if busy > 0 else float("inf")
 
 
 def summarize(records, makespan=None):

@@ -183,3 +183,11 @@ def test_prepare_pool_gives_the_same_schedule():
         out.append(([(r["admitted"], r["finished"]) for r in recs], ex.admit_order))
         assert set(srv.phase) >= {"admit", "step_launch", "sync", "finish", "free"}
     assert out[0] == out[1]
+
+
+def test_plain_busy_capacity():
+    reqs = _reqs(n=10, rate=5.0)
+    clk = FakeClock()
+    recs = serve.run_plain(FakeExecutor(clk), reqs, clock=clk, sleep=clk.sleep)
+    service = [q["steps"] * (1e-3 + 1e-8 * q["nx"] * q["ny"]) for q in reqs]
+    assert serve.busy_capacity(recs) == pytest.approx(len(reqs) / sum(service))

@@ -159,18 +159,85 @@ def equilibrium_dir(lat, i, rho, u):
     return w * rho * (1.0 + cu / cs2 + (cu * cu - cs2 * uu) / (2.0 * cs2 * cs2))
 
 
-def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1):
+WALL_NEQ = ("bounceback", "regularized")
+
+
+def hermite2(lat, i):
+    """Second-order Hermite polynomial of directions i (App. Hermite):
+    H_ab = c_a c_b - cs2 delta_ab over the lattice's D axes.  Returns (n, D, D)."""
+    D = lat.d
+    c = lat.c[i][:, :D].astype(np.float64)
+    return np.einsum("na,nb->nab", c, c) - lat.cs2 * np.eye(D)[None]
+
+
+def hermite3(lat, i):
+    """Third-order Hermite polynomial of directions i (App. Hermite):
+    H_abg = c_a c_b c_g - cs2 (delta_ab c_g + delta_ag c_b + delta_bg c_a).
+    Returns (n, D, D, D)."""
+    D = lat.d
+    c = lat.c[i][:, :D].astype(np.float64)
+    I = np.eye(D)
+    ccc = np.einsum("na,nb,ng->nabg", c, c, c)
+    dc = (np.einsum("ab,ng->nabg", I, c) + np.einsum("ag,nb->nabg", I, c) + np.einsum("bg,na->nabg", I, c))
+    return ccc - lat.cs2 * dc
+
+
+def neq_stress(lat, f, feq):
+    """Non-equilibrium second moment Pi_ab = sum_j c_ja c_jb (f_j - f^eq_j) over
+    the lattice's D axes.  f, feq: (Q, n).  Returns (n, D, D)."""
+    D = lat.d
+    c = lat.c[:, :D].astype(np.float64)
+    return np.einsum("ja,jb,jn->nab", c, c, f - feq)
+
+
+def regularized_neq(lat, i, Pi, u):
+    """Non-equilibrium of directions i rebuilt from its Hermite expansion truncated
+    at third order (eq. fi_neq, App. C):
+        f_i^neq = w_i [ H_i2 : a2 / (2 cs2^2) + H_i3 : a3 / (6 cs2^3) ]
+    with a2 = Pi, the non-equilibrium stress, and a3 from the recursion of
+    eq. malaspinas at n = 3 (divided by rho):
+        a3_abg = u_a Pi_bg + u_b Pi_ag + u_g Pi_ab.
+    Reading: Pi stands for the first-order Hermite coefficient a^(1)_2; the stress
+    Lambda of eq. fi_neq is replaced through a^(1)_2 = -cs2 tau rho Lambda, the
+    relation under which the rebuilt non-equilibrium has second moment Pi (the
+    printed constants of eq. fi_neq and eq. a12Eqlambda disagree in sign and in a
+    factor cs2).  rho and tau then drop out.
+
+    i: (n,) directions; Pi: (n, D, D); u: (3, n) velocity.  Returns (n,).
+    """
+    D = lat.d
+    cs2 = lat.cs2
+    uD = np.asarray(u, dtype=np.float64)[:D].T                   # (n, D)
+    a3 = (np.einsum("na,nbg->nabg", uD, Pi) + np.einsum("nb,nag->nabg", uD, Pi)
+          + np.einsum("ng,nab->nabg", uD, Pi))
+    t2 = np.einsum("nab,nab->n", hermite2(lat, i), Pi) / (2.0 * cs2 ** 2)
+    t3 = np.einsum("nabg,nabg->n", hermite3(lat, i), a3) / (6.0 * cs2 ** 3)
+    return lat.w[i] * (t2 + t3)
+
+
+def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq="bounceback"):
     """The four interpolation quantities P0..P3 for links with missing direction i.
 
     i: (n,) missing directions; rho_F: (n,) density of node F at t;
     feq_F, f_F, fstar_F: (Q, n) equilibrium, pre- and post-collision populations
     of node F at time t; uw_t, uw_t1: (3, n) wall velocity at x_W at t and t+1.
+    wall_neq: how the wall non-equilibrium is estimated (Sec. II, "Approximation
+    of the wall populations"): "bounceback", the bounced non-equilibrium of F
+    (eq. neqbb-s), or "regularized", eq. fi_neq with the wall velocity and the
+    non-equilibrium stress of F (Lambda(x_W) ~ Lambda(x_F)): pre-collision for
+    P0 (with u_w(t+1)), post-collision for P1 (with u_w(t)).
     Returns P (4, n).
     """
     ib = lat.opp[i]
     n = np.arange(i.size)
-    n_pre = f_F[ib, n] - feq_F[ib, n]          # bounced pre-collision non-equilibrium (eq. neqbb-s)
-    n_post = fstar_F[ib, n] - feq_F[ib, n]     # bounced post-collision non-equilibrium
+    if wall_neq == "bounceback":
+        n_pre = f_F[ib, n] - feq_F[ib, n]          # bounced pre-collision non-equilibrium (eq. neqbb-s)
+        n_post = fstar_F[ib, n] - feq_F[ib, n]     # bounced post-collision non-equilibrium
+    elif wall_neq == "regularized":
+        n_pre = regularized_neq(lat, i, neq_stress(lat, f_F, feq_F), uw_t1)
+        n_post = regularized_neq(lat, i, neq_stress(lat, fstar_F, feq_F), uw_t)
+    else:
+        raise ValueError(f"unknown wall non-equilibrium {wall_neq!r}")
     P0 = equilibrium_dir(lat, i, rho_F, uw_t1) + n_pre
     P1 = equilibrium_dir(lat, i, rho_F, uw_t) + n_post
     cu_w = (lat.c[i].T.astype(np.float64) * uw_t).sum(axis=0)

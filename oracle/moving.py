@@ -38,9 +38,10 @@ class Kinematics:
 
 
 class MovingSphereSim:
-    def __init__(self, dom, radius, kin, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
+    def __init__(self, dom, radius, kin, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None,
+                 wall_neq="bounceback"):
         self.dom, self.radius, self.kin = dom, float(radius), kin
-        self.variant, self.q_cut = variant, q_cut
+        self.variant, self.q_cut, self.wall_neq = variant, q_cut, wall_neq
         self.sim = Simulation(dom, tau, rho0=rho0, u0=u0, magic=magic)
         self.t = 0
         self._install(first=True)
@@ -64,7 +65,7 @@ class MovingSphereSim:
         if not first:
             X = self.dom.coords().astype(np.float64)
             self.sim.refill(fluid, sph.velocity(self.dom, X))
-        self.sim.set_geometry(fluid, links, self.variant, self.q_cut)
+        self.sim.set_geometry(fluid, links, self.variant, self.q_cut, wall_neq=self.wall_neq)
 
     def step(self):
         self.sim.step()

@@ -118,12 +118,15 @@ class Simulation:
         self.n_groups = 1
 
     # -- geometry -----------------------------------------------------------------
-    def set_geometry(self, fluid, links, variant="FQ", q_cut=0.01):
-        """Install a fluid mask and a cut-link list (dict from oracle.geometry.cut_links)."""
+    def set_geometry(self, fluid, links, variant="FQ", q_cut=0.01, wall_neq="bounceback"):
+        """Install a fluid mask and a cut-link list (dict from oracle.geometry.cut_links).
+        wall_neq: the wall non-equilibrium estimator (see boundary.link_points)."""
         dom, lat = self.dom, self.lat
         fl = np.asarray(fluid, dtype=bool).reshape(-1)
+        if wall_neq not in boundary.WALL_NEQ:
+            raise ValueError(f"unknown wall non-equilibrium {wall_neq!r}")
         self.fluid = fl
-        self.variant, self.q_cut = variant, float(q_cut)
+        self.variant, self.q_cut, self.wall_neq = variant, float(q_cut), wall_neq
         L = {k: np.asarray(v) for k, v in links.items()}
         self.links = L
         self.coef = boundary.coefficients(variant, L["q"], q_cut)
@@ -194,7 +197,8 @@ class Simulation:
         L = self.links
         if L["node"].size:
             n, d = L["node"], L["dir"]
-            P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"])
+            P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"],
+                                     self.wall_neq)
             fnew[d, n] = boundary.reconstruct(self.coef, P)
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
             self.last_force = boundary.momentum_exchange(lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp,
@@ -251,7 +255,8 @@ class Simulation:
         return idx
 
 
-def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01, magic=None):
+def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01, magic=None,
+            wall_neq="bounceback"):
     """f(x, t+1) at the given fluid nodes only, from the full state f (Q, N) at t.
 
     The same step as Simulation.step, evaluated node by node: every pulled
@@ -297,6 +302,6 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
             li = order[k[sel]]
             coef = boundary.coefficients(variant, L["q"][li], q_cut)
             P = boundary.link_points(lat, np.full(sel.size, i), rho_s[sel], feq_s[:, sel], f[:, nodes[sel]],
-                                     fs_self[:, sel], L["uw_t"][:, li], L["uw_t1"][:, li])
+                                     fs_self[:, sel], L["uw_t"][:, li], L["uw_t1"][:, li], wall_neq)
             out[i, sel] = boundary.reconstruct(coef, P)
     return out

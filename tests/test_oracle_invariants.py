@@ -3,7 +3,8 @@
 * rest state f = f^eq(rho0, 0) with resting walls is a fixed point for every
   variant and any q;
 * co-moving uniform flow f = f^eq(rho, U) with every wall moving at U is a
-  fixed point for every variant and any q, at rho != 1 (pins the wall
+  fixed point for every variant and any q, at rho != 1, with either wall
+  non-equilibrium estimator (pins the wall
   equilibria at rho_F, the Ladd term of eq. ME-solid-to-fluid with rho_F, and
   the partition of unity of the coefficients);
 * a periodic all-fluid box conserves mass and momentum; Guo forcing adds
@@ -18,7 +19,8 @@ from oracle import boundary, geometry as G, lattice, solver
 from tests import cases
 
 
-def _sphere_box(lat, variant, V=(0.0, 0.0, 0.0), rho=1.0, U=(0.0, 0.0, 0.0), tau=0.7, n=(14, 12, 10)):
+def _sphere_box(lat, variant, V=(0.0, 0.0, 0.0), rho=1.0, U=(0.0, 0.0, 0.0), tau=0.7, n=(14, 12, 10),
+                wall_neq="bounceback"):
     nz = 1 if lat.d == 2 else n[2]
     dom = G.Domain(lat, n[0], n[1], nz)
     centre = (6.3, 5.6, 4.7 if lat.d == 3 else 0.0)
@@ -27,26 +29,28 @@ def _sphere_box(lat, variant, V=(0.0, 0.0, 0.0), rho=1.0, U=(0.0, 0.0, 0.0), tau
     links = G.cut_links(dom, fluid, [sph])
     assert links["q"].min() < 0.3 and links["q"].max() > 0.7
     sim = solver.Simulation(dom, tau, rho0=rho, u0=U)
-    sim.set_geometry(fluid, links, variant)
+    sim.set_geometry(fluid, links, variant, wall_neq=wall_neq)
     sim.init_equilibrium()
     return sim
 
 
+@pytest.mark.parametrize("wall_neq", boundary.WALL_NEQ)
 @pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
 @pytest.mark.parametrize("variant", boundary.VARIANTS)
-def test_rest_state_is_fixed_point(lat, variant):
-    sim = _sphere_box(lat, variant)
+def test_rest_state_is_fixed_point(lat, variant, wall_neq):
+    sim = _sphere_box(lat, variant, wall_neq=wall_neq)
     f0 = sim.f.copy()
     sim.run(25)
     fl = sim.fluid
     np.testing.assert_allclose(sim.f[:, fl], f0[:, fl], rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("wall_neq", boundary.WALL_NEQ)
 @pytest.mark.parametrize("lat", [lattice.D2Q9, lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
 @pytest.mark.parametrize("variant", boundary.VARIANTS)
-def test_comoving_uniform_flow_is_fixed_point(lat, variant):
+def test_comoving_uniform_flow_is_fixed_point(lat, variant, wall_neq):
     U = (0.03, -0.02, 0.015 if lat.d == 3 else 0.0)
-    sim = _sphere_box(lat, variant, V=U, rho=1.1, U=U)
+    sim = _sphere_box(lat, variant, V=U, rho=1.1, U=U, wall_neq=wall_neq)
     f0 = sim.f.copy()
     sim.run(25)
     fl = sim.fluid
@@ -65,8 +69,8 @@ def test_comoving_flow_breaks_without_ladd_density(monkeypatch):
     assert np.abs(sim.f[:, sim.fluid] - f0[:, sim.fluid]).max() > 1e-6
 
 
-def _wrong_ladd(orig, lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1):
-    P = orig(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1)
+def _wrong_ladd(orig, lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq="bounceback"):
+    P = orig(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq)
     cu = (lat.c[i].T * uw_t).sum(0)
     P[2] += 2.0 * lat.w[i] * (1.0 - rho_F) * cu / lat.cs2
     return P

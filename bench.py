@@ -44,6 +44,8 @@ def parse():
                     help="lattice of the packing workload")
     ap.add_argument("--collision", default="BGK", choices=["BGK", "TRT"],
                     help="collision model (TRT with the magic parameter 3/16)")
+    ap.add_argument("--wall-neq", default="bounceback", choices=["bounceback", "regularized"],
+                    help="wall non-equilibrium estimator of the ELIBB links")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -83,21 +85,23 @@ def traffic_from_profile(workload, storage):
         return None
 
 
-def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK"):
+def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK", wall_neq="bounceback"):
     import synth
     from paper_2009_04604_amd import workloads as W
     if name == "packing256":
         n = 256
-        d, mask, links = W.packing_domain(n, storage, layout=layout, lattice=lattice, collision=collision)
+        d, mask, links = W.packing_domain(n, storage, layout=layout, lattice=lattice, collision=collision,
+                                          wall_neq=wall_neq)
         cfg = {"workload": f"sphere_packing_256^3_{lattice}", "lattice": lattice, "n": [n, n, n],
                "porosity_target": 0.6, "tau": 0.9, "force": [1e-6, 0, 0], "variant": "ELIBB-FQ", "storage": storage,
                "collision": collision if collision == "BGK" else "TRT (Lambda 3/16)"}
     else:
         p = synth.cylinder_channel()
-        d, mask, links = W.channel_domain(p, storage, layout=layout)
+        d, mask, links = W.channel_domain(p, storage, layout=layout, wall_neq=wall_neq)
         cfg = {"workload": "cylinder_channel_2048x1024_D2Q9", "lattice": "D2Q9", "n": [p["nx"], p["ny"], 1],
                "reynolds": 100, "tau": p["tau"], "variant": "ELIBB-FQ", "storage": storage}
     cfg["layout"] = layout
+    cfg["wall_neq"] = wall_neq
     return d, cfg
 
 
@@ -122,7 +126,7 @@ def copy_bandwidth(gib=2, reps=5):
     return round(2.0 * gib * 2**30 / (ms * 1e-3) / 1e9, 1)
 
 
-def cpu_baseline(name, seconds):
+def cpu_baseline(name, seconds, wall_neq="bounceback"):
     """Time the FP64 oracle on one core on a bounded sample of the workload recipe."""
     try:
         from threadpoolctl import threadpool_limits
@@ -140,7 +144,7 @@ def cpu_baseline(name, seconds):
             sh = [G.Sphere(cc, rr, True) for cc, rr in zip(c, r)]
             fluid = G.classify(dom, sh)
             sim = solver.Simulation(dom, 0.9, force=(1e-6, 0, 0))
-            sim.set_geometry(fluid, G.cut_links(dom, fluid, sh), "FQ")
+            sim.set_geometry(fluid, G.cut_links(dom, fluid, sh), "FQ", wall_neq=wall_neq)
             sample = f"same recipe (largest-first RSA, radii U[6,12], porosity 0.6) in a periodic {n}^3 box, FP64 oracle"
         else:
             p = synth.cylinder_channel(nx=512, ny=256, radius=5.0, centre=(100.0, 128.0))
@@ -149,7 +153,7 @@ def cpu_baseline(name, seconds):
             faces = [G.FaceWall(0, 0.5, G.parabolic_inlet(p["ny"], p["u_max"])), G.FaceWall(2, 0.5), G.FaceWall(3, 0.5)]
             fluid = G.classify(dom, [cyl])
             sim = solver.Simulation(dom, p["tau"])
-            sim.set_geometry(fluid, G.cut_links(dom, fluid, [cyl], faces), "FQ")
+            sim.set_geometry(fluid, G.cut_links(dom, fluid, [cyl], faces), "FQ", wall_neq=wall_neq)
             sample = "cylinder channel at 512x256 (same recipe scaled), FP64 oracle"
         sim.init_equilibrium()
         sim.step()
@@ -324,7 +328,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     log(f"main: building {a.workload} ({a.storage}, {a.layout})")
-    d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision)
+    d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision, a.wall_neq)
     log("main: timed steps")
     info = d.info()
     nfl = info["n_fluid"]
@@ -350,7 +354,7 @@ def main():
 
     mlups = nfl * a.steps / wall / 1e6
     achieved = bytes_per_update * nfl / (kernel_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(a.workload, a.storage) if (a.lattice, a.collision) == ("D3Q19", "BGK") else None
+    traffic = traffic_from_profile(a.workload, a.storage) if (a.lattice, a.collision, a.wall_neq) == ("D3Q19", "BGK", "bounceback") else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_fluid_update": bytes_per_update,
@@ -374,7 +378,7 @@ def main():
     if not a.no_served:
         out["served_batch"] = served_section(a, log)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds, a.wall_neq)
     print(json.dumps(out), flush=True)
     if a.calibration_copy_mib > 0:
         n = a.calibration_copy_mib * 2**20 // 4

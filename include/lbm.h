@@ -60,6 +60,13 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFTED = 2, LBM_BF16_SHIFTED = 3 };
  * moving-wall term (eq. ME-solid-to-fluid). */
 enum { LBM_ELIBB_FQ = 0, LBM_ELIBB_F = 1, LBM_ELIBB_UQ = 2, LBM_ELIBB_U = 3, LBM_HWBB = 4 };
 
+/* Estimators of the non-equilibrium part of the wall populations (Sec. II,
+ * approximation of the wall populations; App. C): the bounced non-equilibrium
+ * of the boundary node (eq. neqbb-s, the default), or the regularised one
+ * rebuilt from the node's non-equilibrium stress and the wall velocity
+ * (eq. fi_neq). */
+enum { LBM_NEQ_BOUNCEBACK = 0, LBM_NEQ_REGULARIZED = 1 };
+
 /* Domain faces: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z. */
 enum { LBM_FACE_NONE = -1 };
 
@@ -123,6 +130,22 @@ int lbm_init_domain(const lbm_domain_desc* d, const uint8_t* fluid_mask, lbm_dom
 int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir,
                            const double* q, const double* uw_t, const double* uw_t1,
                            int32_t variant, double q_cutoff);
+
+/* Selects the wall non-equilibrium estimator of every cut link of the domain
+ * (eq. ELIBB-approximations).  LBM_NEQ_BOUNCEBACK: f_i^neq(x_W) is taken as the
+ * bounced non-equilibrium f_ibar - f^eq_ibar of the boundary node F (eq.
+ * neqbb-s), pre-collision for the wall population at t+1 and post-collision for
+ * the post-collision one.  LBM_NEQ_REGULARIZED: f_i^neq(x_W) is the third-order
+ * Hermite reconstruction of eq. fi_neq,
+ *   w_i [ 9/2 H_i2 : Pi + 27/2 H_i3 : (u_w Pi) ]  (c_s^2 = 1/3),
+ * with Pi the non-equilibrium stress sum_j c_j c_j (f_j - f^eq_j) of node F
+ * (the stress at the wall taken as the stress at F) -- before collision, with
+ * u_w(t+1), for the wall population at t+1; after collision, with u_w(t), for
+ * the post-collision one.  Takes effect from the next step and stays when the
+ * links are replaced.  Any lattice, storage, collision and layout; for a moving
+ * sphere it must be chosen before lbm_set_moving_sphere.  Errors: LBM_EINVAL for
+ * an unknown mode, LBM_ESTATE on a domain that already has a moving sphere. */
+int lbm_set_wall_neq(lbm_domain d, int32_t mode);
 
 /* A rigid sphere in prescribed motion (Sec. II.E moving boundaries): centre
  * x_c(t) = x0 + amplitude sin(2 pi t / period) direction, translational velocity

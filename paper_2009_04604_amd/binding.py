@@ -23,6 +23,7 @@ LAYOUTS = {"compact": 0, "dense": 1}
 COLLISIONS = {"BGK": 0, "TRT": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
 VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
+WALL_NEQ = {"bounceback": 0, "regularized": 1}
 FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 D_OF = {"D2Q9": 2, "D3Q19": 3, "D3Q27": 3}
@@ -34,6 +35,7 @@ EXPORTED = [
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
+    "lbm_set_wall_neq",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -107,6 +109,7 @@ def lib():
         "lbm_set_link_groups": (I32, [P, P, I32]),
         "lbm_momentum_exchange": (I32, [P, P]),
         "lbm_geometry_get_shapes": (I32, [P, P]),
+        "lbm_set_wall_neq": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -298,6 +301,12 @@ class Domain:
         g = None if group is None else np.ascontiguousarray(group, dtype=np.int32)
         _check(lib().lbm_set_link_groups(self.h, _ptr(g), int(n_groups)))
         self._n_groups = int(n_groups)
+
+    def set_wall_neq(self, mode):
+        """Wall non-equilibrium estimator: "bounceback" (eq. neqbb-s) or
+        "regularized" (eq. fi_neq)."""
+        m = WALL_NEQ[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().lbm_set_wall_neq(self.h, m))
 
     def force(self):
         """(n_groups, 3) momentum-exchange force of the last step (FP64)."""

@@ -131,6 +131,8 @@ LinkView link_view(const lbm_domain_s* d, const void* lv_in, void* lv_out) {
   lk.lg = d->lg;
   lk.lv_in = lv_in;
   lk.lv_out = lv_out;
+  lk.luv = d->luv;
+  lk.luv_stride = d->moving ? d->link_cap : d->nl;
   return lk;
 }
 
@@ -153,6 +155,7 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.variant = d->variant;
   p.q_cut = d->q_cut;
   p.outlet_face = d->desc.outlet_face;
+  p.wall_neq = d->wall_neq;
   return p;
 }
 
@@ -192,6 +195,8 @@ MovingParams moving_params(const lbm_domain_s* d, int cur) {
   mp.lld = d->lld;
   mp.lq = d->lq;
   mp.lg = d->lg;
+  mp.luv = d->luv;
+  mp.luv_stride = d->link_cap;
   mp.pop = d->buf[cur];
   mp.rho0 = d->desc.rho0;
   return mp;
@@ -269,6 +274,7 @@ void free_links(lbm_domain_s* d) {
   dfree(d->lv[1]);
   dfree(d->lq);
   dfree(d->lg);
+  dfree(d->luv);
   dfree(d->luw);
   dfree(d->lgrp);
   dfree(d->lforce);
@@ -554,8 +560,10 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
     if (int e = dalloc(d->lq, qd.size() * rs)) return e;
     if (int e = dalloc(d->lv[0], qd.size() * rs)) return e;
     if (int e = dalloc(d->lv[1], qd.size() * rs)) return e;
-    if (moving)
+    if (moving) {
       if (int e = dalloc(d->lg, gd.size() * rs)) return e;
+      if (int e = dalloc(d->luv, 6 * qd.size() * rs)) return e;
+    }
     HIP_TRY(hipMemcpy(d->lld, lld.data(), lld.size() * 2, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d->lnode, lnode.data(), lnode.size() * 4, hipMemcpyHostToDevice));
     auto upload_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
@@ -564,7 +572,20 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
       return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
     };
     HIP_TRY(upload_real(d->lq, qd));
-    if (moving) HIP_TRY(upload_real(d->lg, gd));
+    if (moving) {
+      HIP_TRY(upload_real(d->lg, gd));
+      // u_w(t) and u_w(t+1) of every stored link, [6][nl] (regularised wall non-equilibrium)
+      std::vector<double> uv(6 * (size_t)n_links, 0.0);
+      for (int64_t k = 0; k < n_links; ++k) {
+        const int64_t o = order[k];
+        for (int a = 0; a < L.D; ++a) {
+          const double v0 = uw_t ? uw_t[3 * o + a] : 0.0;
+          uv[a * n_links + k] = v0;
+          uv[(3 + a) * n_links + k] = uw_t1 ? uw_t1[3 * o + a] : v0;
+        }
+      }
+      HIP_TRY(upload_real(d->luv, uv));
+    }
     HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d->seg_lbase, slb.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice));
     // wall velocities at t, for the momentum-exchange force (only when a wall moves)
@@ -593,6 +614,19 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   d->q_cut = q_cutoff;
   d->links_ok = true;
   d->uid = next_uid();
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_set_wall_neq(lbm_domain d, int32_t mode) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (mode != LBM_NEQ_BOUNCEBACK && mode != LBM_NEQ_REGULARIZED)
+    return fail(LBM_EINVAL, "invalid wall non-equilibrium mode " + std::to_string(mode));
+  if (d->moving) return fail(LBM_ESTATE, "choose the wall non-equilibrium before lbm_set_moving_sphere");
+  if (mode != d->wall_neq) {
+    d->wall_neq = mode;
+    d->uid = next_uid();   // batches rebuild their tables
+  }
   clear_error();
   return LBM_OK;
 }
@@ -653,6 +687,8 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   if (int e = dalloc(d->lld, d->link_cap * 2)) return e;
   if (int e = dalloc(d->lq, d->link_cap * rs)) return e;
   if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
+  if (d->wall_neq == LBM_NEQ_REGULARIZED)
+    if (int e = dalloc(d->luv, 6 * d->link_cap * rs)) return e;
   HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));

@@ -60,6 +60,7 @@ struct Group {
   int lattice = 0, storage = 0;
   bool compact = false;
   bool trt = false;
+  bool reg = false;                  // regularised wall non-equilibrium
   std::vector<int> members;          // indices into the batch's member list
   std::vector<int> movers;           // members with a moving sphere
   DBuf tab[2], tiles, mtab[2], waves;
@@ -76,8 +77,8 @@ struct lbm_batch_s {
   bool use_graph = true;
   bool autotune = false;
   Choice forced{-1, -1};             // set by options; -1 = tuned or default
-  std::map<std::tuple<int, int, int, int, int>, Choice> tuned;
-  std::map<std::tuple<int, int, int, int, int>, double> tuned_us;
+  std::map<std::tuple<int, int, int, int, int, int>, Choice> tuned;
+  std::map<std::tuple<int, int, int, int, int, int>, double> tuned_us;
   // composition
   std::vector<lbm_domain> members;
   std::vector<uint64_t> member_uid;  // identity of each member when the tables were built
@@ -158,10 +159,10 @@ int commit(lbm_batch_s* b, const std::vector<Upload>& ups) {
 
 uint32_t blocks_of(const lbm_domain_s* d) { return (uint32_t)((d->g.nseg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK); }
 
-std::tuple<int, int, int, int, int> shape_key(const Group& g) {
+std::tuple<int, int, int, int, int, int> shape_key(const Group& g) {
   int lg = 0;
   while ((1u << (lg + 1)) <= std::max<uint32_t>(g.ntiles, 1)) ++lg;
-  return {g.lattice, g.storage, g.compact ? 1 : 0, g.trt ? 1 : 0, lg};
+  return {g.lattice, g.storage, g.compact ? 1 : 0, g.trt ? 1 : 0, g.reg ? 1 : 0, lg};
 }
 
 // Tile table of a group for one launch choice (see the kernel's comment).
@@ -283,7 +284,8 @@ int write_tables(lbm_batch_s* b) {
 std::vector<int64_t> launch_signature(const lbm_batch_s* b) {
   std::vector<int64_t> s;
   for (const Group& g : b->groups) {
-    for (int64_t v : {(int64_t)g.lattice, (int64_t)g.storage, (int64_t)g.compact, (int64_t)g.trt, (int64_t)(intptr_t)g.tab[0].p,
+    for (int64_t v : {(int64_t)g.lattice, (int64_t)g.storage, (int64_t)g.compact, (int64_t)g.trt, (int64_t)g.reg,
+                      (int64_t)(intptr_t)g.tab[0].p,
                       (int64_t)(intptr_t)g.tab[1].p, (int64_t)(intptr_t)g.tiles.p, (int64_t)g.nslots, (int64_t)g.grid,
                       (int64_t)g.movers.size(), (int64_t)(intptr_t)g.mtab[0].p, (int64_t)(intptr_t)g.mtab[1].p,
                       (int64_t)(intptr_t)g.waves.p, (int64_t)g.nwaves})
@@ -299,7 +301,7 @@ std::vector<int64_t> launch_signature(const lbm_batch_s* b) {
 // tables were written for, p = 1: in the other ones.
 hipError_t enqueue_step(lbm_batch_s* b, int p, hipStream_t s) {
   for (const Group& g : b->groups) {
-    hipError_t e = launch_step_batch(g.lattice, g.storage, g.compact, g.trt, static_cast<const StepParams*>(g.tab[p].p),
+    hipError_t e = launch_step_batch(g.lattice, g.storage, g.compact, g.trt, g.reg, static_cast<const StepParams*>(g.tab[p].p),
                                      static_cast<const uint32_t*>(g.tiles.p), g.nslots, g.grid, s);
     if (e != hipSuccess) return e;
   }
@@ -399,9 +401,10 @@ int prepare(lbm_batch_s* b, const lbm_domain* ds, int32_t n) {
       const lbm_domain_s* d = ds[k];
       Group* g = nullptr;
       const bool trt = d->desc.collision == LBM_TRT;
+      const bool reg = d->wall_neq == LBM_NEQ_REGULARIZED;
       for (Group& x : b->groups)
         if (x.lattice == d->desc.lattice && x.storage == d->desc.storage && x.compact == (d->g.compact != 0) &&
-            x.trt == trt)
+            x.trt == trt && x.reg == reg)
           g = &x;
       if (!g) {
         b->groups.emplace_back();
@@ -410,6 +413,7 @@ int prepare(lbm_batch_s* b, const lbm_domain* ds, int32_t n) {
         g->storage = d->desc.storage;
         g->compact = d->g.compact != 0;
         g->trt = trt;
+        g->reg = reg;
       }
       if ((int)g->members.size() >= MAX_GROUP_DOMAINS) return bfail(LBM_EINVAL, "too many domains of one kind in a batch");
       if (d->moving) g->movers.push_back((int)g->members.size());

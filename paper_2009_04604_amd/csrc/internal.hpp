@@ -94,6 +94,9 @@ struct LinkView {
   const void* lg;                // link wall term Gw, or null when every wall rests
   const void* lv_in;             // link values at t (null: slot mode)
   void* lv_out;                  // link values at t+1
+  const void* luv;               // [6][luv_stride] wall velocities u_w(t), u_w(t+1) per link
+                                 // (regularised wall non-equilibrium with moving walls), or null
+  int64_t luv_stride;
 };
 
 struct StepParams {
@@ -109,6 +112,8 @@ struct StepParams {
   int32_t variant;
   double q_cut;
   int32_t outlet_face;
+  int32_t wall_neq;              // 0: bounced non-equilibrium (eq. neqbb-s); 1: regularised (eq. fi_neq);
+                                 // selects the kernel variant (batches group by it)
 };
 
 struct InitParams {
@@ -173,6 +178,9 @@ struct MovingParams {
   uint16_t* lld;
   void* lq;
   void* lg;
+  void* luv;                     // [6][luv_stride] wall velocities per link (regularised wall
+                                 // non-equilibrium), or null
+  int64_t luv_stride;            // link capacity
   void* pop;                     // current population buffer (refill)
   double rho0;
 };
@@ -190,8 +198,8 @@ int64_t grid_blocks(const GridGeom& g);
 template <class L>
 struct Launch {
   static hipError_t step(int storage, const StepParams& p, hipStream_t s);
-  static hipError_t step_batch(int storage, bool compact, bool trt, const StepParams* tab, const uint32_t* tiles,
-                               uint32_t nslots, uint32_t grid, hipStream_t s);
+  static hipError_t step_batch(int storage, bool compact, bool trt, bool reg, const StepParams* tab,
+                               const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s);
   static hipError_t init(int storage, const InitParams& p, hipStream_t s);
   static hipError_t init_links(int storage, const InitParams& p, hipStream_t s);
   static hipError_t export_state(int storage, const ExportParams& p, hipStream_t s);
@@ -215,7 +223,7 @@ hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_
 hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
-hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, const StepParams* tab,
+hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, bool reg, const StepParams* tab,
                              const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s);
 // Batched moving-sphere rebuild (moving.hip).  tab: one MovingParams per sphere;
 // waves: region waves as sphere << TILE_SHIFT | wave; kin: [step][nkin] table,
@@ -262,6 +270,8 @@ struct lbm_domain_s {
   bool links_ok;
   int32_t variant;
   double q_cut;
+  int32_t wall_neq;              // LBM_NEQ_BOUNCEBACK or LBM_NEQ_REGULARIZED
+  void* luv;                     // [6][nl or link_cap] u_w(t), u_w(t+1) per link (moving walls), or null
   // reductions
   double* partials;
   double* sums;

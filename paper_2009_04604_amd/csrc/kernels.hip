@@ -154,6 +154,79 @@ struct Collider {
   }
 };
 
+// Non-equilibrium stress Pi_ab = sum_j c_ja c_jb (f_j - f^eq_j(rho, u)) over the
+// lattice's D axes.  From shifted populations h_j = f_j - w_j:
+//   Pi = sum_j c c h_j - (rho - 1) cs2 delta - rho u u
+// (sum_j w_j c c = cs2 delta cancels against the equilibrium's rho cs2 delta).
+template <typename R>
+struct Stress {
+  R xx, yy, zz, xy, xz, yz;
+};
+
+// Stress of boundary node t from its staged pre-collision populations.
+template <class L, typename R>
+__device__ __forceinline__ Stress<R> neq_stress(const R (*stage)[BLOCK], int t, const Moments<R>& m) {
+  Stress<R> s{R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int j = 1; j < L::Q; ++j) {
+    const R h = stage[j][t];
+    if (L::cx(j)) s.xx += h;
+    if (L::cy(j)) s.yy += h;
+    if (L::cz(j)) s.zz += h;
+    if (L::cx(j) && L::cy(j)) s.xy += R(L::cx(j) * L::cy(j)) * h;
+    if (L::cx(j) && L::cz(j)) s.xz += R(L::cx(j) * L::cz(j)) * h;
+    if (L::cy(j) && L::cz(j)) s.yz += R(L::cy(j) * L::cz(j)) * h;
+  }
+  const R d3 = m.drho * R(1.0 / 3.0);
+  s.xx -= d3 + m.rho * m.ux * m.ux;
+  s.yy -= d3 + m.rho * m.uy * m.uy;
+  s.xy -= m.rho * m.ux * m.uy;
+  if constexpr (L::D == 3) {
+    s.zz -= d3 + m.rho * m.uz * m.uz;
+    s.xz -= m.rho * m.ux * m.uz;
+    s.yz -= m.rho * m.uy * m.uz;
+  }
+  return s;
+}
+
+// Stress after collision.  Pi is an even moment: BGK and TRT both relax it with
+// omega (= omega+), and Guo's source adds (1 - omega/2) sum_j c c S_j =
+// (1 - omega/2) (u F + F u).
+template <class L, typename R, bool TRT>
+__device__ __forceinline__ Stress<R> post_stress(const Stress<R>& s, const Collider<R, TRT>& col, const Moments<R>& m) {
+  const R k = R(1) - col.omega;
+  Stress<R> o{k * s.xx, k * s.yy, k * s.zz, k * s.xy, k * s.xz, k * s.yz};
+  if (col.force) {
+    o.xx += col.kf * R(2) * m.ux * col.Fx;
+    o.yy += col.kf * R(2) * m.uy * col.Fy;
+    o.xy += col.kf * (m.ux * col.Fy + m.uy * col.Fx);
+    if constexpr (L::D == 3) {
+      o.zz += col.kf * R(2) * m.uz * col.Fz;
+      o.xz += col.kf * (m.ux * col.Fz + m.uz * col.Fx);
+      o.yz += col.kf * (m.uy * col.Fz + m.uz * col.Fy);
+    }
+  }
+  return o;
+}
+
+// Wall non-equilibrium of direction c from the Hermite expansion truncated at
+// third order (eq. fi_neq), with the stress as second-order coefficient and the
+// third-order one from the recursion (eq. malaspinas):
+//   w [ H2:Pi / (2 cs2^2) + H3:(u Pi + u Pi + u Pi) / (6 cs2^3) ]
+//   = w [ 4.5 (cPc - tr Pi / 3) + 13.5 ((c.u) cPc - (2 u.Pi.c + (c.u) tr Pi) / 3) ].
+template <typename R>
+__device__ __forceinline__ R regularized_neq(R cx, R cy, R cz, R w, const Stress<R>& s, R ux, R uy, R uz) {
+  const R tr = s.xx + s.yy + s.zz;
+  const R pcx = s.xx * cx + s.xy * cy + s.xz * cz;
+  const R pcy = s.xy * cx + s.yy * cy + s.yz * cz;
+  const R pcz = s.xz * cx + s.yz * cy + s.zz * cz;
+  const R cpc = cx * pcx + cy * pcy + cz * pcz;
+  const R upc = ux * pcx + uy * pcy + uz * pcz;
+  const R cu = cx * ux + cy * uy + cz * uz;
+  const R third = R(1.0 / 3.0);
+  return w * (R(4.5) * (cpc - tr * third) + R(13.5) * (cu * cpc - third * (R(2) * upc + cu * tr)));
+}
+
 template <class L, typename R>
 __device__ __forceinline__ Moments<R> moments(const R (&h)[L::Q], R Fx, R Fy, R Fz) {
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -345,7 +418,7 @@ __device__ __forceinline__ void patch_links(R (&h)[L::Q], R (*stage)[BLOCK], boo
 // The zero-gradient outlet needs no work of its own: its pulls are clamped onto
 // the face layer (see axis_src).
 // ---------------------------------------------------------------------------
-template <class L, int S, bool COMPACT, bool TRT>
+template <class L, int S, bool COMPACT, bool TRT, bool REG>
 __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   using St = Storage<S>;
   using T = typename St::T;
@@ -390,6 +463,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   const R* __restrict__ lg = static_cast<const R*>(lk.lg);
   const R* __restrict__ lvi = static_cast<const R*>(lk.lv_in);
   R* __restrict__ lvo = static_cast<R*>(lk.lv_out);
+  const R* __restrict__ luv = static_cast<const R*>(lk.luv);
   // the first two links of each lane are fetched before the populations so that
   // their latency overlaps the pull
   int ldp[2] = {0, 0};
@@ -468,8 +542,23 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       // bounced direction: c_ibar = -c_i, w_ibar = w_i
       const R he_b = col.heq(-cx, -cy, -cz, w, mb);
       const R hs_b = col.post(-cx, -cy, -cz, w, hb, hi, mb);
-      const R n_pre = hb - he_b;         // bounced pre-collision non-equilibrium (eq. neqbb-s)
-      const R n_post = hs_b - he_b;      // bounced post-collision non-equilibrium
+      R n_pre, n_post;
+      if constexpr (REG) {
+        // regularised wall non-equilibrium (eq. fi_neq): the stress of node F at
+        // t before and after collision, with u_w(t+1) and u_w(t) respectively
+        const Stress<R> sp = neq_stress<L, R>(stage, t, mb);
+        const Stress<R> sq = post_stress<L, R, TRT>(sp, col, mb);
+        R u[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        if (luv) {
+#pragma unroll
+          for (int a = 0; a < 6; ++a) u[a] = luv[k + a * lk.luv_stride];
+        }
+        n_pre = regularized_neq(cx, cy, cz, w, sp, u[3], u[4], u[5]);
+        n_post = regularized_neq(cx, cy, cz, w, sq, u[0], u[1], u[2]);
+      } else {
+        n_pre = hb - he_b;               // bounced pre-collision non-equilibrium (eq. neqbb-s)
+        n_post = hs_b - he_b;            // bounced post-collision non-equilibrium
+      }
       R v = a.a4 * n_pre + a.a5 * n_post + a.a2 * hs_b + w * (mb.drho * (a.a4 + a.a5) + mb.rho * gw);
       v += a.a3 * col.post(cx, cy, cz, w, hi, hb, mb);
       if (list_mode) {
@@ -489,9 +578,9 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   }
 }
 
-template <class L, int S, bool COMPACT, bool TRT>
+template <class L, int S, bool COMPACT, bool TRT, bool REG>
 __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
-  step_body<L, S, COMPACT, TRT>(p, logical_block(p.g.xcd_remap));
+  step_body<L, S, COMPACT, TRT, REG>(p, logical_block(p.g.xcd_remap));
 }
 
 // Several domains in one persistent launch.  Slot k of the tile table names a
@@ -499,12 +588,12 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
 // walks the slots b, b + gridDim.x, ...  The host orders the table (see
 // tile_table), so the grid size and the order are launch choices that leave
 // every result unchanged.
-template <class L, int S, bool COMPACT, bool TRT>
+template <class L, int S, bool COMPACT, bool TRT, bool REG>
 __global__ __launch_bounds__(BLOCK) void step_batch_kernel(const StepParams* __restrict__ tab,
                                                            const uint32_t* __restrict__ tiles, uint32_t nslots) {
   for (uint32_t k = blockIdx.x; k < nslots; k += gridDim.x) {
     const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[k]);
-    if (t != TILE_EMPTY) step_body<L, S, COMPACT, TRT>(tab[t >> TILE_SHIFT], t & TILE_MASK);
+    if (t != TILE_EMPTY) step_body<L, S, COMPACT, TRT, REG>(tab[t >> TILE_SHIFT], t & TILE_MASK);
     wave_lds_sync();   // the next tile reuses the wave's LDS columns
   }
 }
@@ -813,39 +902,45 @@ __global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib,
     else LBM_DISPATCH_L(KERNEL, LAT, storage, false, grid, stream, __VA_ARGS__);                               \
   } while (0)
 
-// step kernels: storage x layout x collision
-#define LBM_STEP_L(KERNEL, LAT, storage, C, T, grid, stream, ...)                                              \
+// step kernels: storage x layout x collision x wall non-equilibrium estimator
+#define LBM_STEP_L(KERNEL, LAT, storage, C, T, G, grid, stream, ...)                                           \
   do {                                                                                                         \
     switch (storage) {                                                                                         \
-      case ST_F64: KERNEL<LAT, ST_F64, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                  \
-      case ST_F32: KERNEL<LAT, ST_F32, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                  \
-      case ST_F16S: KERNEL<LAT, ST_F16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                \
-      default: KERNEL<LAT, ST_BF16S, C, T><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                    \
+      case ST_F64: KERNEL<LAT, ST_F64, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;               \
+      case ST_F32: KERNEL<LAT, ST_F32, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;               \
+      case ST_F16S: KERNEL<LAT, ST_F16S, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;             \
+      default: KERNEL<LAT, ST_BF16S, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                 \
     }                                                                                                          \
   } while (0)
 
-#define LBM_STEP_SCT(KERNEL, LAT, storage, compact, trt, grid, stream, ...)                                    \
+#define LBM_STEP_TG(KERNEL, LAT, storage, C, trt, reg, grid, stream, ...)                                      \
   do {                                                                                                         \
-    if (compact) {                                                                                             \
-      if (trt) LBM_STEP_L(KERNEL, LAT, storage, true, true, grid, stream, __VA_ARGS__);                        \
-      else LBM_STEP_L(KERNEL, LAT, storage, true, false, grid, stream, __VA_ARGS__);                           \
+    if (trt) {                                                                                                 \
+      if (reg) LBM_STEP_L(KERNEL, LAT, storage, C, true, true, grid, stream, __VA_ARGS__);                     \
+      else LBM_STEP_L(KERNEL, LAT, storage, C, true, false, grid, stream, __VA_ARGS__);                        \
     } else {                                                                                                   \
-      if (trt) LBM_STEP_L(KERNEL, LAT, storage, false, true, grid, stream, __VA_ARGS__);                       \
-      else LBM_STEP_L(KERNEL, LAT, storage, false, false, grid, stream, __VA_ARGS__);                          \
+      if (reg) LBM_STEP_L(KERNEL, LAT, storage, C, false, true, grid, stream, __VA_ARGS__);                    \
+      else LBM_STEP_L(KERNEL, LAT, storage, C, false, false, grid, stream, __VA_ARGS__);                       \
     }                                                                                                          \
+  } while (0)
+
+#define LBM_STEP_SCT(KERNEL, LAT, storage, compact, trt, reg, grid, stream, ...)                               \
+  do {                                                                                                         \
+    if (compact) LBM_STEP_TG(KERNEL, LAT, storage, true, trt, reg, grid, stream, __VA_ARGS__);                 \
+    else LBM_STEP_TG(KERNEL, LAT, storage, false, trt, reg, grid, stream, __VA_ARGS__);                        \
   } while (0)
 
 template <class L>
 hipError_t Launch<L>::step(int storage, const StepParams& p, hipStream_t s) {
   const dim3 grid((unsigned)grid_blocks(p.g));
-  LBM_STEP_SCT(step_kernel, L, storage, p.g.compact, p.trt, grid, s, p);
+  LBM_STEP_SCT(step_kernel, L, storage, p.g.compact, p.trt, p.wall_neq != 0, grid, s, p);
   return hipGetLastError();
 }
 
 template <class L>
-hipError_t Launch<L>::step_batch(int storage, bool compact, bool trt, const StepParams* tab, const uint32_t* tiles,
-                                 uint32_t nslots, uint32_t grid, hipStream_t s) {
-  LBM_STEP_SCT(step_batch_kernel, L, storage, compact, trt, dim3(grid), s, tab, tiles, nslots);
+hipError_t Launch<L>::step_batch(int storage, bool compact, bool trt, bool reg, const StepParams* tab,
+                                 const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s) {
+  LBM_STEP_SCT(step_batch_kernel, L, storage, compact, trt, reg, dim3(grid), s, tab, tiles, nslots);
   return hipGetLastError();
 }
 
@@ -905,10 +1000,10 @@ hipError_t launch_step(int lattice, int storage, const StepParams& p, hipStream_
   LBM_BY_LATTICE(lattice, step(storage, p, s));
 }
 
-hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, const StepParams* tab,
+hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, bool reg, const StepParams* tab,
                              const uint32_t* tiles, uint32_t nslots, uint32_t grid, hipStream_t s) {
   if (nslots == 0 || grid == 0) return hipSuccess;
-  LBM_BY_LATTICE(lattice, step_batch(storage, compact, trt, tab, tiles, nslots, grid, s));
+  LBM_BY_LATTICE(lattice, step_batch(storage, compact, trt, reg, tab, tiles, nslots, grid, s));
 }
 
 hipError_t launch_init(int lattice, int storage, const InitParams& p, hipStream_t s) {

@@ -215,6 +215,14 @@ __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
     p.lld[k] = (uint16_t)(s.lane | (i << 8));
     lq[k] = R(q);
     lg[k] = R(wall_term<double>(ad, cu0, uu0, cu1, uu1));
+    if (p.luv) {
+      R* uv = static_cast<R*>(p.luv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        uv[k + a * p.luv_stride] = R(u0[a]);
+        uv[k + (3 + a) * p.luv_stride] = R(u1[a]);
+      }
+    }
     ++k;
   }
 }

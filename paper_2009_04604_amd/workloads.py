@@ -49,21 +49,23 @@ def couette_domain(p, storage="f64", variant="FQ", layout="compact"):
     return d, mask, links
 
 
-def channel_domain(p, storage="f32", variant="FQ", layout="compact"):
+def channel_domain(p, storage="f32", variant="FQ", layout="compact", wall_neq="bounceback"):
     mask, links = channel_geometry(p)
     d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage,
                  periodic=(False, False, True), outlet_face="+x", layout=layout)
     d.set_boundary_links(links, variant=variant)
+    d.set_wall_neq(wall_neq)
     return d, mask, links
 
 
 def packing_domain(n=256, storage="f32", tau=0.9, force=(1e-6, 0.0, 0.0), variant="FQ", spheres=None,
-                   layout="compact", lattice="D3Q19", collision="BGK", magic=3.0 / 16.0):
+                   layout="compact", lattice="D3Q19", collision="BGK", magic=3.0 / 16.0, wall_neq="bounceback"):
     centres, radii = synth.sphere_packing(n=n) if spheres is None else spheres
     mask, links = packing_geometry(n, centres, radii, lattice)
     d = B.Domain(lattice, n, n, n, mask, tau, storage=storage, force=force, layout=layout, collision=collision,
                  magic=magic)
     d.set_boundary_links(links, variant=variant)
+    d.set_wall_neq(wall_neq)
     return d, mask, links
 
 

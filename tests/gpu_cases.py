@@ -34,15 +34,15 @@ class Case:
         fluid = G.classify(dom, sh)
         return dom, fluid, sh, fcs
 
-    def oracle(self, variant="FQ", q_cut=0.01):
+    def oracle(self, variant="FQ", q_cut=0.01, wall_neq="bounceback"):
         dom, fluid, sh, fcs = self.oracle_geometry()
         sim = solver.Simulation(dom, self.tau, force=self.force, rho0=self.rho0, u0=self.u0, magic=self.magic)
-        sim.set_geometry(fluid, G.cut_links(dom, fluid, sh, fcs), variant, q_cut)
+        sim.set_geometry(fluid, G.cut_links(dom, fluid, sh, fcs), variant, q_cut, wall_neq=wall_neq)
         sim.init_equilibrium()
         return sim
 
     # -- product path ----------------------------------------------------------
-    def gpu(self, B, storage="f64", variant="FQ", q_cut=0.01, layout="compact"):
+    def gpu(self, B, storage="f64", variant="FQ", q_cut=0.01, layout="compact", wall_neq="bounceback"):
         nx, ny, nz = self.n
         g = B.Geometry(self.lat, nx, ny, nz, periodic=self.periodic, outlet_face=self.outlet)
         for c, r, ins, V, Om in self.spheres:
@@ -55,6 +55,8 @@ class Case:
         d = B.Domain(self.lat, nx, ny, nz, mask, self.tau, storage=storage, periodic=self.periodic,
                      force=self.force, rho0=self.rho0, u0=self.u0, outlet_face=self.outlet, layout=layout, **trt)
         d.set_boundary_links(links, variant=variant, q_cutoff=q_cut)
+        if wall_neq != "bounceback":
+            d.set_wall_neq(wall_neq)
         return d, mask, links
 
 

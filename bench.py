@@ -46,6 +46,9 @@ def parse():
                     help="collision model (TRT with the magic parameter 3/16)")
     ap.add_argument("--wall-neq", default="bounceback", choices=["bounceback", "regularized"],
                     help="wall non-equilibrium estimator of the ELIBB links")
+    ap.add_argument("--xcd-remap", type=int, choices=[0, 1], default=None,
+                    help="launch option: XCD deal of the step kernel's workgroups: 0 round-robin, 1 contiguous "
+                         "eighths; default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -329,6 +332,9 @@ def main():
     torch.cuda.set_device(0)
     log(f"main: building {a.workload} ({a.storage}, {a.layout})")
     d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision, a.wall_neq)
+    if a.xcd_remap is not None:
+        d.set_launch_option(0, a.xcd_remap)
+        cfg["xcd_remap"] = a.xcd_remap
     log("main: timed steps")
     info = d.info()
     nfl = info["n_fluid"]

@@ -78,3 +78,67 @@ def test_sphere_packing_256_f32_one_step(gpu_lib):
     sub = G.cut_links(dom, fluid, sh, nodes=nodes)
     out = solver.step_at(dom, f0, fluid, sub, nodes, 0.9, force=(1e-6, 0.0, 0.0))
     _check_one_step(f0, f1, out, nodes, 1e-6)
+
+
+def test_moving_boxes_32_bf16_batched_one_step(gpu_lib):
+    """The 32 moving-sphere boxes (BF16 shifted, dense layout) stepped by the
+    autotuned batch as the benchmark runs them; one step of the largest box is
+    checked node by node against the oracle's step from the exported state on
+    20k sampled nodes plus every boundary node of a slab through the sphere.
+    The GPU stores each post-collision value h* = f* - w rounded to BF16 (round
+    to nearest even, 8 significant bits, so half an ulp is at most 2^-8 |h*|):
+    |df| <= 2^-8 |h*| + FP32 error, tested as 2^-8 |h*| + 1e-6 (measured: 0.88 of
+    that bound at most)."""
+    from oracle import moving
+    from paper_2009_04604_amd import binding as B, workloads as W
+    boxes = synth.moving_boxes()
+    _say("case moving boxes 32 bf16, batched")
+    ds = [W.moving_box_domain(b, storage="bf16s") for b in boxes]
+    bt = B.Batch()
+    bt.autotune(ds, steps_per_candidate=4)
+    bt.step(ds, 20)
+    k = int(np.argmax([b["nx"] for b in boxes]))
+    box, d = boxes[k], ds[k]
+    n = box["nx"]
+    t = d.info()["steps_done"]
+    n_fluid_t = d.info()["n_fluid"]
+    f0 = d.get_state()
+    bt.step(ds, 1)
+    f1 = d.get_state()
+    bt.close()
+    for x in ds:
+        x.close()
+    _say("box", k, "side", n, "t", t)
+    dom = G.Domain(OL.D3Q19, n, n, n)
+    kin = moving.Kinematics(box["x0"], box["amplitude"], box["period"], box["direction"], box["omega"])
+
+    def sphere(tt):
+        return G.Sphere(kin.centre(tt), box["radius"], True, V=kin.velocity(tt), Omega=kin.Omega)
+
+    sph = sphere(t)
+    fluid_t = G.classify(dom, [sph]).reshape(-1)
+    fluid_t1 = G.classify(dom, [sphere(t + 1)]).reshape(-1)
+    assert int(fluid_t.sum()) == n_fluid_t
+    c_t, V1 = kin.centre(t), kin.velocity(t + 1)
+
+    def uw1(shape, xw):
+        r = dom.min_image(xw - c_t[:, None])
+        return V1[:, None] + np.cross(kin.Omega, r.T).T
+
+    both = np.flatnonzero(fluid_t & fluid_t1)
+    rng = np.random.default_rng(3)
+    pick = rng.choice(both, size=20000, replace=False)
+    z = both // (n * n)
+    zc = int(round(c_t[2]))
+    slab = both[np.abs(z - zc) <= 1]
+    cand = np.unique(np.concatenate([pick, slab]))
+    links = G.cut_links(dom, fluid_t, [sph], uw_t1_fn=uw1, nodes=cand)
+    assert np.unique(links["node"]).size > 100          # the slab holds boundary nodes
+    out = solver.step_at(dom, f0, fluid_t, links, cand, box["tau"])
+    got = f1[:, cand]
+    h = out - OL.D3Q19.w[:, None]
+    err = np.abs(got - out)
+    _say("max |df|", err.max(), "max |df| / (2^-8 |h*| + 1e-6)", (err / (2.0 ** -8 * np.abs(h) + 1e-6)).max(),
+         "nodes", cand.size)
+    assert np.isfinite(out).all()
+    assert (err <= 2.0 ** -8 * np.abs(h) + 1e-6).all()

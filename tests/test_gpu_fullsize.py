@@ -142,3 +142,60 @@ def test_moving_boxes_32_bf16_batched_one_step(gpu_lib):
          "nodes", cand.size)
     assert np.isfinite(out).all()
     assert (err <= 2.0 ** -8 * np.abs(h) + 1e-6).all()
+
+
+def test_served_requests_f16_batched_one_step(gpu_lib):
+    """Served requests in their served form (FP16 shifted, one batched launch):
+    the largest cylinder channel (2L x L) and the largest circular Couette (L x L)
+    of the request stream, batched with four smaller requests; one step of each
+    of the two checked node by node against the oracle's step from the exported
+    state on 20k sampled nodes plus every boundary node of selected columns.
+    FP16 keeps 11 significant bits: half an ulp is at most 2^-11 |h*| (2^-25 in
+    the subnormal range), tested as 2^-11 |h*| + 1e-7."""
+    from paper_2009_04604_amd import binding as B, workloads as W
+    reqs = synth.request_stream()
+    chan = max((r for r in reqs if r["kind"] == "channel"), key=lambda r: r["L"])
+    cou = max((r for r in reqs if r["kind"] == "couette"), key=lambda r: r["L"])
+    small = [r for r in reqs if r["L"] < 256][:4]
+    members = [chan, cou] + small
+    _say("case served f16: channel", chan["nx"], "x", chan["ny"], "couette", cou["nx"], "+", len(small), "small")
+    built = [W.request_domain(r, storage="f16s") for r in members]
+    ds = [b[0] for b in built]
+    bt = B.Batch()
+    bt.step(ds, 200)
+    f0 = [ds[0].get_state(), ds[1].get_state()]
+    bt.step(ds, 1)
+    f1 = [ds[0].get_state(), ds[1].get_state()]
+    bt.close()
+    for d in ds:
+        d.close()
+    rng = np.random.default_rng(4)
+    w = OL.D2Q9.w[:, None]
+    for k, r in enumerate((chan, cou)):
+        nx, ny = r["nx"], r["ny"]
+        mask, links = built[k][1], built[k][2]
+        if r["kind"] == "channel":
+            dom = G.Domain(OL.D2Q9, nx, ny, 1, periodic=(False, False, True), outlet_face=1)
+            sh = [G.Sphere(r["centre"], r["radius"], True)]
+            faces = [G.FaceWall(0, 0.5, G.parabolic_inlet(ny, r["u_max"])), G.FaceWall(2, 0.5), G.FaceWall(3, 0.5)]
+            x = lambda n: n % nx
+            region = lambda bn: (x(bn) < 3) | (x(bn) > nx - 3) | (np.abs(x(bn) - int(r["centre"][0])) < 30)
+        else:
+            dom = G.Domain(OL.D2Q9, nx, ny, 1)
+            om1 = r["u_inner"] / r["r1"]
+            sh = [G.Sphere(r["centre"], r["r1"], True, Omega=(0, 0, om1)), G.Sphere(r["centre"], r["r2"], False)]
+            faces = []
+            x = lambda n: n % nx
+            region = lambda bn: np.abs(x(bn) - nx // 2) < 20
+        fluid = G.classify(dom, sh)
+        assert np.array_equal(fluid.reshape(-1), np.asarray(mask, bool))
+        nodes = _sample(mask, links, rng, 20000, region)
+        sub = G.cut_links(dom, fluid, sh, faces, nodes=nodes)
+        out = solver.step_at(dom, f0[k], fluid, sub, nodes, r["tau"])
+        got = f1[k][:, nodes]
+        h = out - w
+        err = np.abs(got - out)
+        _say(r["kind"], nx, "x", ny, "max |df|", err.max(), "max |df| / bound",
+             (err / (2.0 ** -11 * np.abs(h) + 1e-7)).max(), "nodes", nodes.size)
+        assert np.isfinite(out).all()
+        assert (err <= 2.0 ** -11 * np.abs(h) + 1e-7).all()

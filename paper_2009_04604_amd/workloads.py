@@ -77,11 +77,12 @@ def request_domain(req, storage="f16s", variant="FQ", layout="compact"):
     return channel_domain(req, storage=storage, variant=variant, layout=layout)
 
 
-def moving_box_domain(box, storage="bf16s", variant="FQ"):
+def moving_box_domain(box, storage="bf16s", variant="FQ", wall_neq="bounceback"):
     """One periodic box with a sphere in prescribed motion (``synth.moving_boxes``)."""
     n = (box["nx"], box["ny"], box["nz"])
     d = B.Domain("D3Q19", *n, np.ones(n[0] * n[1] * n[2], np.uint8), box["tau"], storage=storage,
                  rho0=box.get("rho0", 1.0), layout="dense")
+    d.set_wall_neq(wall_neq)
     d.set_moving_sphere(box["x0"], box["radius"], box["amplitude"], box["period"], box["direction"], box["omega"],
                         variant=variant)
     return d

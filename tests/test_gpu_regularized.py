@@ -3,8 +3,8 @@ estimator selected by lbm_set_wall_neq) against the FP64 oracle, through the
 C-ABI: the annulus with its rotating inner wall (per-link wall velocities), BGK
 and TRT; a forced 3D packing on both layouts and on D3Q27; the channel with its
 parabolic inlet and outlet; a moving sphere (wall velocities written by the
-device-side link rebuild); a switch of estimator in the middle of a run; a batch
-mixing both estimators; the full-size packing in the benchmark configuration;
+device-side link rebuild, alone and batched); a switch of estimator in the
+middle of a run; a batch mixing both estimators; the full-size packing in the benchmark configuration;
 the 16-bit errors; argument checks."""
 import numpy as np
 import pytest
@@ -127,6 +127,30 @@ def test_batch_mixing_estimators(gpu_lib):
     b.step(batched, 6)
     for a, c in zip(alone, batched):
         assert np.array_equal(a.get_state(), c.get_state())
+    b.close()
+    for d in alone + batched:
+        d.close()
+
+
+def test_moving_batch_mixing_estimators(gpu_lib):
+    """Moving spheres with the regularised estimator in a batch (the batched link
+    rebuild writes the wall velocities) end bit-identical to the same boxes
+    stepped alone, next to a box with the bounced estimator."""
+    from paper_2009_04604_amd import workloads as W
+    B = gpu_lib
+    _say("case moving batch, regularised + bounce-back")
+    boxes = synth.moving_boxes(n_boxes=3, side_min=40, side_max=56, r_min=5.0, r_max=7.0, amplitude=4.0,
+                               period=120.0, seed=5)
+    modes = [REG, REG, "bounceback"]
+    alone = [W.moving_box_domain(bx, storage="f32", wall_neq=m) for bx, m in zip(boxes, modes)]
+    batched = [W.moving_box_domain(bx, storage="f32", wall_neq=m) for bx, m in zip(boxes, modes)]
+    b = B.Batch()
+    for n in (3, 300):               # 300 crosses a kinematics upload chunk
+        for d in alone:
+            d.step(n)
+        b.step(batched, n)
+        for a, c in zip(alone, batched):
+            assert np.array_equal(a.get_state(), c.get_state())
     b.close()
     for d in alone + batched:
         d.close()

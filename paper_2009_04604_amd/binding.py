@@ -77,6 +77,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_04604_amd.build`")
+    # torch first: liblbm then binds to the HIP runtime torch has loaded, so torch's
+    # streams and device memory are valid in the library (loaded first, the library
+    # would pull in the system runtime and torch would bring a second one)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "lbm_arena_bytes": (ctypes.c_size_t, [P, P]),

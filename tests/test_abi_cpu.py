@@ -99,3 +99,16 @@ def test_builder_matches_oracle_packing_d3q27(B):
     _compare(mask, links, fluid, G.cut_links(dom, fluid, sh))
     assert (links["dir"] >= 19).any()          # corner links exist
 
+
+
+def test_binding_loads_torch_before_the_library():
+    """The library must bind to the HIP runtime torch loads (torch's streams and
+    memory are passed to it); loading it first would pull in a second runtime."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; from paper_2009_04604_amd import binding as B; "
+            "assert 'torch' not in sys.modules; B.lib(); assert 'torch' in sys.modules; print('ok')")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr

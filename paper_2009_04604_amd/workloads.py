@@ -42,10 +42,13 @@ def packing_geometry(n, centres, radii, lattice="D3Q19"):
     return mask, links
 
 
-def couette_domain(p, storage="f64", variant="FQ", layout="compact"):
+def couette_domain(p, storage="f64", variant="FQ", layout="compact", collision="BGK", magic=3.0 / 16.0,
+                   wall_neq="bounceback"):
     mask, links = annulus_geometry(p)
-    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage, rho0=p.get("rho0", 1.0), layout=layout)
+    d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage, rho0=p.get("rho0", 1.0), layout=layout,
+                 collision=collision, magic=magic)
     d.set_boundary_links(links, variant=variant)
+    d.set_wall_neq(wall_neq)
     return d, mask, links
 
 

@@ -13,9 +13,9 @@ from oracle import analytic, metrics
 pytestmark = pytest.mark.gpu
 
 
-def _rrse(B, W, scale, storage):
+def _rrse(B, W, scale, storage, **kw):
     p = synth.couette_annulus(scale)
-    d, mask, _ = W.couette_domain(p, storage=storage)
+    d, mask, _ = W.couette_domain(p, storage=storage, **kw)
     d.step(int(3500 * scale * scale))
     _, u, _, unstable = d.macros()
     assert not unstable
@@ -29,10 +29,10 @@ def _rrse(B, W, scale, storage):
     return metrics.rrse(np.linalg.norm(u[fl], axis=1), uth)
 
 
-def _errors(B, storage):
+def _errors(B, storage, **kw):
     from paper_2009_04604_amd import workloads as W
     scales = np.array([1.0, 2.0, 4.0])
-    errs = np.array([_rrse(B, W, s, storage) for s in scales])
+    errs = np.array([_rrse(B, W, s, storage, **kw) for s in scales])
     # least-squares slope over the three resolutions (the wall's position in the
     # lattice changes with the resolution, so pairwise slopes scatter)
     slope = -np.polyfit(np.log(scales), np.log(errs), 1)[0]
@@ -62,3 +62,14 @@ def test_couette_bf16_error_stated(gpu_lib):
     convergence claim)."""
     errs, _ = _errors(gpu_lib, "bf16s")
     assert errs[0] < 0.005
+
+
+@pytest.mark.parametrize("kw", [{"collision": "TRT"}, {"wall_neq": "regularized"},
+                                {"collision": "TRT", "wall_neq": "regularized"}],
+                         ids=["TRT", "regularized", "TRT-regularized"])
+def test_couette_second_order_trt_and_regularized(gpu_lib, kw):
+    """The paper's accuracy experiments use TRT (Lambda = 3/16) and compare the
+    two wall non-equilibrium estimators: both stay second order in FP64."""
+    errs, slope = _errors(gpu_lib, "f64", **kw)
+    print("case", kw, flush=True)
+    assert errs[0] < 0.01 and slope > 1.8

@@ -11,6 +11,8 @@ q = 1 to its neighbour).
 Shapes:
 * ``Sphere``    ball (3D) or disk (2D, centre z = 0), solid inside or outside,
                 rigid-body wall velocity u_w = V + Omega x (x_W - centre).
+* ``Cylinder``  circular cylinder along z through the centre (3D lattices): the
+                sphere's formulas in the xy-plane.
 * ``FaceWall``  a plane parallel to a non-periodic domain face at distance q_f
                 from the first node layer, with a wall velocity given as a
                 function of x_W (constant, or the parabolic inlet profile).
@@ -20,8 +22,9 @@ the post-collision value of the face-layer node one step back along the face
 (the "producer"), if that node is fluid; otherwise the pair must be a cut link.
 
 Status: pinned -- the q of straight walls (exact closed values) and of circles
-with lattice points on them (q = 1 exactly) in tests; circle/sphere q values
-are pinned against a bisection of the signed distance.
+with lattice points on them (q = 1 exactly) in tests; circle/sphere/cylinder q
+values are pinned against a bisection of the signed distance, and a cylinder's
+layers against the 2D disk.
 """
 import numpy as np
 
@@ -61,6 +64,9 @@ class Domain:
 
 
 class Sphere:
+    # axes the distance is measured along (a cylinder drops z)
+    AXES = np.array([1.0, 1.0, 1.0])
+
     def __init__(self, centre, radius, solid_inside=True, V=(0.0, 0.0, 0.0), Omega=(0.0, 0.0, 0.0)):
         self.centre = np.asarray(centre, dtype=np.float64).reshape(3)
         self.radius = float(radius)
@@ -68,37 +74,50 @@ class Sphere:
         self.V = np.asarray(V, dtype=np.float64).reshape(3)
         self.Omega = np.asarray(Omega, dtype=np.float64).reshape(3)
 
+    def _rel(self, dom, pts):
+        return dom.min_image(pts - self.centre[:, None]) * self.AXES[:, None]
+
     def solid(self, dom, pts):
-        d = dom.min_image(pts - self.centre[:, None])
+        d = self._rel(dom, pts)
         r2 = (d * d).sum(axis=0)
         R2 = self.radius ** 2
         return r2 < R2 if self.solid_inside else r2 > R2
 
     def on_or_solid(self, dom, pts):
-        d = dom.min_image(pts - self.centre[:, None])
+        d = self._rel(dom, pts)
         r2 = (d * d).sum(axis=0)
         R2 = self.radius ** 2
         return r2 <= R2 if self.solid_inside else r2 >= R2
 
     def crossing(self, dom, xf, c):
         """First crossing lam in (0, 1] of the segment xf - lam c with the surface, NaN if none."""
-        d = dom.min_image(xf - self.centre[:, None])
+        d = self._rel(dom, xf)
+        c = c * self.AXES[:, None]
         a = (c * c).sum(axis=0)
         b = (d * c).sum(axis=0)
         c0 = (d * d).sum(axis=0) - self.radius ** 2
         disc = b * b - a * c0
-        ok = disc >= 0.0
+        ok = (disc >= 0.0) & (a > 0.0)
         sq = np.sqrt(np.where(ok, disc, 0.0))
+        aa = np.where(a > 0.0, a, 1.0)
         # |d - lam c|^2 = R^2  <=>  a lam^2 - 2 b lam + c0 = 0
-        lam = (b - sq) / a if self.solid_inside else (b + sq) / a
+        lam = (b - sq) / aa if self.solid_inside else (b + sq) / aa
         # a fluid node lying on the surface to within rounding gives a root at
         # lam ~ 0 (possibly -1e-16): it is accepted and clamped to LAM_MIN
         good = ok & (lam > -1e-12) & (lam <= 1.0 + 1e-12)
         return np.where(good, np.clip(lam, LAM_MIN, 1.0), np.nan)
 
     def velocity(self, dom, xw):
-        r = dom.min_image(xw - self.centre[:, None])
+        r = self._rel(dom, xw)
         return self.V[:, None] + np.cross(self.Omega, r.T).T
+
+
+class Cylinder(Sphere):
+    """Circular cylinder of infinite extent along z whose axis passes through
+    ``centre`` (the cylindrical Couette geometry of Sec. III.B on a 3D lattice):
+    the sphere's distance, crossing and rigid-body velocity taken in the
+    xy-plane.  A direction along the axis never crosses it."""
+    AXES = np.array([1.0, 1.0, 0.0])
 
 
 class FaceWall:
@@ -171,6 +190,9 @@ def _bbox_nodes(dom, sph, pad):
     for a in range(3):
         if dom.lat.d == 2 and a == 2:
             rng.append(np.array([0]))
+            continue
+        if sph.AXES[a] == 0.0:                   # unbounded along this axis (cylinder)
+            rng.append(np.arange(dom.n[a]))
             continue
         lo = int(np.floor(sph.centre[a] - sph.radius)) - pad
         hi = int(np.ceil(sph.centre[a] + sph.radius)) + pad

@@ -95,3 +95,61 @@ def test_channel_with_outlet_is_fully_covered():
     inl = np.flatnonzero((L["node"] % nx == 0) & (L["dir"] == 1))
     y = L["node"][inl] // nx
     np.testing.assert_allclose(L["uw_t"][0, inl], 4 * 0.05 * (y + 0.5) * (ny - 0.5 - y) / ny ** 2, rtol=1e-14)
+
+
+def _bisect_q_cylinder(dom, cyl, xf, c):
+    """Reference for a cylinder along z: bisection on the squared xy-distance."""
+    def g(lam):
+        p = xf - lam * c
+        d = dom.min_image((p - cyl.centre)[:, None])[:, 0]
+        v = d[0] * d[0] + d[1] * d[1] - cyl.radius ** 2
+        return v if cyl.solid_inside else -v
+    lo, hi = 0.0, 1.0
+    assert g(lo) > 0 and g(hi) <= 0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    return hi
+
+
+@pytest.mark.parametrize("lat", [lattice.D3Q19, lattice.D3Q27], ids=lambda l: l.name)
+@pytest.mark.parametrize("inside", [True, False])
+def test_cylinder_q_matches_bisection(lat, inside):
+    dom = G.Domain(lat, 18, 17, 5)
+    cyl = G.Cylinder((8.37, 8.61, 2.3), 5.3 if inside else 7.2, inside)
+    fluid = G.classify(dom, [cyl])
+    L = G.cut_links(dom, fluid, [cyl])
+    assert L["node"].size > 50
+    X = dom.coords()
+    for k in range(0, L["node"].size, max(1, L["node"].size // 60)):
+        xf = X[:, L["node"][k]].astype(float)
+        c = lat.c[L["dir"][k]].astype(float)
+        assert c[0] != 0 or c[1] != 0                  # an axial direction never crosses
+        assert abs(L["q"][k] - _bisect_q_cylinder(dom, cyl, xf, c)) < 1e-12
+
+
+def test_cylinder_layers_equal_the_disk():
+    """Every z-layer of a cylinder on D3Q19 is the D2Q9 disk: same fluid nodes,
+    and every link's q is the disk's q of the link's in-plane projection; the
+    wall moves at |Omega| R."""
+    n, nz, R, om = 30, 4, 9.3, 2e-3
+    ctr = (14.6, 15.2, 0.0)
+    d2 = G.Domain(lattice.D2Q9, n, n, 1)
+    disk = G.Sphere(ctr, R, True, Omega=(0, 0, om))
+    f2 = G.classify(d2, [disk]).reshape(-1)
+    L2 = G.cut_links(d2, f2.reshape(d2.shape), [disk])
+    q2 = {(int(nd), tuple(lattice.D2Q9.c[d][:2])): q for nd, d, q in zip(L2["node"], L2["dir"], L2["q"])}
+    d3 = G.Domain(lattice.D3Q19, n, n, nz)
+    cyl = G.Cylinder(ctr, R, True, Omega=(0, 0, om))
+    f3 = G.classify(d3, [cyl]).reshape(nz, n * n)
+    for z in range(nz):
+        assert np.array_equal(f3[z], f2)
+    L3 = G.cut_links(d3, f3.reshape(d3.shape), [cyl])
+    assert L3["node"].size > 0
+    for nd, d, q in zip(L3["node"], L3["dir"], L3["q"]):
+        cxy = tuple(lattice.D3Q19.c[d][:2])
+        assert q2[(int(nd) % (n * n), cxy)] == q
+    np.testing.assert_allclose(np.linalg.norm(L3["uw_t"], axis=0), om * R, rtol=1e-12)

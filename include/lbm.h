@@ -295,6 +295,15 @@ int lbm_geometry_create(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, int
  * periodic axes).  V, Omega may be NULL (zero). */
 int lbm_geometry_add_sphere(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
                             const double V[3], const double Omega[3]);
+
+/* Circular cylinder of infinite extent along z, its axis through centre (the
+ * cylindrical Couette geometry of Sec. III.B on a 3D lattice): the sphere's
+ * rules with distances taken in the xy-plane; wall velocity
+ * u_w = V + Omega x r, r the xy-offset of x_W from the axis.  A link along z never
+ * crosses it.  On D2Q9 it is the disk.  LBM_EINVAL for a null geometry or centre,
+ * a radius that is not finite and > 0, or a non-finite centre or motion. */
+int lbm_geometry_add_cylinder(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
+                              const double V[3], const double Omega[3]);
 /* n solid-inside spheres at rest: centres [3n], radii [n]. */
 int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, const double* radii);
 /* Plane wall parallel to a non-periodic face at distance q_face in (0, 1] from

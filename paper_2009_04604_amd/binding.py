@@ -35,7 +35,7 @@ EXPORTED = [
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
-    "lbm_set_wall_neq",
+    "lbm_set_wall_neq", "lbm_geometry_add_cylinder",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -117,6 +117,7 @@ def lib():
         "lbm_momentum_exchange": (I32, [P, P]),
         "lbm_geometry_get_shapes": (I32, [P, P]),
         "lbm_set_wall_neq": (I32, [P, I32]),
+        "lbm_geometry_add_cylinder": (I32, [P, P, DBL, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -431,6 +432,14 @@ class Geometry:
         Vv = None if V is None else np.ascontiguousarray(V, dtype=np.float64).reshape(3)
         Om = None if Omega is None else np.ascontiguousarray(Omega, dtype=np.float64).reshape(3)
         _check(lib().lbm_geometry_add_sphere(self.h, _ptr(c), float(radius), int(bool(solid_inside)), _ptr(Vv), _ptr(Om)))
+
+    def add_cylinder(self, centre, radius, solid_inside=True, V=None, Omega=None):
+        """Circular cylinder along z through ``centre``."""
+        c = np.ascontiguousarray(centre, dtype=np.float64).reshape(3)
+        Vv = None if V is None else np.ascontiguousarray(V, dtype=np.float64).reshape(3)
+        Om = None if Omega is None else np.ascontiguousarray(Omega, dtype=np.float64).reshape(3)
+        _check(lib().lbm_geometry_add_cylinder(self.h, _ptr(c), float(radius), int(bool(solid_inside)), _ptr(Vv),
+                                               _ptr(Om)))
 
     def add_spheres(self, centres, radii):
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)

@@ -2,9 +2,9 @@
 // intersections (Sec. II.B: q = |x_W - x_F| / |c_i|, the first wall crossing
 // along the segment x_F -> x_F - c_i).
 //
-// Shapes: spheres / disks (solid inside or outside, rigid-body wall velocity)
-// and plane walls parallel to non-periodic faces (constant or parabolic
-// velocity).  Many solid-inside spheres are bucketed on a coarse grid so that a
+// Shapes: spheres / disks (solid inside or outside, rigid-body wall velocity),
+// circular cylinders along z (the sphere's formulas in the xy-plane) and plane
+// walls parallel to non-periodic faces (constant or parabolic velocity).  Many solid-inside spheres are bucketed on a coarse grid so that a
 // link is only tested against spheres that can reach it; candidates are always
 // evaluated in insertion order, spheres before face walls, and the first
 // strictly smaller crossing wins.
@@ -25,6 +25,7 @@ struct Sph {
   double r;
   int inside;
   double V[3], Om[3];
+  double ax[3];   // axes the distance is measured along: {1, 1, 1} sphere, {1, 1, 0} cylinder along z
 };
 
 struct Face {
@@ -79,7 +80,7 @@ inline double min_image(const lbm_geometry_s* g, int a, double d) {
 inline bool solid_or_on(const lbm_geometry_s* g, const Sph& s, const double p[3]) {
   double r2 = 0.0;
   for (int a = 0; a < 3; ++a) {
-    const double d = min_image(g, a, p[a] - s.c[a]);
+    const double d = min_image(g, a, p[a] - s.c[a]) * s.ax[a];
     r2 += d * d;
   }
   const double R2 = s.r * s.r;
@@ -87,10 +88,14 @@ inline bool solid_or_on(const lbm_geometry_s* g, const Sph& s, const double p[3]
 }
 
 // first crossing lam in (0, 1] of xf - lam c with the sphere surface, NaN if none
-inline double sphere_crossing(const lbm_geometry_s* g, const Sph& s, const double xf[3], const double c[3]) {
-  double dd[3];
-  for (int a = 0; a < 3; ++a) dd[a] = min_image(g, a, xf[a] - s.c[a]);
+inline double sphere_crossing(const lbm_geometry_s* g, const Sph& s, const double xf[3], const double c0[3]) {
+  double dd[3], c[3];
+  for (int a = 0; a < 3; ++a) {
+    dd[a] = min_image(g, a, xf[a] - s.c[a]) * s.ax[a];
+    c[a] = c0[a] * s.ax[a];
+  }
   const double A = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  if (!(A > 0.0)) return NAN;   // along a cylinder's axis
   const double B = dd[0] * c[0] + dd[1] * c[1] + dd[2] * c[2];
   const double C0 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] - s.r * s.r;
   const double disc = B * B - A * C0;
@@ -111,6 +116,25 @@ inline double face_crossing(const lbm_geometry_s* g, const Face& f, const double
   return NAN;
 }
 
+int add_round(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside, const double V[3],
+              const double Omega[3], bool cylinder) {
+  if (!g || !centre) return gfail(LBM_EINVAL, "null argument");
+  if (!(radius > 0.0) || !std::isfinite(radius)) return gfail(LBM_EINVAL, "radius must be finite and > 0");
+  Sph s{};
+  for (int a = 0; a < 3; ++a) {
+    s.c[a] = (g->lattice == LBM_D2Q9 && a == 2) ? 0.0 : centre[a];
+    s.V[a] = V ? V[a] : 0.0;
+    s.Om[a] = Omega ? Omega[a] : 0.0;
+    s.ax[a] = (cylinder && a == 2) ? 0.0 : 1.0;
+    if (!std::isfinite(s.c[a]) || !std::isfinite(s.V[a]) || !std::isfinite(s.Om[a]))
+      return gfail(LBM_EINVAL, "non-finite centre or motion");
+  }
+  s.r = radius;
+  s.inside = solid_inside ? 1 : 0;
+  g->sph.push_back(s);
+  g->built = false;
+  return LBM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -143,21 +167,15 @@ int lbm_geometry_create(int32_t lattice, int32_t nx, int32_t ny, int32_t nz, int
   return LBM_OK;
 }
 
+
 int lbm_geometry_add_sphere(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
                             const double V[3], const double Omega[3]) {
-  if (!g || !centre) return gfail(LBM_EINVAL, "null argument");
-  if (!(radius > 0.0)) return gfail(LBM_EINVAL, "radius must be > 0");
-  Sph s{};
-  for (int a = 0; a < 3; ++a) {
-    s.c[a] = (g->lattice == LBM_D2Q9 && a == 2) ? 0.0 : centre[a];
-    s.V[a] = V ? V[a] : 0.0;
-    s.Om[a] = Omega ? Omega[a] : 0.0;
-  }
-  s.r = radius;
-  s.inside = solid_inside ? 1 : 0;
-  g->sph.push_back(s);
-  g->built = false;
-  return LBM_OK;
+  return add_round(g, centre, radius, solid_inside, V, Omega, false);
+}
+
+int lbm_geometry_add_cylinder(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
+                              const double V[3], const double Omega[3]) {
+  return add_round(g, centre, radius, solid_inside, V, Omega, true);
 }
 
 int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, const double* radii) {
@@ -191,7 +209,7 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
   // classification
   double rmax = 0.0;
   for (const Sph& s : g->sph) {
-    if (!s.inside) {
+    if (!s.inside || s.ax[2] == 0.0) {   // outside shapes and cylinders: every node
       for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
           for (int x = 0; x < nx; ++x) {
@@ -239,7 +257,7 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
   std::vector<int> outside;
   for (int k = 0; k < (int)g->sph.size(); ++k) {
     const Sph& s = g->sph[k];
-    if (!s.inside) {
+    if (!s.inside || s.ax[2] == 0.0) {   // candidates of every link
       outside.push_back(k);
       continue;
     }
@@ -338,7 +356,7 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
           if (owner < (int)g->sph.size()) {
             const Sph& s = g->sph[owner];
             double r[3];
-            for (int a = 0; a < 3; ++a) r[a] = min_image(g, a, xw[a] - s.c[a]);
+            for (int a = 0; a < 3; ++a) r[a] = min_image(g, a, xw[a] - s.c[a]) * s.ax[a];
             u[0] = s.V[0] + (s.Om[1] * r[2] - s.Om[2] * r[1]);
             u[1] = s.V[1] + (s.Om[2] * r[0] - s.Om[0] * r[2]);
             u[2] = s.V[2] + (s.Om[0] * r[1] - s.Om[1] * r[0]);

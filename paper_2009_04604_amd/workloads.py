@@ -20,6 +20,27 @@ def annulus_geometry(p):
     return mask, links
 
 
+def annulus3d_geometry(p, lattice="D3Q19", nz=4):
+    """The circular Couette annulus on a 3D lattice: coaxial cylinders along z
+    (inner turning at u_inner, outer at rest), periodic in z."""
+    g = B.Geometry(lattice, p["nx"], p["ny"], nz)
+    om1 = p["u_inner"] / p["r1"]
+    g.add_cylinder(p["centre"], p["r1"], True, Omega=(0, 0, om1))
+    g.add_cylinder(p["centre"], p["r2"], False)
+    mask, links = g.build()
+    g.close()
+    return mask, links
+
+
+def couette3d_domain(p, lattice="D3Q19", nz=4, storage="f64", variant="FQ", collision="BGK", magic=3.0 / 16.0,
+                     wall_neq="bounceback"):
+    mask, links = annulus3d_geometry(p, lattice, nz)
+    d = B.Domain(lattice, p["nx"], p["ny"], nz, mask, p["tau"], storage=storage, collision=collision, magic=magic)
+    d.set_boundary_links(links, variant=variant)
+    d.set_wall_neq(wall_neq)
+    return d, mask, links
+
+
 def channel_geometry(p):
     """Channel with a cylinder: parabolic inlet at x = -1/2, walls at y = -1/2 and
     ny - 1/2, zero-gradient outlet at +x."""

@@ -101,6 +101,30 @@ def test_builder_matches_oracle_packing_d3q27(B):
 
 
 
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q27"])
+def test_builder_matches_oracle_cylinders(B, lat):
+    """Coaxial cylinders along z (the 3D annulus) plus small spheres between them,
+    which exercises the candidate lists of bucketed spheres next to cylinders."""
+    p = synth.couette_annulus(scale=0.75)
+    nz = 10            # a ball and its periodic image stay apart: r + sqrt(3) < nz / 2
+    om1 = p["u_inner"] / p["r1"]
+    balls = [((p["centre"][0] + 0.5 * (p["r1"] + p["r2"]), p["centre"][1] + 0.3, 2.7), 1.9),
+             ((p["centre"][0] - 0.3, p["centre"][1] - 0.5 * (p["r1"] + p["r2"]), 4.1), 2.2)]
+    g = B.Geometry(lat, p["nx"], p["ny"], nz)
+    g.add_cylinder(p["centre"], p["r1"], True, Omega=(0, 0, om1))
+    g.add_cylinder(p["centre"], p["r2"], False)
+    for c, r in balls:
+        g.add_sphere(c, r, True)
+    mask, links = g.build()
+    g.close()
+    dom = G.Domain(lattice.get(lat), p["nx"], p["ny"], nz)
+    sh = [G.Cylinder(p["centre"], p["r1"], True, Omega=(0, 0, om1)), G.Cylinder(p["centre"], p["r2"], False)]
+    sh += [G.Sphere(c, r, True) for c, r in balls]
+    fluid = G.classify(dom, sh)
+    _compare(mask, links, fluid, G.cut_links(dom, fluid, sh))
+    assert set(np.unique(links["shape"])) == {0, 1, 2, 3}
+
+
 def test_binding_loads_torch_before_the_library():
     """The library must bind to the HIP runtime torch loads (torch's streams and
     memory are passed to it); loading it first would pull in a second runtime."""

@@ -145,3 +145,26 @@ def test_metrics_elementary():
     assert abs(metrics.rrse(a * 1.01, a) - 0.01) < 1e-14
     assert abs(metrics.rel_l2(a * 0.98, a) - 0.02) < 1e-14
     assert abs(metrics.mean_density_fluctuation([1.1, 0.9, 1.3]) - 0.1) < 1e-14
+
+
+def test_wall_distance_matters_little_for_elibb_and_much_for_hwbb():
+    """The paper finds that q has a small effect on the error of the ELIBB
+    variants and a large one for half-way bounce-back (Sec. III.B, q-dependence):
+    force-driven Poiseuille (BGK, tau 0.8) between walls at distance q from the
+    first and last node layers, against the parabola between the true walls."""
+    ny, F, tau = 8, 1e-5, 0.8
+    nu = (tau - 0.5) / 3
+    err = {}
+    for v in ("FQ", "HWBB"):
+        for q in (0.1, 0.5, 0.9):
+            sim = cases.channel(3, ny, q=q, tau=tau, force=(F, 0, 0), variant=v)
+            sim.run(int(12 * ny * ny / nu))
+            _, u = sim.macros()
+            y = sim.dom.coords()[1].astype(float) + q           # distance from the lower wall
+            H = ny - 1 + 2 * q
+            uth = F / (2 * nu) * y * (H - y)
+            err[v, q] = np.abs(u[0] - uth).max() / uth.max()
+    assert err["FQ", 0.5] == err["HWBB", 0.5]                   # q = 1/2: the same scheme
+    assert max(err["FQ", q] for q in (0.1, 0.5, 0.9)) < 0.04
+    for q in (0.1, 0.9):
+        assert err["HWBB", q] > 5 * err["FQ", q]

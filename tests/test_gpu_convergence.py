@@ -73,3 +73,26 @@ def test_couette_second_order_trt_and_regularized(gpu_lib, kw):
     errs, slope = _errors(gpu_lib, "f64", **kw)
     print("case", kw, flush=True)
     assert errs[0] < 0.01 and slope > 1.8
+
+
+def test_mass_drift_stated(gpu_lib):
+    """Mass conservation (the paper's metric |sum_i (rho_i - rho_0) / N| over the
+    annulus at t* = t u / (r2 - r1) = 3, TRT, tau = 1): at the coarsest grid every
+    interpolated variant drifts more than half-way bounce-back, as the paper
+    reports, and every variant's drift falls under refinement (values printed)."""
+    from paper_2009_04604_amd import workloads as W
+    drift = {}
+    for v in ("FQ", "F", "U", "HWBB"):
+        for s in (1.0, 2.0, 4.0):
+            p = synth.couette_annulus(s)
+            p["tau"] = 1.0
+            d, mask, _ = W.couette_domain(p, storage="f64", variant=v, collision="TRT", magic=3.0 / 16.0)
+            d.step(int(round(3 * (p["r2"] - p["r1"]) / p["u_inner"])))
+            rho = d.macros()[0]
+            d.close()
+            drift[v, s] = abs((rho[np.asarray(mask, bool)] - 1.0).mean())
+        print("mass drift", v, [drift[v, s] for s in (1.0, 2.0, 4.0)], flush=True)
+    for v in ("FQ", "F", "U"):
+        assert drift[v, 1.0] > drift["HWBB", 1.0]
+    for v in ("FQ", "F", "U", "HWBB"):
+        assert drift[v, 4.0] < drift[v, 1.0]

@@ -96,3 +96,37 @@ def test_mass_drift_stated(gpu_lib):
         assert drift[v, 1.0] > drift["HWBB", 1.0]
     for v in ("FQ", "F", "U", "HWBB"):
         assert drift[v, 4.0] < drift[v, 1.0]
+
+
+def test_viscosity_dependence_bgk_and_trt(gpu_lib):
+    """The paper's tau-sensitivity findings (48^2 annulus, FP64, the same viscous
+    time at every tau): with BGK the wall error grows with tau (the boundary's
+    viscosity dependence); with TRT (Lambda = 3/16) half-way bounce-back no longer
+    depends on tau and ELIBB-FQ stays within a factor two over tau in [0.6, 2]."""
+    from paper_2009_04604_amd import workloads as W
+    taus = (0.6, 0.8, 1.0, 1.5, 2.0)
+    e = {}
+    for coll in ("BGK", "TRT"):
+        for v in ("FQ", "HWBB"):
+            for tau in taus:
+                p = synth.couette_annulus(1.0)
+                p["tau"] = tau
+                nu = (tau - 0.5) / 3
+                d, mask, _ = W.couette_domain(p, storage="f64", variant=v, collision=coll, magic=3.0 / 16.0)
+                d.step(int(3500 * 0.1 / nu))
+                _, u, _, _ = d.macros()
+                d.close()
+                n = p["nx"]
+                fl = np.asarray(mask, bool)
+                y, x = np.divmod(np.arange(n * n), n)
+                r = np.hypot(x[fl] - p["centre"][0], y[fl] - p["centre"][1])
+                uth = analytic.circular_couette(r, p["r1"], p["r2"], p["u_inner"] / p["r1"])
+                e[coll, v, tau] = metrics.rrse(np.linalg.norm(u[fl], axis=1), uth)
+            print("tau sweep", coll, v, [e[coll, v, t] for t in taus], flush=True)
+    assert e["BGK", "FQ", 2.0] > 5 * e["BGK", "FQ", 0.8]
+    assert e["BGK", "HWBB", 2.0] > 2 * e["BGK", "HWBB", 0.8]
+    trt_hw = [e["TRT", "HWBB", t] for t in taus]
+    assert max(trt_hw) < 1.01 * min(trt_hw)
+    trt_fq = [e["TRT", "FQ", t] for t in taus]
+    assert max(trt_fq) < 2 * min(trt_fq)
+    assert e["TRT", "FQ", 2.0] < e["BGK", "FQ", 2.0] / 5

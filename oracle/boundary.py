@@ -162,32 +162,49 @@ def equilibrium_dir(lat, i, rho, u):
 WALL_NEQ = ("bounceback", "regularized")
 
 
-def hermite2(lat, i):
-    """Second-order Hermite polynomial of directions i (App. Hermite):
-    H_ab = c_a c_b - cs2 delta_ab over the lattice's D axes.  Returns (n, D, D)."""
+def _hermite2_of(lat):
+    """H_ab = c_a c_b - cs2 delta_ab of every direction, over the lattice's D axes: (Q, D, D)."""
     D = lat.d
-    c = lat.c[i][:, :D].astype(np.float64)
+    c = lat.c[:, :D].astype(np.float64)
     return np.einsum("na,nb->nab", c, c) - lat.cs2 * np.eye(D)[None]
 
 
-def hermite3(lat, i):
-    """Third-order Hermite polynomial of directions i (App. Hermite):
-    H_abg = c_a c_b c_g - cs2 (delta_ab c_g + delta_ag c_b + delta_bg c_a).
-    Returns (n, D, D, D)."""
+def _hermite3_of(lat):
+    """H_abg = c_a c_b c_g - cs2 (delta_ab c_g + delta_ag c_b + delta_bg c_a) of
+    every direction: (Q, D, D, D)."""
     D = lat.d
-    c = lat.c[i][:, :D].astype(np.float64)
+    c = lat.c[:, :D].astype(np.float64)
     I = np.eye(D)
     ccc = np.einsum("na,nb,ng->nabg", c, c, c)
     dc = (np.einsum("ab,ng->nabg", I, c) + np.einsum("ag,nb->nabg", I, c) + np.einsum("bg,na->nabg", I, c))
     return ccc - lat.cs2 * dc
 
 
+_TABLES = {}
+
+
+def _tables(lat):
+    """Per-lattice tables: H2, H3 and c c of every direction (computed once)."""
+    if lat.name not in _TABLES:
+        c = lat.c[:, :lat.d].astype(np.float64)
+        _TABLES[lat.name] = (_hermite2_of(lat), _hermite3_of(lat), np.einsum("ja,jb->jab", c, c))
+    return _TABLES[lat.name]
+
+
+def hermite2(lat, i):
+    """Second-order Hermite polynomial of directions i (App. Hermite), (n, D, D)."""
+    return _tables(lat)[0][i]
+
+
+def hermite3(lat, i):
+    """Third-order Hermite polynomial of directions i (App. Hermite), (n, D, D, D)."""
+    return _tables(lat)[1][i]
+
+
 def neq_stress(lat, f, feq):
     """Non-equilibrium second moment Pi_ab = sum_j c_ja c_jb (f_j - f^eq_j) over
     the lattice's D axes.  f, feq: (Q, n).  Returns (n, D, D)."""
-    D = lat.d
-    c = lat.c[:, :D].astype(np.float64)
-    return np.einsum("ja,jb,jn->nab", c, c, f - feq)
+    return np.tensordot(f - feq, _tables(lat)[2], axes=(0, 0))
 
 
 def regularized_neq(lat, i, Pi, u):

@@ -102,11 +102,12 @@ def collide(lat, f, tau, force, magic=None):
 class Simulation:
     """A lattice with a fixed (or externally updated) geometry and link list."""
 
-    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
+    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None, rho_out=None):
         self.dom = dom
         self.lat = dom.lat
         self.tau = float(tau)
         self.magic = None if magic is None else float(magic)   # TRT magic parameter, None = BGK
+        self.rho_out = None if rho_out is None else float(rho_out)   # density of open (q = 0) links
         self.force = np.asarray(force, dtype=np.float64).reshape(3)
         self.rho0 = float(rho0)
         self.u0 = np.asarray(u0, dtype=np.float64).reshape(3)
@@ -129,7 +130,11 @@ class Simulation:
         self.variant, self.q_cut, self.wall_neq = variant, float(q_cut), wall_neq
         L = {k: np.asarray(v) for k, v in links.items()}
         self.links = L
-        self.coef = boundary.coefficients(variant, L["q"], q_cut)
+        # open links (q = 0, boundary.open_link_value) have no interpolation weights
+        self.open = L["q"] == 0.0 if L["node"].size else np.zeros(0, bool)
+        if self.open.any() and self.rho_out is None:
+            raise ValueError("open (q = 0) links need the outlet density rho_out")
+        self.coef = boundary.coefficients(variant, np.where(self.open, 1.0, L["q"]), q_cut)
         cut = np.zeros((lat.q, dom.N), dtype=bool)
         if L["node"].size:
             if not fl[L["node"]].all():
@@ -200,6 +205,9 @@ class Simulation:
             P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"],
                                      self.wall_neq)
             fnew[d, n] = boundary.reconstruct(self.coef, P)
+            if self.open.any():
+                o = self.open
+                fnew[d[o], n[o]] = boundary.open_link_value(lat, d[o], self.rho_out, u[:, n[o]], fstar[:, n[o]])
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
             self.last_force = boundary.momentum_exchange(lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp,
                                                          self.n_groups)
@@ -256,7 +264,7 @@ class Simulation:
 
 
 def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01, magic=None,
-            wall_neq="bounceback"):
+            wall_neq="bounceback", rho_out=None):
     """f(x, t+1) at the given fluid nodes only, from the full state f (Q, N) at t.
 
     The same step as Simulation.step, evaluated node by node: every pulled
@@ -300,8 +308,12 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
         if is_cut.any():
             sel = np.flatnonzero(is_cut)
             li = order[k[sel]]
-            coef = boundary.coefficients(variant, L["q"][li], q_cut)
+            op = L["q"][li] == 0.0
+            coef = boundary.coefficients(variant, np.where(op, 1.0, L["q"][li]), q_cut)
             P = boundary.link_points(lat, np.full(sel.size, i), rho_s[sel], feq_s[:, sel], f[:, nodes[sel]],
                                      fs_self[:, sel], L["uw_t"][:, li], L["uw_t1"][:, li], wall_neq)
             out[i, sel] = boundary.reconstruct(coef, P)
+            if op.any():
+                out[i, sel[op]] = boundary.open_link_value(lat, np.full(op.sum(), i), rho_out, u_s[:, sel[op]],
+                                                           fs_self[:, sel[op]])
     return out

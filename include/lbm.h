@@ -117,19 +117,31 @@ int lbm_init_domain(const lbm_domain_desc* d, const uint8_t* fluid_mask, lbm_dom
  * boundary node `node` after streaming, because node - c_dir is solid or lies
  * beyond a non-periodic face.  Its f_dir(x_F, t+1) is rebuilt by eq.
  * ELIBB-general from the node's own time-t data:
- *   q      (0, 1]: |x_W - x_F| / |c_dir|, x_W the first wall crossing
+ *   q      (0, 1]: |x_W - x_F| / |c_dir|, x_W the first wall crossing; or 0 for an
+ *          open link at the outlet density (see lbm_set_outlet_density)
  *   uw_t   [3*n] wall velocity at x_W at time t (NULL: wall at rest)
  *   uw_t1  [3*n] wall velocity at x_W at time t+1 (NULL: equal to uw_t)
  * Velocity triples are (x, y, z) per link; z ignored for D2Q9.
  * Validation (LBM_EINVAL, message names the first offending link): node is a
  * fluid node; 1 <= dir < Q; node - c_dir is not a fluid node; the pair is not
- * covered by the outlet; 0 < q <= 1; no duplicate (node, dir); every missing
- * population of every fluid node is covered by a link or by the outlet;
+ * covered by the outlet; 0 < q <= 1, or q = 0 once lbm_set_outlet_density was
+ * called; no duplicate (node, dir); every missing population of every fluid node
+ * is covered by a link or by the outlet;
  * variant in range; q_cutoff >= 0 (the paper uses 0.01).  Host arrays are
  * copied. */
 int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir,
                            const double* q, const double* uw_t, const double* uw_t1,
                            int32_t variant, double q_cutoff);
+
+/* Density of the domain's open links (q = 0, see lbm_geometry_add_pressure_face):
+ * each missing population i of an open link is rebuilt by the anti-bounce-back
+ * rule of a pressure boundary half-way beyond the node,
+ *   f_i(x_F, t+1) = -f*_ibar(x_F, t) + 2 w_i rho_out [1 + 9/2 (c_i.u)^2 - 3/2 u.u],
+ * u the node's velocity at t.  Not in the paper (which treats walls only): a
+ * fixed-density outlet that keeps the mass bounded, where the zero-gradient outlet
+ * lets it grow.  Must be set before links with q = 0 are installed; takes effect
+ * from the next step.  LBM_EINVAL unless rho_out is finite and > 0. */
+int lbm_set_outlet_density(lbm_domain d, double rho_out);
 
 /* Selects the wall non-equilibrium estimator of every cut link of the domain
  * (eq. ELIBB-approximations).  LBM_NEQ_BOUNCEBACK: f_i^neq(x_W) is taken as the
@@ -311,6 +323,13 @@ int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, c
  * 4 (y + 1/2)(ny - 1/2 - y) / ny^2 at the wall point (parabolic inlet across y). */
 int lbm_geometry_add_face_wall(lbm_geometry g, int32_t face, double q_face, const double uw[3],
                                int32_t profile);
+
+/* An open face at fixed density on a non-periodic axis (not the zero-gradient
+ * outlet face): every population of the first node layer whose pull source lies
+ * beyond the face becomes a link with q = 0 and zero wall velocity, rebuilt at the
+ * domain's outlet density (lbm_set_outlet_density).  LBM_EINVAL for a periodic
+ * axis or the zero-gradient outlet's face. */
+int lbm_geometry_add_pressure_face(lbm_geometry g, int32_t face);
 /* Classify nodes and find every cut link.  Outputs counts. */
 int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links);
 /* Copy the results of lbm_geometry_build: mask [N]; node, dir, q [n_links];

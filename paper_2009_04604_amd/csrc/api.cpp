@@ -156,6 +156,7 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.q_cut = d->q_cut;
   p.outlet_face = d->desc.outlet_face;
   p.wall_neq = d->wall_neq;
+  p.rho_out = d->rho_out;
   return p;
 }
 
@@ -458,7 +459,11 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   for (int64_t k = 0; k < n_links; ++k) {
     if (node[k] < 0 || node[k] >= N) return fail(LBM_EINVAL, where(k) + ": node out of range");
     if (dir[k] < 1 || dir[k] >= L.Q) return fail(LBM_EINVAL, where(k) + ": dir out of range");
-    if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1]");
+    if (q[k] == 0.0) {
+      if (!(d->rho_out > 0.0)) return fail(LBM_EINVAL, where(k) + ": an open link (q = 0) needs lbm_set_outlet_density first");
+    } else if (!(q[k] > 0.0 && q[k] <= 1.0)) {
+      return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1], or be 0 for an open link");
+    }
     for (int a = 0; a < 3; ++a) {
       if (uw_t && !std::isfinite(uw_t[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t");
       if (uw_t1 && !std::isfinite(uw_t1[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t1");
@@ -514,7 +519,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   for (int64_t k = 0; k < n_links; ++k) {
     const int64_t o = order[k];
     qd[k] = q[o];
-    if (moving) {
+    if (moving && q[o] != 0.0) {   // open links have no wall term
       const int i = dir[o];
       const double* u0 = uw_t ? uw_t + 3 * o : nullptr;
       const double* u1 = uw_t1 ? uw_t1 + 3 * o : u0;
@@ -614,6 +619,17 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   d->q_cut = q_cutoff;
   d->links_ok = true;
   d->uid = next_uid();
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_set_outlet_density(lbm_domain d, double rho_out) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (!(rho_out > 0.0) || !std::isfinite(rho_out)) return fail(LBM_EINVAL, "outlet density must be finite and > 0");
+  if (rho_out != d->rho_out) {
+    d->rho_out = rho_out;
+    d->uid = next_uid();   // batches rebuild their tables
+  }
   clear_error();
   return LBM_OK;
 }

@@ -114,6 +114,7 @@ struct StepParams {
   int32_t outlet_face;
   int32_t wall_neq;              // 0: bounced non-equilibrium (eq. neqbb-s); 1: regularised (eq. fi_neq);
                                  // selects the kernel variant (batches group by it)
+  double rho_out;                // density of open links (q = 0)
 };
 
 struct InitParams {
@@ -271,6 +272,7 @@ struct lbm_domain_s {
   int32_t variant;
   double q_cut;
   int32_t wall_neq;              // LBM_NEQ_BOUNCEBACK or LBM_NEQ_REGULARIZED
+  double rho_out;                // density of open links (q = 0); 0 = not set
   void* luv;                     // [6][nl or link_cap] u_w(t), u_w(t+1) per link (moving walls), or null
   // reductions
   double* partials;

@@ -13,7 +13,8 @@ nodes, so that a read of solid data poisons the result).  One step t -> t+1
    (see collide);
 3. streaming: f_i(x, t+1) = f*_i(x - c_i, t) for every pair that is not a cut
    link, wrapping on periodic axes (eq. LBE);
-4. zero-gradient outlet (a reading: open boundaries are outside the paper);
+4. zero-gradient outlet (a reading: open boundaries are outside the paper); open
+   faces at fixed density are links instead (step 5);
 5. every cut link is rebuilt by the ELIBB (eq. ELIBB-general) from node F's own
    time-t data (see oracle.boundary).
 
@@ -26,8 +27,11 @@ valid populations (rho0 if there are none).
 Status: pinned -- exact invariants (rest, co-moving uniform flow, periodic mass
 and momentum, momentum growth by F per node and step under Guo forcing), the
 textbook half-way bounce-back reduction, and closed-form flows (circular
-Couette, impulsively started Couette, force-driven Poiseuille); the outlet and
-the refill are "parity unpinned" beyond self-consistency checks.
+Couette, impulsively started Couette, force-driven Poiseuille); the open links
+of a pressure face (q = 0, boundary.open_link_value) against the developed
+Poiseuille channel and its pressure gradient; the zero-gradient outlet only as
+far as its mass growth under a velocity inlet, and the refill, are "parity
+unpinned" beyond self-consistency checks.
 """
 import numpy as np
 

@@ -157,6 +157,7 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.outlet_face = d->desc.outlet_face;
   p.wall_neq = d->wall_neq;
   p.rho_out = d->rho_out;
+  p.open_links = d->rho_out > 0.0;
   return p;
 }
 

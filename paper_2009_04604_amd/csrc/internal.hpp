@@ -115,6 +115,7 @@ struct StepParams {
   int32_t wall_neq;              // 0: bounced non-equilibrium (eq. neqbb-s); 1: regularised (eq. fi_neq);
                                  // selects the kernel variant (batches group by it)
   double rho_out;                // density of open links (q = 0)
+  int32_t open_links;            // the domain may hold open links (its outlet density is set)
 };
 
 struct InitParams {

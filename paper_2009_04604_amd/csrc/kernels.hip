@@ -561,7 +561,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       }
       R v = a.a4 * n_pre + a.a5 * n_post + a.a2 * hs_b + w * (mb.drho * (a.a4 + a.a5) + mb.rho * gw);
       v += a.a3 * col.post(cx, cy, cz, w, hi, hb, mb);
-      if (q == R(0)) {
+      if (p.open_links && q == R(0)) {
         // open link (q = 0) at the outlet density: anti-bounce-back with the node's
         // velocity, h_i = -h*_ibar + 2 (w rho_out [1 + 4.5 (c.u)^2 - 1.5 u.u] - w)
         const R cu = cx * mb.ux + cy * mb.uy + cz * mb.uz;

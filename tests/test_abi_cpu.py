@@ -150,3 +150,25 @@ def test_binding_loads_torch_before_the_library():
             "assert 'torch' not in sys.modules; B.lib(); assert 'torch' in sys.modules; print('ok')")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr
+
+
+def test_builder_rejects_bad_shapes(B):
+    """Host-only argument checks of the builder's shapes (no GPU needed)."""
+    g = B.Geometry("D3Q19", 16, 16, 8, periodic=(True, False, True))
+    for r in (0.0, -1.0, float("inf")):
+        with pytest.raises(B.LBMError) as e:
+            g.add_cylinder((8.0, 8.0, 0.0), r)
+        assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LBMError) as e:
+        g.add_cylinder((8.0, float("nan"), 0.0), 3.0)
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LBMError) as e:
+        g.add_pressure_face("+x")                      # periodic axis
+    assert e.value.code == B.LBM_EINVAL
+    g.add_pressure_face("+y")
+    g.close()
+    g = B.Geometry("D2Q9", 32, 16, 1, periodic=(False, False, True), outlet_face="+x")
+    with pytest.raises(B.LBMError) as e:
+        g.add_pressure_face("+x")                      # the zero-gradient outlet's face
+    assert e.value.code == B.LBM_EINVAL
+    g.close()

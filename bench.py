@@ -179,8 +179,9 @@ def cpu_baseline(name, seconds, wall_neq="bounceback"):
 
 def served_section(a, log):
     """Served D2Q9 requests (circular Couette L x L and cylinder channel 2L x L,
-    L ~ U{64..1024}, Poisson arrivals): continuously batched FP16-shifted form
-    against the plain FP32 one-request-at-a-time form on the same arrivals."""
+    L ~ U{64..1024}, Poisson arrivals): continuously batched FP16-shifted form,
+    and the same batching in FP32 (results identical to the plain form's), against
+    the plain FP32 one-request-at-a-time form on the same arrivals."""
     import numpy as np
     import torch
     import synth
@@ -214,6 +215,12 @@ def served_section(a, log):
     served = srv.run(reqs)
     exs.close()
     log("served: done")
+    # the served form at exactly the plain form's error: FP32 storage, same batching
+    exs32 = serve.GpuExecutor(storage="f32", keep_fields=ids)
+    srv32 = serve.Server(exs32, hbm_budget=budget, chunk=100, prepare_workers=4)
+    log("served: batched FP32 run")
+    served32 = srv32.run(reqs)
+    exs32.close()
     exp = serve.GpuExecutor(storage="f32", keep_fields=ids)
     plain = serve.run_plain(exp, reqs)
     exp.close()
@@ -226,10 +233,15 @@ def served_section(a, log):
     srv0 = serve.Server(exc, hbm_budget=budget, chunk=100, prepare_workers=4)
     cap_served = serve.summarize(srv0.run(reqs0))["solves_per_s"]
     exc.close()
+    exc = serve.GpuExecutor(storage="f32")
+    srv0 = serve.Server(exc, hbm_budget=budget, chunk=100, prepare_workers=4)
+    cap_served32 = serve.summarize(srv0.run(reqs0))["solves_per_s"]
+    exc.close()
     cap_plain = serve.busy_capacity(plain)
     log("served: FP64 references")
     ref = serve.GpuExecutor(storage="f64", keep_fields=ids)
-    e_s, e_p = [], []
+    e_s, e_p, e_s32 = [], [], []
+    same32 = True
     for k in sample:
         q = reqs[k]
         h = ref.admit(ref.prepare(q))
@@ -239,9 +251,11 @@ def served_section(a, log):
         nrm = np.linalg.norm(u)
         e_s.append(float(np.linalg.norm(served[k]["result"]["u"] - u) / nrm))
         e_p.append(float(np.linalg.norm(plain[k]["result"]["u"] - u) / nrm))
+        e_s32.append(float(np.linalg.norm(served32[k]["result"]["u"] - u) / nrm))
+        same32 = same32 and np.array_equal(served32[k]["result"]["u"], plain[k]["result"]["u"])
     ref.close()
     torch.cuda.synchronize()
-    ss, sp = serve.summarize(served), serve.summarize(plain)
+    ss, sp, s32 = serve.summarize(served), serve.summarize(plain), serve.summarize(served32)
     nodes = sum(r["nx"] * r["ny"] for r in reqs)
     return {
         "workload": f"{len(reqs)} D2Q9 requests (circular Couette LxL / cylinder channel 2LxL, L~U{{64..1024}}), "
@@ -256,8 +270,16 @@ def served_section(a, log):
         "plain": {"storage": "f32, one request at a time (FIFO)", "solves_per_s": round(sp["solves_per_s"], 3),
                   "p50_s": round(sp["p50_s"], 4), "p99_s": round(sp["p99_s"], 4), "makespan_s": round(sp["makespan_s"], 3),
                   "E_vs_f64_max": max(e_p), "E_vs_f64_median": float(np.median(e_p))},
-        "capacity_solves_per_s": {"served": round(cap_served, 3), "plain": round(cap_plain, 3),
-                                  "ratio": round(cap_served / cap_plain, 3),
+        "served_f32": {"storage": "f32, continuous batching (the plain form's arithmetic)",
+                       "solves_per_s": round(s32["solves_per_s"], 3), "p50_s": round(s32["p50_s"], 4),
+                       "p99_s": round(s32["p99_s"], 4), "makespan_s": round(s32["makespan_s"], 3),
+                       "peak_resident": srv32.peak_active, "E_vs_f64_max": max(e_s32),
+                       "E_vs_f64_median": float(np.median(e_s32)), "fields_identical_to_plain": bool(same32)},
+        "equal_error_speedup_solves_per_s": round(s32["solves_per_s"] / sp["solves_per_s"], 3),
+        "equal_error_p99_ratio_plain_over_served": round(sp["p99_s"] / s32["p99_s"], 3),
+        "capacity_solves_per_s": {"served": round(cap_served, 3), "served_f32": round(cap_served32, 3),
+                                  "plain": round(cap_plain, 3), "ratio": round(cap_served / cap_plain, 3),
+                                  "ratio_f32": round(cap_served32 / cap_plain, 3),
                                   "how": "served: all requests queued at t = 0, over the makespan; "
                                          "plain: requests per second of busy time in the run above"},
         "speedup_solves_per_s": round(ss["solves_per_s"] / sp["solves_per_s"], 3),

@@ -110,6 +110,23 @@ struct Moments {
   R drho, rho, ux, uy, uz, uu;
 };
 
+// c_i . v for a direction whose components are constants after unrolling,
+// written as signed sums (products with 0 are not dropped by the compiler).
+template <class L, typename R>
+__device__ __forceinline__ R cdot(int i, R x, R y, R z) {
+  R s = R(0);
+  bool any = false;
+  auto acc = [&](int c, R v) {
+    if (c == 0) return;
+    s = any ? (c > 0 ? s + v : s - v) : (c > 0 ? v : -v);
+    any = true;
+  };
+  acc(L::cx(i), x);
+  acc(L::cy(i), y);
+  acc(L::cz(i), z);
+  return s;
+}
+
 // Post-collision shifted population, with h^eq_i = f^eq_i - w_i =
 // w_i [ (rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 uu) ] (eq. Eq2ndOrder, c_s^2 = 1/3)
 // and Guo's source S_i = w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]:
@@ -123,6 +140,7 @@ template <typename R, bool TRT>
 struct Collider {
   R omega, kf, Fx, Fy, Fz;
   R omega_m, kf_m;               // TRT: omega- and 1 - omega-/2
+  R src_eq;                      // BGK: 3 (1 - omega/2) / omega (BgkPairs)
   bool force;
   __device__ __forceinline__ R heq(R cx, R cy, R cz, R w, const Moments<R>& m) const {
     const R cu = cx * m.ux + cy * m.uy + cz * m.uz;
@@ -153,6 +171,66 @@ struct Collider {
     }
   }
 };
+
+// The BGK + Guo update above with the work of a direction and its opposite
+// shared.  The source enters through the equilibrium, omega h^eq'_i = omega h^eq_i
+// + S_i, and h^eq'_i splits into parts even and odd in c_i:
+//   h*_i = h_i + omega ([E + O] - h_i),   h*_ibar = h_ibar + omega ([E - O] - h_ibar),
+//   E = w [t + cu (4.5 rho cu + 9 s cF)],  O = w [3 rho cu + 3 s cF],
+//   t = (rho - 1) - 1.5 rho uu - 3 s u.F,  s = (1 - omega/2) / omega,
+// with cu = c_i.u, cF = c_i.F for the member i of the pair with the smaller
+// index (with F = 0 the source terms add exact zeros).  The update keeps the
+// form h + omega (h^eq - h): regrouped as (1 - omega) h + omega h^eq it biases
+// the rounding of the momentum, which then builds up over steps in steady flow.
+// The node's own update and the link rebuild, which needs the bounced
+// post-collision value again, both go through eo() and value() (explicit fused
+// operations, no contraction), so that the two agree to the bit.
+template <typename R>
+struct BgkPairs {
+  R om, t, r45, r3, s3, s9;
+  template <bool TRT>
+  __device__ __forceinline__ BgkPairs(const Collider<R, TRT>& col, const Moments<R>& m) {
+#pragma clang fp contract(off)
+    om = col.omega;
+    s3 = col.src_eq;                           // 3 s
+    s9 = R(3) * col.src_eq;                    // 9 s
+    const R uF = fma(m.uz, col.Fz, fma(m.uy, col.Fy, m.ux * col.Fx));
+    t = fma(-s3, uF, fma(R(-1.5) * m.rho, m.uu, m.drho));
+    r45 = R(4.5) * m.rho;
+    r3 = R(3) * m.rho;
+  }
+  // E and O of a pair with weight w
+  __device__ __forceinline__ void eo(R w, R cu, R cF, R& e, R& o) const {
+#pragma clang fp contract(off)
+    e = fma(cu, fma(w * r45, cu, (w * s9) * cF), w * t);
+    o = fma(w * r3, cu, (w * s3) * cF);
+  }
+  // post-collision value of a pair member from its pre-collision value
+  __device__ __forceinline__ R value(R h, R e, R o, bool lower) const {
+#pragma clang fp contract(off)
+    return fma(om, lower ? e + (o - h) : e - (o + h), h);
+  }
+  __device__ __forceinline__ R rest(R h, R w) const {
+#pragma clang fp contract(off)
+    return fma(om, w * t - h, h);
+  }
+  // post-collision values of direction i (a constant after unrolling) and of its opposite
+  template <class L>
+  __device__ __forceinline__ void pair(int i, R h, R hbar, const Moments<R>& m, const Collider<R, false>& col, R& out,
+                                       R& outbar) const {
+    R e, o;
+    eo(R(L::w(i)), cdot<L, R>(i, m.ux, m.uy, m.uz), cdot<L, R>(i, col.Fx, col.Fy, col.Fz), e, o);
+    out = value(h, e, o, true);
+    outbar = value(hbar, e, o, false);
+  }
+};
+
+// u.u with a fixed evaluation order (the node update and the link rebuild both use it)
+template <typename R>
+__device__ __forceinline__ R dot_uu(R ux, R uy, R uz) {
+#pragma clang fp contract(off)
+  return fma(uz, uz, fma(uy, uy, ux * ux));
+}
 
 // Non-equilibrium stress Pi_ab = sum_j c_ja c_jb (f_j - f^eq_j(rho, u)) over the
 // lattice's D axes.  From shifted populations h_j = f_j - w_j:
@@ -229,22 +307,39 @@ __device__ __forceinline__ R regularized_neq(R cx, R cy, R cz, R w, const Stress
 
 template <class L, typename R>
 __device__ __forceinline__ Moments<R> moments(const R (&h)[L::Q], R Fx, R Fy, R Fz) {
-  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  // over the pairs (i, ibar): the sum h_i + h_ibar enters the density, the
+  // difference h_i - h_ibar the momentum along the nonzero components of c_i
+  R drho = h[0], jx = R(0), jy = R(0), jz = R(0);
+  bool ax = false, ay = false, az = false;
+  auto acc = [](R& s, bool& any, int c, R v) {
+    if (c == 0) return;
+    s = any ? (c > 0 ? s + v : s - v) : (c > 0 ? v : -v);
+    any = true;
+  };
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    drho += h[i];
-    if (L::cx(i)) jx += R(L::cx(i)) * h[i];
-    if (L::cy(i)) jy += R(L::cy(i)) * h[i];
-    if (L::cz(i)) jz += R(L::cz(i)) * h[i];
+  for (int i = 1; i < L::Q; ++i) {
+    if (i > L::opp(i)) continue;
+    const R sum = h[i] + h[L::opp(i)], dif = h[i] - h[L::opp(i)];
+    drho += sum;
+    acc(jx, ax, L::cx(i), dif);
+    acc(jy, ay, L::cy(i), dif);
+    acc(jz, az, L::cz(i), dif);
   }
   Moments<R> m;
   m.drho = drho;
   m.rho = R(1) + drho;
-  const R inv = R(1) / m.rho;
+  R inv;
+  if constexpr (sizeof(R) == 4) {
+    // hardware reciprocal (1 ulp) refined by one Newton step
+    const R r0 = __builtin_amdgcn_rcpf(m.rho);
+    inv = r0 + r0 * (R(1) - m.rho * r0);
+  } else {
+    inv = R(1) / m.rho;
+  }
   m.ux = (jx + R(0.5) * Fx) * inv;
   m.uy = (jy + R(0.5) * Fy) * inv;
   m.uz = (jz + R(0.5) * Fz) * inv;
-  m.uu = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  m.uu = dot_uu(m.ux, m.uy, m.uz);
   return m;
 }
 
@@ -369,6 +464,15 @@ __device__ __forceinline__ uint32_t src_index_dyn(const GridGeom& g, Coords c, i
   return (uint32_t)(sx + g.px) + (uint32_t)g.NX * ((uint32_t)(sy + g.py) + (uint32_t)g.NY * (uint32_t)(sz + g.pz));
 }
 
+// A wave-uniform 64-bit value, pinned to scalar registers: an address formed
+// as base + (this) + 32-bit lane offset then keeps its base in scalar registers
+// instead of being folded into per-lane 64-bit arithmetic.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Wave-local visibility of LDS writes made by other lanes of the same wave.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -449,6 +553,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   col.Fx = R(p.force[0]);
   col.Fy = R(p.force[1]);
   col.Fz = R(p.force[2]);
+  col.src_eq = R(p.src_eq);
   col.force = p.has_force != 0;
 
   // segments without boundary nodes have no links (and need not read seg_lbase)
@@ -498,10 +603,32 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   // that the shared cache lines are written whole (nothing reads those slots);
   // the compact layout has no solid slots
   if (fluid || (!COMPACT && list_mode && inrow)) {
+    if constexpr (!TRT) {
+      // the slots of the storing lanes grow with the lane, so every address is
+      // a wave-uniform base (scalar registers) plus a small 32-bit lane offset
+      const uint32_t self0 = __builtin_amdgcn_readfirstlane(ix.self);
+      const uint32_t off = (ix.self - self0) * (uint32_t)sizeof(T);
+      auto at = [&](int i) {
+        return reinterpret_cast<T*>(reinterpret_cast<char*>(dst + uniform_u64(i * np + self0)) + off);
+      };
+      // (every storing lane is fluid in the compact layout)
+      const bool keep = COMPACT || fluid;
+      const BgkPairs<R> bp(col, m);
+      St::template store<L>(at(0), keep ? bp.rest(h[0], R(L::w(0))) : R(0), 0);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], h[L::opp(i)], m);
-      St::template store<L>(dst + i * np + ix.self, fluid ? v : R(0), i);
+      for (int i = 1; i < L::Q; ++i) {
+        if (i > L::opp(i)) continue;
+        R v, vb;
+        bp.template pair<L>(i, h[i], h[L::opp(i)], m, col, v, vb);
+        St::template store<L>(at(i), keep ? v : R(0), i);
+        St::template store<L>(at(L::opp(i)), keep ? vb : R(0), L::opp(i));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) {
+        const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], h[L::opp(i)], m);
+        St::template store<L>(dst + i * np + ix.self, fluid ? v : R(0), i);
+      }
     }
   }
   if (fluid) {
@@ -532,7 +659,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       mb.ux = stage[L::Q + 1][t];
       mb.uy = stage[L::Q + 2][t];
       mb.uz = stage[L::Q + 3][t];
-      mb.uu = mb.ux * mb.ux + mb.uy * mb.uy + mb.uz * mb.uz;
+      mb.uu = dot_uu(mb.ux, mb.uy, mb.uz);
       const R hb = stage[ib][t];
       const R hi = stage[i][t];
       const int icx = dyn_c<L, 0>(i), icy = dyn_c<L, 1>(i), icz = dyn_c<L, 2>(i);
@@ -541,7 +668,23 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       const Coef<R> a = elibb_coefficients_fast<R>(p.variant, q, qc);
       // bounced direction: c_ibar = -c_i, w_ibar = w_i
       const R he_b = col.heq(-cx, -cy, -cz, w, mb);
-      const R hs_b = col.post(-cx, -cy, -cz, w, hb, hi, mb);
+      R hs_b, hs_i;             // post-collision values of ibar and i at node F
+      if constexpr (!TRT) {
+        // the same arithmetic as the node's own update (BgkPairs), on the pair's
+        // member with the smaller index
+        const BgkPairs<R> bp(col, mb);
+        const bool low = i < ib;
+        const R s = low ? R(1) : R(-1);
+        const R cul = s * (cx * mb.ux + cy * mb.uy + cz * mb.uz);
+        const R cFl = s * (cx * col.Fx + cy * col.Fy + cz * col.Fz);
+        R e, o;
+        bp.eo(w, cul, cFl, e, o);
+        hs_b = bp.value(hb, e, o, !low);
+        hs_i = bp.value(hi, e, o, low);
+      } else {
+        hs_b = col.post(-cx, -cy, -cz, w, hb, hi, mb);
+        hs_i = col.post(cx, cy, cz, w, hi, hb, mb);
+      }
       R n_pre, n_post;
       if constexpr (REG) {
         // regularised wall non-equilibrium (eq. fi_neq): the stress of node F at
@@ -560,7 +703,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
         n_post = hs_b - he_b;            // bounced post-collision non-equilibrium
       }
       R v = a.a4 * n_pre + a.a5 * n_post + a.a2 * hs_b + w * (mb.drho * (a.a4 + a.a5) + mb.rho * gw);
-      v += a.a3 * col.post(cx, cy, cz, w, hi, hb, mb);
+      v += a.a3 * hs_i;
       if (p.open_links && q == R(0)) {
         // open link (q = 0) at the outlet density: anti-bounce-back with the node's
         // velocity, h_i = -h*_ibar + 2 (w rho_out [1 + 4.5 (c.u)^2 - 1.5 u.u] - w)

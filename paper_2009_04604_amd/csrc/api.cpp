@@ -152,6 +152,7 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.omega_minus = p.trt ? 1.0 / (d->desc.magic / (d->desc.tau - 0.5) + 0.5) : p.omega;
   for (int a = 0; a < 3; ++a) p.force[a] = d->desc.force[a];
   p.src_eq = 3.0 * (1.0 - 0.5 * p.omega) / p.omega;
+  p.src_eq_minus = 3.0 * (1.0 - 0.5 * p.omega_minus) / p.omega_minus;
   p.has_force = (d->desc.force[0] != 0.0 || d->desc.force[1] != 0.0 || d->desc.force[2] != 0.0);
   p.variant = d->variant;
   p.q_cut = d->q_cut;

@@ -108,7 +108,8 @@ struct StepParams {
   double omega_minus;            // TRT: omega-; BGK: omega
   int32_t trt;                   // 1: TRT collision
   double force[3];
-  double src_eq;                 // BGK: 3 (1 - omega/2) / omega, Guo's source folded into the equilibrium
+  double src_eq;                 // 3 (1 - omega/2) / omega: Guo's source folded into the equilibrium
+  double src_eq_minus;           // TRT: the same with omega- (odd part)
   int32_t has_force;
   int32_t variant;
   double q_cut;

@@ -139,61 +139,43 @@ __device__ __forceinline__ R cdot(int i, R x, R y, R z) {
 template <typename R, bool TRT>
 struct Collider {
   R omega, kf, Fx, Fy, Fz;
-  R omega_m, kf_m;               // TRT: omega- and 1 - omega-/2
-  R src_eq;                      // BGK: 3 (1 - omega/2) / omega (BgkPairs)
+  R omega_m;                     // TRT: omega-
+  R src_eq, src_eq_m;            // 3 (1 - omega/2) / omega, and with omega- (Pairs)
   bool force;
   __device__ __forceinline__ R heq(R cx, R cy, R cz, R w, const Moments<R>& m) const {
     const R cu = cx * m.ux + cy * m.uy + cz * m.uz;
     return w * ((m.drho - R(1.5) * m.rho * m.uu) + m.rho * cu * (R(3) + R(4.5) * cu));
   }
-  __device__ __forceinline__ R post(R cx, R cy, R cz, R w, R h, R hopp, const Moments<R>& m) const {
-    const R cu = cx * m.ux + cy * m.uy + cz * m.uz;
-    if constexpr (!TRT) {
-      const R he = w * ((m.drho - R(1.5) * m.rho * m.uu) + m.rho * cu * (R(3) + R(4.5) * cu));
-      R v = h + omega * (he - h);
-      if (force) {
-        const R cF = cx * Fx + cy * Fy + cz * Fz;
-        const R uF = m.ux * Fx + m.uy * Fy + m.uz * Fz;
-        v += (kf * w) * (R(3) * (cF - uF) + R(9) * cu * cF);
-      }
-      return v;
-    } else {
-      const R hep = w * ((m.drho - R(1.5) * m.rho * m.uu) + R(4.5) * m.rho * cu * cu);
-      const R hem = w * (R(3) * m.rho * cu);
-      const R hp = R(0.5) * (h + hopp), hm = R(0.5) * (h - hopp);
-      R v = h - omega * (hp - hep) - omega_m * (hm - hem);
-      if (force) {
-        const R cF = cx * Fx + cy * Fy + cz * Fz;
-        const R uF = m.ux * Fx + m.uy * Fy + m.uz * Fz;
-        v += (kf * w) * (R(9) * cu * cF - R(3) * uF) + (kf_m * w) * (R(3) * cF);
-      }
-      return v;
-    }
-  }
 };
 
-// The BGK + Guo update above with the work of a direction and its opposite
-// shared.  The source enters through the equilibrium, omega h^eq'_i = omega h^eq_i
-// + S_i, and h^eq'_i splits into parts even and odd in c_i:
-//   h*_i = h_i + omega ([E + O] - h_i),   h*_ibar = h_ibar + omega ([E - O] - h_ibar),
-//   E = w [t + cu (4.5 rho cu + 9 s cF)],  O = w [3 rho cu + 3 s cF],
+// The BGK / TRT + Guo updates above with the work of a direction and its
+// opposite shared.  The source enters through the equilibrium (omega h^eq'_i =
+// omega h^eq_i + (1 - omega/2) S_i, per parity for TRT), and h^eq'_i splits into
+// parts even and odd in c_i, h^eq'_i = E + O, h^eq'_ibar = E - O:
+//   E = w [t + cu (4.5 rho cu + 9 s cF)],  O = w [3 rho cu + 3 s- cF],
 //   t = (rho - 1) - 1.5 rho uu - 3 s u.F,  s = (1 - omega/2) / omega,
+//   s- = (1 - omega-/2) / omega- (= s for BGK),
 // with cu = c_i.u, cF = c_i.F for the member i of the pair with the smaller
-// index (with F = 0 the source terms add exact zeros).  The update keeps the
-// form h + omega (h^eq - h): regrouped as (1 - omega) h + omega h^eq it biases
-// the rounding of the momentum, which then builds up over steps in steady flow.
-// The node's own update and the link rebuild, which needs the bounced
-// post-collision value again, both go through eo() and value() (explicit fused
-// operations, no contraction), so that the two agree to the bit.
+// index (with F = 0 the source terms add exact zeros).  Then
+//   BGK  h*_i = h_i + omega ([E + O] - h_i),   h*_ibar = h_ibar + omega ([E - O] - h_ibar),
+//   TRT  h*_i = h_i - P - M,  h*_ibar = h_ibar - P + M,
+//        P = omega (h+ - E),  M = omega- (h- - O),  h+- = (h_i +- h_ibar) / 2.
+// Both keep the form h + correction: regrouped as (1 - omega) h + omega h^eq the
+// BGK update biases the rounding of the momentum, which then builds up over
+// steps in steady flow.  The node's own update and the link rebuild, which needs
+// the bounced post-collision values again, both go through these helpers
+// (explicit fused operations, no contraction), so that the two agree to the bit.
 template <typename R>
-struct BgkPairs {
-  R om, t, r45, r3, s3, s9;
+struct Pairs {
+  R om, omm, t, r45, r3, s3, s9, s3m;
   template <bool TRT>
-  __device__ __forceinline__ BgkPairs(const Collider<R, TRT>& col, const Moments<R>& m) {
+  __device__ __forceinline__ Pairs(const Collider<R, TRT>& col, const Moments<R>& m) {
 #pragma clang fp contract(off)
     om = col.omega;
+    omm = col.omega_m;
     s3 = col.src_eq;                           // 3 s
     s9 = R(3) * col.src_eq;                    // 9 s
+    s3m = TRT ? col.src_eq_m : col.src_eq;     // 3 s-
     const R uF = fma(m.uz, col.Fz, fma(m.uy, col.Fy, m.ux * col.Fx));
     t = fma(-s3, uF, fma(R(-1.5) * m.rho, m.uu, m.drho));
     r45 = R(4.5) * m.rho;
@@ -203,25 +185,38 @@ struct BgkPairs {
   __device__ __forceinline__ void eo(R w, R cu, R cF, R& e, R& o) const {
 #pragma clang fp contract(off)
     e = fma(cu, fma(w * r45, cu, (w * s9) * cF), w * t);
-    o = fma(w * r3, cu, (w * s3) * cF);
+    o = fma(w * r3, cu, (w * s3m) * cF);
   }
-  // post-collision value of a pair member from its pre-collision value
+  // BGK: post-collision value of a pair member from its pre-collision value
   __device__ __forceinline__ R value(R h, R e, R o, bool lower) const {
 #pragma clang fp contract(off)
     return fma(om, lower ? e + (o - h) : e - (o + h), h);
   }
+  // TRT: post-collision values of the lower member (h) and the upper one (hbar)
+  __device__ __forceinline__ void values_trt(R h, R hbar, R e, R o, R& out, R& outbar) const {
+#pragma clang fp contract(off)
+    const R p = fma(R(0.5) * om, h + hbar, -(om * e));
+    const R q = fma(R(0.5) * omm, h - hbar, -(omm * o));
+    out = (h - p) - q;
+    outbar = (hbar - p) + q;
+  }
+  // the rest population (even: relaxed with omega in both models)
   __device__ __forceinline__ R rest(R h, R w) const {
 #pragma clang fp contract(off)
     return fma(om, w * t - h, h);
   }
   // post-collision values of direction i (a constant after unrolling) and of its opposite
-  template <class L>
-  __device__ __forceinline__ void pair(int i, R h, R hbar, const Moments<R>& m, const Collider<R, false>& col, R& out,
+  template <class L, bool TRT>
+  __device__ __forceinline__ void pair(int i, R h, R hbar, const Moments<R>& m, const Collider<R, TRT>& col, R& out,
                                        R& outbar) const {
     R e, o;
     eo(R(L::w(i)), cdot<L, R>(i, m.ux, m.uy, m.uz), cdot<L, R>(i, col.Fx, col.Fy, col.Fz), e, o);
-    out = value(h, e, o, true);
-    outbar = value(hbar, e, o, false);
+    if constexpr (TRT) {
+      values_trt(h, hbar, e, o, out, outbar);
+    } else {
+      out = value(h, e, o, true);
+      outbar = value(hbar, e, o, false);
+    }
   }
 };
 
@@ -549,11 +544,11 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   col.omega = R(p.omega);
   col.kf = R(1) - R(0.5) * col.omega;
   col.omega_m = R(p.omega_minus);
-  col.kf_m = R(1) - R(0.5) * col.omega_m;
   col.Fx = R(p.force[0]);
   col.Fy = R(p.force[1]);
   col.Fz = R(p.force[2]);
   col.src_eq = R(p.src_eq);
+  col.src_eq_m = R(p.src_eq_minus);
   col.force = p.has_force != 0;
 
   // segments without boundary nodes have no links (and need not read seg_lbase)
@@ -603,32 +598,24 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   // that the shared cache lines are written whole (nothing reads those slots);
   // the compact layout has no solid slots
   if (fluid || (!COMPACT && list_mode && inrow)) {
-    if constexpr (!TRT) {
-      // the slots of the storing lanes grow with the lane, so every address is
-      // a wave-uniform base (scalar registers) plus a small 32-bit lane offset
-      const uint32_t self0 = __builtin_amdgcn_readfirstlane(ix.self);
-      const uint32_t off = (ix.self - self0) * (uint32_t)sizeof(T);
-      auto at = [&](int i) {
-        return reinterpret_cast<T*>(reinterpret_cast<char*>(dst + uniform_u64(i * np + self0)) + off);
-      };
-      // (every storing lane is fluid in the compact layout)
-      const bool keep = COMPACT || fluid;
-      const BgkPairs<R> bp(col, m);
-      St::template store<L>(at(0), keep ? bp.rest(h[0], R(L::w(0))) : R(0), 0);
+    // the slots of the storing lanes grow with the lane, so every address is
+    // a wave-uniform base (scalar registers) plus a small 32-bit lane offset
+    const uint32_t self0 = __builtin_amdgcn_readfirstlane(ix.self);
+    const uint32_t off = (ix.self - self0) * (uint32_t)sizeof(T);
+    auto at = [&](int i) {
+      return reinterpret_cast<T*>(reinterpret_cast<char*>(dst + uniform_u64(i * np + self0)) + off);
+    };
+    // (every storing lane is fluid in the compact layout)
+    const bool keep = COMPACT || fluid;
+    const Pairs<R> pr(col, m);
+    St::template store<L>(at(0), keep ? pr.rest(h[0], R(L::w(0))) : R(0), 0);
 #pragma unroll
-      for (int i = 1; i < L::Q; ++i) {
-        if (i > L::opp(i)) continue;
-        R v, vb;
-        bp.template pair<L>(i, h[i], h[L::opp(i)], m, col, v, vb);
-        St::template store<L>(at(i), keep ? v : R(0), i);
-        St::template store<L>(at(L::opp(i)), keep ? vb : R(0), L::opp(i));
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
-        const R v = col.post(R(L::cx(i)), R(L::cy(i)), R(L::cz(i)), R(L::w(i)), h[i], h[L::opp(i)], m);
-        St::template store<L>(dst + i * np + ix.self, fluid ? v : R(0), i);
-      }
+    for (int i = 1; i < L::Q; ++i) {
+      if (i > L::opp(i)) continue;
+      R v, vb;
+      pr.template pair<L, TRT>(i, h[i], h[L::opp(i)], m, col, v, vb);
+      St::template store<L>(at(i), keep ? v : R(0), i);
+      St::template store<L>(at(L::opp(i)), keep ? vb : R(0), L::opp(i));
     }
   }
   if (fluid) {
@@ -668,22 +655,26 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       const Coef<R> a = elibb_coefficients_fast<R>(p.variant, q, qc);
       // bounced direction: c_ibar = -c_i, w_ibar = w_i
       const R he_b = col.heq(-cx, -cy, -cz, w, mb);
-      R hs_b, hs_i;             // post-collision values of ibar and i at node F
-      if constexpr (!TRT) {
-        // the same arithmetic as the node's own update (BgkPairs), on the pair's
-        // member with the smaller index
-        const BgkPairs<R> bp(col, mb);
+      // post-collision values of ibar and i at node F, with the arithmetic of the
+      // node's own update (Pairs) on the pair's member with the smaller index
+      R hs_b, hs_i;
+      {
+        const Pairs<R> pr(col, mb);
         const bool low = i < ib;
         const R s = low ? R(1) : R(-1);
         const R cul = s * (cx * mb.ux + cy * mb.uy + cz * mb.uz);
         const R cFl = s * (cx * col.Fx + cy * col.Fy + cz * col.Fz);
         R e, o;
-        bp.eo(w, cul, cFl, e, o);
-        hs_b = bp.value(hb, e, o, !low);
-        hs_i = bp.value(hi, e, o, low);
-      } else {
-        hs_b = col.post(-cx, -cy, -cz, w, hb, hi, mb);
-        hs_i = col.post(cx, cy, cz, w, hi, hb, mb);
+        pr.eo(w, cul, cFl, e, o);
+        if constexpr (TRT) {
+          R vl, vu;
+          pr.values_trt(low ? hi : hb, low ? hb : hi, e, o, vl, vu);
+          hs_i = low ? vl : vu;
+          hs_b = low ? vu : vl;
+        } else {
+          hs_b = pr.value(hb, e, o, !low);
+          hs_i = pr.value(hi, e, o, low);
+        }
       }
       R n_pre, n_post;
       if constexpr (REG) {

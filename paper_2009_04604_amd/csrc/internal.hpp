@@ -49,6 +49,18 @@
 #include "lattice.hpp"
 
 namespace lbm {
+// Load through the constant address space, for data that no thread writes
+// while the kernel runs (domain metadata, parameter tables written by the host).
+// A wave-uniform address then becomes a scalar load, and a pointer loaded this
+// way is taken for a global one: memory instructions through a pointer read from
+// global memory would otherwise be flat ones (slower, and never scalar).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* ptr) {
+  return *(const __attribute__((address_space(4))) T*)ptr;
+}
+}  // namespace lbm
+
+namespace lbm {
 
 constexpr int SEG = 64;          // lanes per segment (one wavefront)
 constexpr int WAVES_PER_BLOCK = 4;

@@ -413,15 +413,15 @@ __device__ __forceinline__ CompactIndex<L> compact_index(const GridGeom& g, cons
       const uint32_t yy = (uint32_t)min(max(ys, 0), g.ny - 1), zz = (uint32_t)min(max(zs, 0), g.nz - 1);
       const uint32_t row = yy + (uint32_t)g.ny * zz;
       const uint32_t s0 = row * (uint32_t)g.nseg_x;
-      const uint64_t fm = lk.seg_fluid[s0 + sx];
-      const uint32_t fb = (uint32_t)lk.seg_fbase[s0 + sx] + 1u;
+      const uint64_t fm = load_const(lk.seg_fluid + s0 + sx);
+      const uint32_t fb = (uint32_t)load_const(lk.seg_fbase + s0 + sx) + 1u;
       // number of fluid nodes of this segment below the lane (one mbcnt pair)
       const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
       p.P[a][b] = fb + below;
       p.B[a][b] = (uint32_t)((fm >> si.lane) & 1ull);
       if (wrap) {
-        p.lo[a][b] = (uint32_t)lk.seg_fbase[s0 + (uint32_t)g.nseg_x];   // last fluid node of the row
-        p.hi[a][b] = (uint32_t)lk.seg_fbase[s0] + 1u;                     // first fluid node of the row
+        p.lo[a][b] = (uint32_t)load_const(lk.seg_fbase + s0 + (uint32_t)g.nseg_x);   // last fluid node of the row
+        p.hi[a][b] = (uint32_t)load_const(lk.seg_fbase + s0) + 1u;                     // first fluid node of the row
       } else {
         p.lo[a][b] = p.P[a][b];
         p.hi[a][b] = p.P[a][b];
@@ -528,7 +528,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   const LinkView& lk = p.lk;
   const SegInfo si = seg_info(g, block);
   if (si.seg >= g.nseg) return;
-  const uint64_t fm = lk.seg_fluid[si.seg];
+  const uint64_t fm = load_const(lk.seg_fluid + si.seg);
   if (fm == 0) return;
   const bool fluid = (fm >> si.lane) & 1ull;
   const bool inrow = si.c.x < g.nx;
@@ -552,11 +552,11 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   col.force = p.has_force != 0;
 
   // segments without boundary nodes have no links (and need not read seg_lbase)
-  const uint64_t bmask = lk.seg_bnd[si.seg];
+  const uint64_t bmask = load_const(lk.seg_bnd + si.seg);
   int lb0 = 0, lb1 = 0;
   if (bmask) {
-    lb0 = lk.seg_lbase[si.seg];
-    lb1 = lk.seg_lbase[si.seg + 1];
+    lb0 = load_const(lk.seg_lbase + si.seg);
+    lb1 = load_const(lk.seg_lbase + si.seg + 1);
   }
   const bool has_links = lb1 > lb0;
   const R* __restrict__ lq = static_cast<const R*>(lk.lq);
@@ -728,12 +728,37 @@ __global__ __launch_bounds__(BLOCK) void step_kernel(StepParams p) {
 // walks the slots b, b + gridDim.x, ...  The host orders the table (see
 // tile_table), so the grid size and the order are launch choices that leave
 // every result unchanged.
+// Entry of the step table with its pointers read through the constant address
+// space (the host writes the table before the launch), so that the arrays they
+// name are addressed with global memory instructions.
+__device__ __forceinline__ StepParams table_entry(const StepParams* e) {
+  StepParams p = *e;
+  p.src = load_const(&e->src);
+  p.dst = load_const(&e->dst);
+  const LinkView* k = &e->lk;
+  p.lk.seg_fluid = load_const(&k->seg_fluid);
+  p.lk.seg_fbase = load_const(&k->seg_fbase);
+  p.lk.seg_bnd = load_const(&k->seg_bnd);
+  p.lk.seg_lbase = load_const(&k->seg_lbase);
+  p.lk.lld = load_const(&k->lld);
+  p.lk.lnode = load_const(&k->lnode);
+  p.lk.lq = load_const(&k->lq);
+  p.lk.lg = load_const(&k->lg);
+  p.lk.lv_in = load_const(&k->lv_in);
+  p.lk.lv_out = load_const(&k->lv_out);
+  p.lk.luv = load_const(&k->luv);
+  return p;
+}
+
 template <class L, int S, bool COMPACT, bool TRT, bool REG>
 __global__ __launch_bounds__(BLOCK) void step_batch_kernel(const StepParams* __restrict__ tab,
                                                            const uint32_t* __restrict__ tiles, uint32_t nslots) {
   for (uint32_t k = blockIdx.x; k < nslots; k += gridDim.x) {
     const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[k]);
-    if (t != TILE_EMPTY) step_body<L, S, COMPACT, TRT, REG>(tab[t >> TILE_SHIFT], t & TILE_MASK);
+    if (t != TILE_EMPTY) {
+      const StepParams p = table_entry(tab + (t >> TILE_SHIFT));
+      step_body<L, S, COMPACT, TRT, REG>(p, t & TILE_MASK);
+    }
     wave_lds_sync();   // the next tile reuses the wave's LDS columns
   }
 }

@@ -304,13 +304,32 @@ __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
   if (wave < p.nreg) refill_body<L, S>(p, wave);
 }
 
+// Entry of the sphere table with its pointers read through the constant address
+// space (the host writes the table; kernels only read it), so that the arrays
+// they name are addressed with global memory instructions.
+__device__ __forceinline__ MovingParams table_entry(const MovingParams* e) {
+  MovingParams p = *e;
+  p.reg_seg = load_const(&e->reg_seg);
+  p.seg_fluid = load_const(&e->seg_fluid);
+  p.seg_prev = load_const(&e->seg_prev);
+  p.seg_bnd = load_const(&e->seg_bnd);
+  p.reg_count = load_const(&e->reg_count);
+  p.seg_lbase = load_const(&e->seg_lbase);
+  p.lld = load_const(&e->lld);
+  p.lq = load_const(&e->lq);
+  p.lg = load_const(&e->lg);
+  p.luv = load_const(&e->luv);
+  p.pop = load_const(&e->pop);
+  return p;
+}
+
 // Batched spheres: the wave table names (sphere, region wave); the kinematics
 // come from row *ctr of the table.
 __device__ __forceinline__ bool batch_wave(const MovingBatch& b, MovingParams& p, int64_t& wave) {
   const uint32_t gw = blockIdx.x * 4u + threadIdx.x / 64u;
   if (gw >= b.nwaves) return false;
   const uint32_t w = __builtin_amdgcn_readfirstlane(b.waves[gw]);
-  p = b.tab[w >> TILE_SHIFT];
+  p = table_entry(b.tab + (w >> TILE_SHIFT));
   p.k = b.kin[*b.ctr * b.nkin + p.kin_slot];
   wave = (int64_t)(w & TILE_MASK);
   return true;
@@ -323,7 +342,9 @@ __global__ __launch_bounds__(256) void classify_batch_kernel(MovingBatch b) {
   if (batch_wave(b, p, wave)) classify_body<L>(p, wave);
 }
 
-__global__ __launch_bounds__(1024) void region_scan_batch_kernel(MovingBatch b) { region_scan_body(b.tab[blockIdx.x]); }
+__global__ __launch_bounds__(1024) void region_scan_batch_kernel(MovingBatch b) {
+  region_scan_body(table_entry(b.tab + blockIdx.x));
+}
 
 template <class L, typename R>
 __global__ __launch_bounds__(256) void fill_batch_kernel(MovingBatch b) {

@@ -127,15 +127,15 @@ __device__ __forceinline__ R cdot(int i, R x, R y, R z) {
   return s;
 }
 
-// Post-collision shifted population, with h^eq_i = f^eq_i - w_i =
-// w_i [ (rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 uu) ] (eq. Eq2ndOrder, c_s^2 = 1/3)
-// and Guo's source S_i = w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]:
+// Parameters of the collision models, which act on shifted populations with
+// h^eq_i = f^eq_i - w_i = w_i [ (rho - 1) + rho (3 cu + 4.5 cu^2 - 1.5 uu) ]
+// (eq. Eq2ndOrder, c_s^2 = 1/3) and Guo's source S_i = w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]:
 //   BGK (eq. LB-BGK)  h*_i = h_i - omega (h_i - h^eq_i) + (1 - omega/2) S_i
 //   TRT (TRT models)  h*_i = h_i - omega+ (h+_i - h^eq+_i) - omega- (h-_i - h^eq-_i)
 //                            + (1 - omega+/2) S+_i + (1 - omega-/2) S-_i
 // where g+-_i = (g_i +- g_ibar)/2: h^eq+ = w [(rho - 1) + rho (4.5 cu^2 - 1.5 uu)],
-// h^eq- = 3 w rho cu, S+ = w [9 cu cF - 3 u.F], S- = 3 w cF.  `hopp` is the
-// population of the opposite direction (TRT only).
+// h^eq- = 3 w rho cu, S+ = w [9 cu cF - 3 u.F], S- = 3 w cF.  The updates are
+// evaluated by Pairs (below); heq() is the equilibrium alone (link rebuild).
 template <typename R, bool TRT>
 struct Collider {
   R omega, kf, Fx, Fy, Fz;

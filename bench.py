@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the device-copy bandwidth measurement (counter runs use their own calibration copy)")
     ap.add_argument("--no-served", action="store_true", help="skip the served-batch section")
+    ap.add_argument("--no-boundary-box", action="store_true",
+                    help="skip the all-fluid 256^3 box (no-boundary calibration)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-steps", type=int, default=5000)
     ap.add_argument("--served-budget-mib", type=int, default=1024)
@@ -288,6 +290,43 @@ def served_section(a, log):
     }
 
 
+def no_boundary_section(a, log):
+    """All-fluid periodic 256^3 D3Q19 box, FP32, compact layout, with the packing's
+    tau and force and no links: the step kernel without boundary work, every
+    segment's slots starting on a 128 B line (the no-boundary calibration)."""
+    import torch
+    from paper_2009_04604_amd import binding as B
+    n = 256
+    g = B.Geometry("D3Q19", n, n, n, periodic=(True, True, True))
+    mask, links = g.build()
+    g.close()
+    d = B.Domain("D3Q19", n, n, n, mask, 0.9, storage="f32", force=(1e-6, 0.0, 0.0), layout="compact")
+    d.set_boundary_links(links)
+    nfl = d.info()["n_fluid"]
+    stream = torch.cuda.current_stream()
+    log("no-boundary box: timed steps")
+    d.step(a.warmup)
+    d.macros(fields=False)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    d.step(a.steps)
+    ev1.record(stream)
+    _, _, _, unstable = d.macros(fields=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / a.steps
+    d.close()
+    achieved = 152 * nfl / (kernel_ms * 1e-3) / 1e9
+    return {"workload": "all-fluid periodic 256^3 D3Q19 box, FP32, compact layout, tau 0.9, Guo force (1e-6, 0, 0), "
+                        "no links", "fluid_nodes": nfl, "cut_links": int(len(links["q"])), "steps": a.steps,
+            "ms_per_step": round(wall * 1e3 / a.steps, 4), "kernel_ms": round(kernel_ms, 4),
+            "mlups": round(nfl * a.steps / wall / 1e6, 1), "achieved_GBps": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "unstable": bool(unstable)}
+
+
 def moving_section(a, log):
     """Batched D3Q19 BF16 periodic boxes, each with a sphere in prescribed
     motion, links rebuilt on the device every step."""
@@ -404,6 +443,8 @@ def main():
     }
     d.close()
 
+    if not a.no_boundary_box:
+        out["no_boundary_box"] = no_boundary_section(a, log)
     if not a.no_moving:
         out["moving_batch"] = moving_section(a, log)
     if not a.no_served:

@@ -5,7 +5,6 @@ minus the change of the fluid's momentum, from the library's own FP64 sums)."""
 import numpy as np
 import pytest
 
-import synth
 from tests.gpu_cases import Case, channel_case
 
 pytestmark = pytest.mark.gpu

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import analytic, geometry as G, lattice as OL, metrics, solver
+from oracle import analytic, metrics
 from tests.gpu_cases import Case, annulus_case, channel_case, fluid_velocity_error
 
 pytestmark = pytest.mark.gpu

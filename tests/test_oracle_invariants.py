@@ -16,7 +16,6 @@ import numpy as np
 import pytest
 
 from oracle import boundary, geometry as G, lattice, solver
-from tests import cases
 
 
 def _sphere_box(lat, variant, V=(0.0, 0.0, 0.0), rho=1.0, U=(0.0, 0.0, 0.0), tau=0.7, n=(14, 12, 10),

@@ -108,8 +108,9 @@ size_t lbm_arena_bytes(const lbm_domain_desc* d, const uint8_t* fluid_mask);
  * fluid node, 0 = solid.  All fluid nodes start at f^eq(rho0, u0) (eq.
  * Eq2ndOrder).  Faces on non-periodic axes are walls or the outlet; every
  * population they leave missing must be covered by lbm_set_boundary_links
- * before the first step.  Errors: LBM_EINVAL (sizes, tau <= 0.5, enum values,
- * outlet face on a periodic axis), LBM_ENOMEM, LBM_EDEVICE. */
+ * before the first step.  Errors: LBM_EINVAL (sizes, among them 2^31 or more
+ * stored nodes per population array, tau <= 0.5, enum values, outlet face on a
+ * periodic axis; all checked before any device call), LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_init_domain(const lbm_domain_desc* d, const uint8_t* fluid_mask, lbm_domain* out);
 
 /* Install the cut-link list (replaces any previous list) -- Sec. II.B-E.

@@ -339,6 +339,12 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (d.collision != LBM_BGK && d.collision != LBM_TRT) return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
   if (d.collision == LBM_TRT && !(d.magic > 0.0 && std::isfinite(d.magic)))
     return fail(LBM_EINVAL, "TRT magic parameter must be finite and > 0");
+  // the kernels index populations and segments with 32-bit integers; checked
+  // before any device call
+  const int64_t npad = population_stride(desc, fluid_mask);
+  const int64_t nseg = (int64_t)((d.nx + SEG - 1) / SEG) * d.ny * d.nz;
+  if (npad >= ((int64_t)1 << 31) || nseg >= ((int64_t)1 << 31) / WAVES_PER_BLOCK)
+    return fail(LBM_EINVAL, "lattice too large: more than 2^31 stored nodes");
   const size_t need = lbm_arena_bytes(desc, fluid_mask);
   if (d.arena && d.arena_bytes < need) return fail(LBM_EINVAL, "arena too small: need " + std::to_string(need) + " bytes");
   if (d.arena && ((uintptr_t)d.arena & 255)) return fail(LBM_EINVAL, "arena must be 256-byte aligned");
@@ -373,11 +379,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   g.compact = d.layout == LBM_LAYOUT_COMPACT;
   g.outlet = d.outlet_face;
   g.xcd_remap = g.compact ? 1 : 0;
-  g.npad = population_stride(desc, fluid_mask);
-  if (g.npad >= ((int64_t)1 << 31) || g.nseg >= ((int64_t)1 << 31) / WAVES_PER_BLOCK) {
-    delete dm;
-    return fail(LBM_EINVAL, "lattice too large: more than 2^31 stored nodes");
-  }
+  g.npad = npad;
   dm->N = N;
   dm->elem = storage_bytes(d.storage);
   dm->stream = static_cast<hipStream_t>(d.stream);

@@ -43,6 +43,18 @@ def test_init_rejects_invalid_descriptor(B, field, value):
     assert B.lib().lbm_last_error().decode()
 
 
+def test_init_rejects_a_lattice_beyond_32_bit_indexing(B):
+    """2048 x 1024 x 1024 stored nodes (dense layout) exceed the kernels' 32-bit
+    population index; refused before any device call (the mask is never read)."""
+    d = B.make_desc("D3Q19", 2048, 1024, 1024, 0.8, periodic=(True, True, True), layout="dense")
+    m = np.zeros(2048 * 1024 * 1024, np.uint8)       # untouched pages: no memory is used
+    h = ctypes.c_void_p()
+    code = B.lib().lbm_init_domain(ctypes.byref(d), m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert code == B.LBM_EINVAL
+    assert "too large" in B.lib().lbm_last_error().decode()
+    assert not h.value
+
+
 def _compare(mask, links, fluid, ol):
     assert np.array_equal(mask.astype(bool), fluid.reshape(-1))
     assert np.array_equal(links["node"], ol["node"])

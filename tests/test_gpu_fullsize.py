@@ -57,15 +57,22 @@ def test_cylinder_channel_2048x1024_f32_one_step(gpu_lib):
     _check_one_step(f0, f1, out, nodes, 1e-6)
 
 
-@pytest.mark.parametrize("lattice,collision", [("D3Q19", "BGK"), ("D3Q27", "TRT")])
-def test_sphere_packing_256_f32_one_step(gpu_lib, lattice, collision):
-    """The benchmark's packing (`bench.py`, and with `--lattice D3Q27 --collision TRT`)."""
+@pytest.mark.parametrize("lattice,collision,storage", [("D3Q19", "BGK", "f32"), ("D3Q27", "TRT", "f32"),
+                                                       ("D3Q19", "BGK", "bf16s"), ("D3Q19", "BGK", "f16s")])
+def test_sphere_packing_256_one_step(gpu_lib, lattice, collision, storage):
+    """The benchmark's packing (`bench.py`, with `--lattice D3Q27 --collision TRT`,
+    and with `--storage bf16s / f16s`).  FP32: within 1e-6.  16-bit: the stored
+    post-collision value h* = f* - w is rounded to nearest even (BF16 8, FP16 11
+    significant bits), so |df| <= 2^-8 |h*| (BF16) or 2^-11 |h*| (FP16) plus FP32
+    error (the cut links' values stay FP32).  The small body force keeps |h*| near
+    1e-5, where FP16 is subnormal (half a step 2^-25 = 3e-8): tested with 1e-9
+    (BF16, FP32's exponent range) and 4e-8 (FP16) added."""
     from paper_2009_04604_amd import workloads as W
     n = 256
     magic = 3.0 / 16.0 if collision == "TRT" else None
     c, r = synth.sphere_packing(n=n)
-    _say("case packing 256^3 f32", lattice, collision)
-    d, mask, links = W.packing_domain(n, "f32", spheres=(c, r), lattice=lattice, collision=collision)
+    _say("case packing 256^3", storage, lattice, collision)
+    d, mask, links = W.packing_domain(n, storage, spheres=(c, r), lattice=lattice, collision=collision)
     d.step(20)
     f0 = d.get_state()
     d.step(1)
@@ -83,7 +90,15 @@ def test_sphere_packing_256_f32_one_step(gpu_lib, lattice, collision):
         nodes = _sample(mask, links, rng, 10000, lambda bn: (z(bn) == 0) | (z(bn) == n - 1))
     sub = G.cut_links(dom, fluid, sh, nodes=nodes)
     out = solver.step_at(dom, f0, fluid, sub, nodes, 0.9, force=(1e-6, 0.0, 0.0), magic=magic)
-    _check_one_step(f0, f1, out, nodes, 1e-6)
+    if storage == "f32":
+        _check_one_step(f0, f1, out, nodes, 1e-6)
+        return
+    eps, floor = (2.0 ** -8, 1e-9) if storage == "bf16s" else (2.0 ** -11, 4e-8)
+    h = out - OL.get(lattice).w[:, None]
+    err = np.abs(f1[:, nodes] - out)
+    _say("max |df|", err.max(), "max |df| / bound", (err / (eps * np.abs(h) + floor)).max(), "nodes", nodes.size)
+    assert np.isfinite(out).all()
+    assert (err <= eps * np.abs(h) + floor).all()
 
 
 def test_moving_boxes_32_bf16_batched_one_step(gpu_lib):

@@ -195,6 +195,7 @@ MovingParams moving_params(const lbm_domain_s* d, int cur) {
   mp.seg_prev = d->seg_prev;
   mp.seg_bnd = d->seg_bnd;
   mp.reg_count = d->reg_count;
+  mp.reg_cut = d->reg_cut;
   mp.seg_lbase = d->seg_lbase;
   mp.lld = d->lld;
   mp.lq = d->lq;
@@ -705,6 +706,7 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   if (int e = dalloc(d->reg_seg, reg.size() * 4)) return e;
   if (int e = dalloc(d->seg_prev, g.nseg * 8)) return e;
   if (int e = dalloc(d->reg_count, reg.size() * 4)) return e;
+  if (int e = dalloc(d->reg_cut, reg.size() * SEG * 4)) return e;
   if (int e = dalloc(d->lld, d->link_cap * 2)) return e;
   if (int e = dalloc(d->lq, d->link_cap * rs)) return e;
   if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
@@ -936,6 +938,7 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->reg_seg);
   dfree(d->seg_prev);
   dfree(d->reg_count);
+  dfree(d->reg_cut);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

@@ -190,6 +190,7 @@ struct MovingParams {
   uint64_t* seg_prev;            // fluid mask at t-1 (written by classify)
   uint64_t* seg_bnd;
   int32_t* reg_count;            // cut links per region segment
+  uint32_t* reg_cut;             // [nreg][64] cut directions of each region node (classify -> fill)
   int32_t* seg_lbase;            // link starts: written around the region segments
   uint16_t* lld;
   void* lq;
@@ -305,6 +306,7 @@ struct lbm_domain_s {
   int64_t nreg;
   uint64_t* seg_prev;
   int32_t* reg_count;
+  uint32_t* reg_cut;
   int64_t link_cap;
   // momentum-exchange force (static link list)
   std::vector<int64_t> link_order;   // position in the caller's list of each stored link

@@ -119,6 +119,7 @@ __device__ __forceinline__ void classify_body(const MovingParams& p, int64_t wav
   const bool fluid = in && !solid_at(p, s.x, s.y, s.z);
   const uint64_t fm = __ballot(fluid);
   const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
+  p.reg_cut[wave * 64 + s.lane] = cm;   // read back by fill in the same rebuild
   const int cnt = __popc(cm);
   const uint64_t bm = __ballot(cnt > 0);
   int tot = cnt;
@@ -179,8 +180,7 @@ template <class L, typename R>
 __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
   if (p.reg_count[wave] == 0) return;   // wave-uniform: no cut link in this segment
   const Site s = region_site(p, wave);
-  const bool fluid = (p.seg_fluid[s.seg] >> s.lane) & 1ull;
-  const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
+  const uint32_t cm = p.reg_cut[wave * 64 + s.lane];   // classify's cut directions (0 off the fluid)
   // exclusive prefix of the lanes' link counts
   const int cnt = __popc(cm);
   int inc = cnt;
@@ -314,6 +314,7 @@ __device__ __forceinline__ MovingParams table_entry(const MovingParams* e) {
   p.seg_prev = load_const(&e->seg_prev);
   p.seg_bnd = load_const(&e->seg_bnd);
   p.reg_count = load_const(&e->reg_count);
+  p.reg_cut = load_const(&e->reg_cut);
   p.seg_lbase = load_const(&e->seg_lbase);
   p.lld = load_const(&e->lld);
   p.lq = load_const(&e->lq);

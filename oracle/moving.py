@@ -13,8 +13,11 @@ One step t -> t+1 (readings, listed in the design notes):
    f^eq(rho_bar, V(t) + Omega x (x - x_c(t))) before the step;
 3. the ordinary step with that geometry.
 
-Status: parity unpinned beyond the co-moving invariant (a sphere moving at the
-velocity of a uniform flow leaves it unchanged, refills included).
+Status: pinned -- V(t) against central differences of x_c(t) over a period and
+its closed values at t = 0 and T/4; the refill rule against hand-listed
+neighbour sets (tests/test_oracle_refill.py); the co-moving invariant (a sphere
+moving at the velocity of a uniform flow leaves it unchanged, refills
+included).
 """
 import numpy as np
 

@@ -29,9 +29,10 @@ and momentum, momentum growth by F per node and step under Guo forcing), the
 textbook half-way bounce-back reduction, and closed-form flows (circular
 Couette, impulsively started Couette, force-driven Poiseuille); the open links
 of a pressure face (q = 0, boundary.open_link_value) against the developed
-Poiseuille channel and its pressure gradient; the zero-gradient outlet only as
-far as its mass growth under a velocity inlet, and the refill, are "parity
-unpinned" beyond self-consistency checks.
+Poiseuille channel and its pressure gradient; the refill against hand-listed
+neighbour sets on tiny grids (tests/test_oracle_refill.py: fluid at both times,
+fresh and newly solid neighbours excluded, rho0 when none is left, faces); the
+zero-gradient outlet only as far as its mass growth under a velocity inlet.
 """
 import numpy as np
 

@@ -46,8 +46,6 @@ def parse():
                     help="collision model (TRT with the magic parameter 3/16)")
     ap.add_argument("--wall-neq", default="bounceback", choices=["bounceback", "regularized"],
                     help="wall non-equilibrium estimator of the ELIBB links")
-    ap.add_argument("--outlet", default="zero-gradient", choices=["zero-gradient", "pressure"],
-                    help="outlet of the channel workload (pressure: open links at fixed density)")
     ap.add_argument("--xcd-remap", type=int, choices=[0, 1], default=None,
                     help="launch option: XCD deal of the step kernel's workgroups: 0 round-robin, 1 contiguous "
                          "eighths; default: the library's")
@@ -92,8 +90,7 @@ def traffic_from_profile(workload, storage):
         return None
 
 
-def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK", wall_neq="bounceback",
-                   outlet="zero-gradient"):
+def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK", wall_neq="bounceback"):
     import synth
     from paper_2009_04604_amd import workloads as W
     if name == "packing256":
@@ -105,9 +102,9 @@ def build_workload(name, storage, layout, lattice="D3Q19", collision="BGK", wall
                "collision": collision if collision == "BGK" else "TRT (Lambda 3/16)"}
     else:
         p = synth.cylinder_channel()
-        d, mask, links = W.channel_domain(p, storage, layout=layout, wall_neq=wall_neq, outlet=outlet)
+        d, mask, links = W.channel_domain(p, storage, layout=layout, wall_neq=wall_neq)
         cfg = {"workload": "cylinder_channel_2048x1024_D2Q9", "lattice": "D2Q9", "n": [p["nx"], p["ny"], 1],
-               "reynolds": 100, "tau": p["tau"], "variant": "ELIBB-FQ", "storage": storage, "outlet": outlet}
+               "reynolds": 100, "tau": p["tau"], "variant": "ELIBB-FQ", "storage": storage, "outlet": "zero-gradient"}
     cfg["layout"] = layout
     cfg["wall_neq"] = wall_neq
     return d, cfg
@@ -395,7 +392,7 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     log(f"main: building {a.workload} ({a.storage}, {a.layout})")
-    d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision, a.wall_neq, a.outlet)
+    d, cfg = build_workload(a.workload, a.storage, a.layout, a.lattice, a.collision, a.wall_neq)
     if a.xcd_remap is not None:
         d.set_launch_option(0, a.xcd_remap)
         cfg["xcd_remap"] = a.xcd_remap

@@ -118,31 +118,18 @@ int lbm_init_domain(const lbm_domain_desc* d, const uint8_t* fluid_mask, lbm_dom
  * boundary node `node` after streaming, because node - c_dir is solid or lies
  * beyond a non-periodic face.  Its f_dir(x_F, t+1) is rebuilt by eq.
  * ELIBB-general from the node's own time-t data:
- *   q      (0, 1]: |x_W - x_F| / |c_dir|, x_W the first wall crossing; or 0 for an
- *          open link at the outlet density (see lbm_set_outlet_density)
+ *   q      (0, 1]: |x_W - x_F| / |c_dir|, x_W the first wall crossing
  *   uw_t   [3*n] wall velocity at x_W at time t (NULL: wall at rest)
  *   uw_t1  [3*n] wall velocity at x_W at time t+1 (NULL: equal to uw_t)
  * Velocity triples are (x, y, z) per link; z ignored for D2Q9.
  * Validation (LBM_EINVAL, message names the first offending link): node is a
  * fluid node; 1 <= dir < Q; node - c_dir is not a fluid node; the pair is not
- * covered by the outlet; 0 < q <= 1, or q = 0 once lbm_set_outlet_density was
- * called; no duplicate (node, dir); every missing population of every fluid node
- * is covered by a link or by the outlet;
- * variant in range; q_cutoff >= 0 (the paper uses 0.01).  Host arrays are
- * copied. */
+ * covered by the outlet; 0 < q <= 1; no duplicate (node, dir); every missing
+ * population of every fluid node is covered by a link or by the outlet; variant
+ * in range; q_cutoff >= 0 (the paper uses 0.01).  Host arrays are copied. */
 int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir,
                            const double* q, const double* uw_t, const double* uw_t1,
                            int32_t variant, double q_cutoff);
-
-/* Density of the domain's open links (q = 0, see lbm_geometry_add_pressure_face):
- * each missing population i of an open link is rebuilt by the anti-bounce-back
- * rule of a pressure boundary half-way beyond the node,
- *   f_i(x_F, t+1) = -f*_ibar(x_F, t) + 2 w_i rho_out [1 + 9/2 (c_i.u)^2 - 3/2 u.u],
- * u the node's velocity at t.  Not in the paper (which treats walls only): a
- * fixed-density outlet that keeps the mass bounded, where the zero-gradient outlet
- * lets it grow.  Must be set before links with q = 0 are installed; takes effect
- * from the next step.  LBM_EINVAL unless rho_out is finite and > 0. */
-int lbm_set_outlet_density(lbm_domain d, double rho_out);
 
 /* Selects the wall non-equilibrium estimator of every cut link of the domain
  * (eq. ELIBB-approximations).  LBM_NEQ_BOUNCEBACK: f_i^neq(x_W) is taken as the
@@ -177,18 +164,32 @@ int lbm_set_wall_neq(lbm_domain d, int32_t mode);
 int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
                           const double direction[3], const double omega[3], int32_t variant, double q_cutoff);
 
-/* Advance n_steps >= 0 time steps (collide, stream, rebuild every cut link);
- * asynchronous on the domain's stream.  LBM_ESTATE if links are missing. */
+/* Advance n_steps >= 0 time steps; asynchronous on the domain's stream.  Each
+ * step is the lattice Boltzmann equation of Sec. II.A (eq. LBE) split into the
+ * local collision -- BGK (eq. LB-BGK) with the second-order equilibrium (eq.
+ * Eq2ndOrder), or TRT (eq. magic-parameter), plus Guo's force term when a body
+ * force is set -- and the exact pull streaming f_i(x, t+1) = f*_i(x - c_i, t);
+ * then every cut link is rebuilt from its boundary node's own time-t data by the
+ * enhanced single-node bounce-back of Sec. II.C-E (eq. ELIBB-general with the
+ * variant's weights of eq. poli_coeff and the moving-wall term of eq.
+ * ME-solid-to-fluid).  With a moving sphere the geometry of the next step is
+ * rebuilt after each step.  LBM_EINVAL for n_steps < 0, LBM_ESTATE if links are
+ * missing, LBM_EDEVICE if a launch fails. */
 int lbm_step(lbm_domain d, int32_t n_steps);
 
-/* Moments of the current pre-collision state (time t): rho [N], u [N*D] (node-
- * major: u[n*D + a]) -- solid nodes get 0 -- and sums = {mass, mom_x, mom_y,
- * (mom_z), residual} summed over fluid nodes in FP64 in a fixed order (same
- * result every call for the same state).  u includes Guo's F/2 shift.  The
- * residual is ||u - u_prev|| / ||u|| where u_prev is the field at the previous
- * lbm_macros call (the initial field for the first call).  Any pointer may be
- * NULL.  Synchronises the stream.  Returns LBM_EUNSTABLE if a NaN/Inf was found
- * (outputs are still written). */
+/* Moments of the current pre-collision state (time t), Sec. II.A: rho = sum_i
+ * f_i and rho u = sum_i c_i f_i (+ F/2 with Guo forcing), as rho [N] and u [N*D]
+ * (node-major: u[n*D + a]) -- solid nodes get 0 -- and sums = {mass, mom_x,
+ * mom_y, (mom_z), residual} summed over fluid nodes in FP64 in a fixed order
+ * (same result every call for the same state).  The mass is the quantity whose
+ * drift Sec. III.B measures (mean density fluctuation); the residual is the
+ * relative L2 change of the velocity field in the form of eq. rRMSE,
+ * ||u - u_prev|| / ||u|| over fluid nodes, with u_prev the field of the
+ * previous lbm_macros call (the initial field for the first call): called
+ * every k steps it is the residual at lag k.  Any pointer may be NULL (all
+ * host, caller-owned).  Synchronises the stream.  Returns LBM_EUNSTABLE if a
+ * NaN/Inf was found in rho or u (outputs are still written), LBM_ENOMEM /
+ * LBM_EDEVICE on allocation or device errors. */
 int lbm_macros(lbm_domain d, double* rho, double* u, double* sums);
 
 /* Export / import the pre-collision populations f_i(x, t) as [Q][N] float64
@@ -215,8 +216,18 @@ int lbm_set_link_groups(lbm_domain d, const int32_t* group, int32_t n_groups);
  * f*_ibar the post-collision population leaving x_F towards the wall and f_i the
  * rebuilt one.  force: n_groups x 3 doubles (z = 0 for D2Q9), caller-owned.
  * Synchronises the stream.  LBM_ESTATE for a moving-sphere domain, without
- * links, or before the first step after the links were installed. */
+ * links, or before the first step after the links or the state were installed. */
 int lbm_momentum_exchange(lbm_domain d, double* force);
+
+/* Force and torque on each group of walls during the last step: the forces of
+ * lbm_momentum_exchange, and the torque T = sum over the group's links of
+ * r x F_link, r = x_W - centre[group] taken as the minimum image on periodic
+ * axes, x_W = x_F - q c_i the link's wall point (the paper's force section names
+ * the torque without fixing its lever arm; the wall point is where the link's
+ * momentum exchange acts).  centres: n_groups x 3 doubles (NULL: the origin);
+ * force, torque: n_groups x 3 doubles, caller-owned (torque is along z for
+ * D2Q9).  Same errors as lbm_momentum_exchange. */
+int lbm_force_torque(lbm_domain d, const double* centres, double* force, double* torque);
 
 /* Change the stream used by later calls. */
 int lbm_set_stream(lbm_domain d, void* stream);
@@ -325,12 +336,6 @@ int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, c
 int lbm_geometry_add_face_wall(lbm_geometry g, int32_t face, double q_face, const double uw[3],
                                int32_t profile);
 
-/* An open face at fixed density on a non-periodic axis (not the zero-gradient
- * outlet face): every population of the first node layer whose pull source lies
- * beyond the face becomes a link with q = 0 and zero wall velocity, rebuilt at the
- * domain's outlet density (lbm_set_outlet_density).  LBM_EINVAL for a periodic
- * axis or the zero-gradient outlet's face. */
-int lbm_geometry_add_pressure_face(lbm_geometry g, int32_t face);
 /* Classify nodes and find every cut link.  Outputs counts. */
 int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links);
 /* Copy the results of lbm_geometry_build: mask [N]; node, dir, q [n_links];

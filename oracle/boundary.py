@@ -263,25 +263,6 @@ def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq="bounc
     return np.stack([P0, P1, P2, P3])
 
 
-def open_link_value(lat, i, rho_out, u_F, fstar_F):
-    """Missing population i at an open face of fixed density (links marked q = 0):
-    the anti-bounce-back rule of Ginzburg's pressure condition with the boundary
-    half-way beyond the node,
-        f_i(x_F, t+1) = -f*_ibar(x_F, t) + 2 w_i rho_out [1 + (c_i.u)^2 / (2 cs2^2) - u.u / (2 cs2)],
-    the boundary velocity taken as the node's velocity u_F(t) (a reading).  Not in
-    the paper, which treats walls only.
-
-    i: (n,) directions; rho_out: scalar; u_F: (3, n); fstar_F: (Q, n).  Returns (n,)."""
-    ib = lat.opp[i]
-    n = np.arange(i.size)
-    c = lat.c[i].T.astype(np.float64)
-    cu = (c * u_F).sum(axis=0)
-    uu = (u_F * u_F).sum(axis=0)
-    cs2 = lat.cs2
-    even = lat.w[i] * rho_out * (1.0 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2))
-    return -fstar_F[ib, n] + 2.0 * even
-
-
 def reconstruct(coef, P):
     """f_i(x_F, t+1) = sum_k a_k P_k  (eq. interpolated_bb_equation)."""
     return (coef.T * P).sum(axis=0)

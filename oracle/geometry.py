@@ -16,7 +16,6 @@ Shapes:
 * ``FaceWall``  a plane parallel to a non-periodic domain face at distance q_f
                 from the first node layer, with a wall velocity given as a
                 function of x_W (constant, or the parabolic inlet profile).
-* ``PressureFace`` an open face at fixed density (links marked q = 0).
 The zero-gradient outlet (a reading; the paper has no open boundaries): on the
 outlet face, a population whose pull source lies beyond the face is copied from
 the post-collision value of the face-layer node one step back along the face
@@ -145,18 +144,6 @@ class FaceWall:
         if callable(self._vel):
             return np.asarray(self._vel(xw), dtype=np.float64)
         return np.repeat(np.asarray(self._vel, dtype=np.float64).reshape(3, 1), xw.shape[1], axis=1)
-
-
-class PressureFace(FaceWall):
-    """An open face at fixed density (the boundary half-way beyond the last node
-    layer): its missing populations are not walls but open links, marked q = 0 in
-    the link list, rebuilt by the anti-bounce-back rule (boundary.open_link_value)
-    at the domain's outlet density.  Not in the paper (which treats walls only): a
-    mass-stable alternative to the zero-gradient outlet."""
-    is_open = True
-
-    def __init__(self, face):
-        super().__init__(face, 0.5, None)
 
 
 class TiltedBand:
@@ -345,9 +332,6 @@ def cut_links(dom, fluid, spheres=(), faces=(), uw_t1_fn=None, nodes=None):
             if sel.any():
                 uw[:, sel] = shp.velocity(dom, xw[:, sel])
                 uw1[:, sel] = uw[:, sel] if uw_t1_fn is None else uw_t1_fn(shp, xw[:, sel])
-        for k, shp in enumerate(shapes):
-            if getattr(shp, "is_open", False):
-                best = np.where(owner == k, 0.0, best)        # open link marker
         out["node"].append(nodes[need])
         out["dir"].append(np.full(need.sum(), i))
         out["q"].append(best)

@@ -13,8 +13,7 @@ nodes, so that a read of solid data poisons the result).  One step t -> t+1
    (see collide);
 3. streaming: f_i(x, t+1) = f*_i(x - c_i, t) for every pair that is not a cut
    link, wrapping on periodic axes (eq. LBE);
-4. zero-gradient outlet (a reading: open boundaries are outside the paper); open
-   faces at fixed density are links instead (step 5);
+4. zero-gradient outlet (a reading: open boundaries are outside the paper);
 5. every cut link is rebuilt by the ELIBB (eq. ELIBB-general) from node F's own
    time-t data (see oracle.boundary).
 
@@ -27,9 +26,7 @@ valid populations (rho0 if there are none).
 Status: pinned -- exact invariants (rest, co-moving uniform flow, periodic mass
 and momentum, momentum growth by F per node and step under Guo forcing), the
 textbook half-way bounce-back reduction, and closed-form flows (circular
-Couette, impulsively started Couette, force-driven Poiseuille); the open links
-of a pressure face (q = 0, boundary.open_link_value) against the developed
-Poiseuille channel and its pressure gradient; the refill against hand-listed
+Couette, impulsively started Couette, force-driven Poiseuille); the refill against hand-listed
 neighbour sets on tiny grids (tests/test_oracle_refill.py: fluid at both times,
 fresh and newly solid neighbours excluded, rho0 when none is left, faces); the
 zero-gradient outlet only as far as its mass growth under a velocity inlet.
@@ -107,12 +104,11 @@ def collide(lat, f, tau, force, magic=None):
 class Simulation:
     """A lattice with a fixed (or externally updated) geometry and link list."""
 
-    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None, rho_out=None):
+    def __init__(self, dom, tau, force=(0.0, 0.0, 0.0), rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None):
         self.dom = dom
         self.lat = dom.lat
         self.tau = float(tau)
         self.magic = None if magic is None else float(magic)   # TRT magic parameter, None = BGK
-        self.rho_out = None if rho_out is None else float(rho_out)   # density of open (q = 0) links
         self.force = np.asarray(force, dtype=np.float64).reshape(3)
         self.rho0 = float(rho0)
         self.u0 = np.asarray(u0, dtype=np.float64).reshape(3)
@@ -135,11 +131,7 @@ class Simulation:
         self.variant, self.q_cut, self.wall_neq = variant, float(q_cut), wall_neq
         L = {k: np.asarray(v) for k, v in links.items()}
         self.links = L
-        # open links (q = 0, boundary.open_link_value) have no interpolation weights
-        self.open = L["q"] == 0.0 if L["node"].size else np.zeros(0, bool)
-        if self.open.any() and self.rho_out is None:
-            raise ValueError("open (q = 0) links need the outlet density rho_out")
-        self.coef = boundary.coefficients(variant, np.where(self.open, 1.0, L["q"]), q_cut)
+        self.coef = boundary.coefficients(variant, L["q"], q_cut)
         cut = np.zeros((lat.q, dom.N), dtype=bool)
         if L["node"].size:
             if not fl[L["node"]].all():
@@ -210,9 +202,6 @@ class Simulation:
             P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"],
                                      self.wall_neq)
             fnew[d, n] = boundary.reconstruct(self.coef, P)
-            if self.open.any():
-                o = self.open
-                fnew[d[o], n[o]] = boundary.open_link_value(lat, d[o], self.rho_out, u[:, n[o]], fstar[:, n[o]])
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
             self.last_force = boundary.momentum_exchange(lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp,
                                                          self.n_groups)
@@ -269,7 +258,7 @@ class Simulation:
 
 
 def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ", q_cut=0.01, magic=None,
-            wall_neq="bounceback", rho_out=None):
+            wall_neq="bounceback"):
     """f(x, t+1) at the given fluid nodes only, from the full state f (Q, N) at t.
 
     The same step as Simulation.step, evaluated node by node: every pulled
@@ -313,12 +302,8 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
         if is_cut.any():
             sel = np.flatnonzero(is_cut)
             li = order[k[sel]]
-            op = L["q"][li] == 0.0
-            coef = boundary.coefficients(variant, np.where(op, 1.0, L["q"][li]), q_cut)
+            coef = boundary.coefficients(variant, L["q"][li], q_cut)
             P = boundary.link_points(lat, np.full(sel.size, i), rho_s[sel], feq_s[:, sel], f[:, nodes[sel]],
                                      fs_self[:, sel], L["uw_t"][:, li], L["uw_t1"][:, li], wall_neq)
             out[i, sel] = boundary.reconstruct(coef, P)
-            if op.any():
-                out[i, sel[op]] = boundary.open_link_value(lat, np.full(op.sum(), i), rho_out, u_s[:, sel[op]],
-                                                           fs_self[:, sel[op]])
     return out

@@ -35,7 +35,7 @@ EXPORTED = [
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
-    "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_set_outlet_density", "lbm_geometry_add_pressure_face",
+    "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -118,8 +118,7 @@ def lib():
         "lbm_geometry_get_shapes": (I32, [P, P]),
         "lbm_set_wall_neq": (I32, [P, I32]),
         "lbm_geometry_add_cylinder": (I32, [P, P, DBL, I32, P, P]),
-        "lbm_set_outlet_density": (I32, [P, DBL]),
-        "lbm_geometry_add_pressure_face": (I32, [P, I32]),
+        "lbm_force_torque": (I32, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -312,10 +311,6 @@ class Domain:
         _check(lib().lbm_set_link_groups(self.h, _ptr(g), int(n_groups)))
         self._n_groups = int(n_groups)
 
-    def set_outlet_density(self, rho_out):
-        """Density of the open links (q = 0) of a pressure face."""
-        _check(lib().lbm_set_outlet_density(self.h, float(rho_out)))
-
     def set_wall_neq(self, mode):
         """Wall non-equilibrium estimator: "bounceback" (eq. neqbb-s) or
         "regularized" (eq. fi_neq)."""
@@ -327,6 +322,15 @@ class Domain:
         out = np.zeros((getattr(self, "_n_groups", 1), 3))
         _check(lib().lbm_momentum_exchange(self.h, _ptr(out)))
         return out
+
+    def force_torque(self, centres=None):
+        """(force, torque), each (n_groups, 3), of the last step; torque about
+        centres (n_groups, 3) (None: the origin)."""
+        n = getattr(self, "_n_groups", 1)
+        c = None if centres is None else np.ascontiguousarray(centres, dtype=np.float64).reshape(n, 3)
+        f, t = np.zeros((n, 3)), np.zeros((n, 3))
+        _check(lib().lbm_force_torque(self.h, _ptr(c), _ptr(f), _ptr(t)))
+        return f, t
 
     def set_launch_option(self, option, value):
         lbm_set_launch_option(self.h, option, value)
@@ -451,11 +455,6 @@ class Geometry:
         c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
         r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
         _check(lib().lbm_geometry_add_spheres(self.h, r.size, _ptr(c), _ptr(r)))
-
-    def add_pressure_face(self, face):
-        """Open face at fixed density: its links are marked q = 0."""
-        f = FACES[face] if isinstance(face, str) else int(face)
-        _check(lib().lbm_geometry_add_pressure_face(self.h, f))
 
     def add_face_wall(self, face, q_face=0.5, uw=None, profile=0):
         f = FACES[face] if isinstance(face, str) else int(face)

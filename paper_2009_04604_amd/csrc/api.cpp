@@ -158,8 +158,6 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.q_cut = d->q_cut;
   p.outlet_face = d->desc.outlet_face;
   p.wall_neq = d->wall_neq;
-  p.rho_out = d->rho_out;
-  p.open_links = d->rho_out > 0.0;
   return p;
 }
 
@@ -234,6 +232,7 @@ hipError_t import_state(lbm_domain_s* d, const double* dev_f) {
   for (int a = 0; a < 3; ++a) ip.u0[a] = d->desc.u0[a];
   hipError_t e = launch_init(d->desc.lattice, d->desc.storage, ip, d->stream);
   if (e == hipSuccess) e = launch_init_links(d->desc.lattice, d->desc.storage, ip, d->stream);
+  d->state_step = d->steps;
   return e;
 }
 
@@ -296,8 +295,9 @@ extern "C" {
 const char* lbm_last_error(void) { return lbm::g_err.c_str(); }
 
 namespace {
-// Elements per direction array: compact = fluid nodes + 2 guards, rounded up to
-// 64 elements; dense = the padded lattice.
+// Elements per direction array: compact = the guard in front, the fluid nodes
+// and one guard slot behind, rounded up to 64 elements; dense = the padded
+// lattice.
 int64_t population_stride(const lbm_domain_desc* d, const uint8_t* mask) {
   const int64_t NX = d->nx + ((d->periodic & 1) ? 0 : 2);
   const int64_t NY = d->ny + ((d->periodic & 2) ? 0 : 2);
@@ -306,7 +306,7 @@ int64_t population_stride(const lbm_domain_desc* d, const uint8_t* mask) {
   const int64_t N = (int64_t)d->nx * d->ny * d->nz;
   int64_t nf = 0;
   for (int64_t n = 0; n < N; ++n) nf += mask[n] ? 1 : 0;
-  return (nf + 2 + 63) / 64 * 64;
+  return (GUARD + nf + 1 + 63) / 64 * 64;
 }
 }  // namespace
 
@@ -374,6 +374,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   g.NZ = g.nz + 2 * g.pz;
   g.nseg_x = (g.nx + SEG - 1) / SEG;
   g.nseg = (int64_t)g.nseg_x * g.ny * g.nz;
+  g.guard = GUARD;
   g.div_nseg_x = make_fastdiv((uint32_t)g.nseg_x);
   g.div_ny = make_fastdiv((uint32_t)g.ny);
   g.xcd_remap = 0;
@@ -465,11 +466,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   for (int64_t k = 0; k < n_links; ++k) {
     if (node[k] < 0 || node[k] >= N) return fail(LBM_EINVAL, where(k) + ": node out of range");
     if (dir[k] < 1 || dir[k] >= L.Q) return fail(LBM_EINVAL, where(k) + ": dir out of range");
-    if (q[k] == 0.0) {
-      if (!(d->rho_out > 0.0)) return fail(LBM_EINVAL, where(k) + ": an open link (q = 0) needs lbm_set_outlet_density first");
-    } else if (!(q[k] > 0.0 && q[k] <= 1.0)) {
-      return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1], or be 0 for an open link");
-    }
+    if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1]");
     for (int a = 0; a < 3; ++a) {
       if (uw_t && !std::isfinite(uw_t[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t");
       if (uw_t1 && !std::isfinite(uw_t1[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t1");
@@ -525,7 +522,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   for (int64_t k = 0; k < n_links; ++k) {
     const int64_t o = order[k];
     qd[k] = q[o];
-    if (moving && q[o] != 0.0) {   // open links have no wall term
+    if (moving) {
       const int i = dir[o];
       const double* u0 = uw_t ? uw_t + 3 * o : nullptr;
       const double* u1 = uw_t1 ? uw_t1 + 3 * o : u0;
@@ -625,17 +622,6 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   d->q_cut = q_cutoff;
   d->links_ok = true;
   d->uid = next_uid();
-  clear_error();
-  return LBM_OK;
-}
-
-int lbm_set_outlet_density(lbm_domain d, double rho_out) {
-  if (!d) return fail(LBM_EINVAL, "null domain");
-  if (!(rho_out > 0.0) || !std::isfinite(rho_out)) return fail(LBM_EINVAL, "outlet density must be finite and > 0");
-  if (rho_out != d->rho_out) {
-    d->rho_out = rho_out;
-    d->uid = next_uid();   // batches rebuild their tables
-  }
   clear_error();
   return LBM_OK;
 }
@@ -778,6 +764,7 @@ int lbm_macros(lbm_domain d, double* rho, double* u, double* sums) {
   p.u = u ? d->u_tmp : nullptr;
   p.uprev = d->uprev;
   p.partials = d->partials;
+  p.nblocks = d->red_blocks;
   HIP_TRY(launch_macros(d->desc.lattice, d->desc.storage, p, d->red_blocks, d->stream));
   HIP_TRY(launch_reduce(d->partials, d->red_blocks, d->sums, d->stream));
   double h[NPART];
@@ -851,27 +838,60 @@ int lbm_set_link_groups(lbm_domain d, const int32_t* group, int32_t n_groups) {
   return LBM_OK;
 }
 
-int lbm_momentum_exchange(lbm_domain d, double* force) {
-  if (!d || !force) return fail(LBM_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+// Force and torque per link group of the last step (static link lists).
+int force_torque(lbm_domain d, const double* centres, double* force, double* torque) {
   if (d->moving) return fail(LBM_ESTATE, "the force of a moving sphere is not available (its links are rebuilt every step)");
   if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set");
-  if (d->steps == d->links_step) return fail(LBM_ESTATE, "no step taken since the links were installed");
+  if (d->steps == d->links_step || d->steps == d->state_step)
+    return fail(LBM_ESTATE, "no step taken since the links or the state were installed");
+  if (centres)
+    for (int k = 0; k < 3 * d->n_groups; ++k)
+      if (!std::isfinite(centres[k])) return fail(LBM_EINVAL, "non-finite torque reference point");
   if (!d->lforce && d->nl > 0)
-    if (int e = dalloc(d->lforce, (size_t)d->nl * 3 * 8)) return e;
+    if (int e = dalloc(d->lforce, (size_t)d->nl * 6 * 8)) return e;
   if (!d->gforce)
-    if (int e = dalloc(d->gforce, (size_t)d->n_groups * 3 * 8)) return e;
+    if (int e = dalloc(d->gforce, (size_t)d->n_groups * 9 * 8)) return e;
+  double* dcentre = nullptr;
+  if (centres) {
+    dcentre = d->gforce + 6 * d->n_groups;
+    HIP_TRY(hipMemcpyAsync(dcentre, centres, (size_t)d->n_groups * 3 * 8, hipMemcpyHostToDevice, d->stream));
+  }
   ForceParams p{};
   p.g = d->g;
   p.pop = d->buf[d->cur];
   p.lk = link_view(d, d->lv[d->cur], nullptr);
   p.luw = d->luw;
+  p.group = d->lgrp;
+  p.centre = dcentre;
   p.contrib = d->lforce;
   p.nl = d->nl;
-  HIP_TRY(launch_force(d->desc.lattice, d->desc.storage, p, d->n_groups, d->lgrp, d->gforce, d->stream));
-  HIP_TRY(hipMemcpyAsync(force, d->gforce, (size_t)d->n_groups * 3 * 8, hipMemcpyDeviceToHost, d->stream));
+  HIP_TRY(launch_force(d->desc.lattice, d->desc.storage, p, d->n_groups, d->gforce, d->stream));
+  std::vector<double> h((size_t)d->n_groups * 6);
+  HIP_TRY(hipMemcpyAsync(h.data(), d->gforce, h.size() * 8, hipMemcpyDeviceToHost, d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
+  for (int gi = 0; gi < d->n_groups; ++gi)
+    for (int a = 0; a < 3; ++a) {
+      if (force) force[3 * gi + a] = h[6 * gi + a];
+      if (torque) torque[3 * gi + a] = h[6 * gi + 3 + a];
+    }
   clear_error();
   return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_momentum_exchange(lbm_domain d, double* force) {
+  if (!d || !force) return fail(LBM_EINVAL, "null argument");
+  return force_torque(d, nullptr, force, nullptr);
+}
+
+int lbm_force_torque(lbm_domain d, const double* centres, double* force, double* torque) {
+  if (!d || !force || !torque) return fail(LBM_EINVAL, "null argument");
+  return force_torque(d, centres, force, torque);
 }
 
 int lbm_set_stream(lbm_domain d, void* stream) {

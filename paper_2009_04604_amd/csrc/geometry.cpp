@@ -4,8 +4,8 @@
 //
 // Shapes: spheres / disks (solid inside or outside, rigid-body wall velocity),
 // circular cylinders along z (the sphere's formulas in the xy-plane), plane
-// walls parallel to non-periodic faces (constant or parabolic velocity) and open
-// faces at fixed density (links marked q = 0).  Many solid-inside spheres are bucketed on a coarse grid so that a
+// walls parallel to non-periodic faces (constant or parabolic velocity).  Many
+// solid-inside spheres are bucketed on a coarse grid so that a
 // link is only tested against spheres that can reach it; candidates are always
 // evaluated in insertion order, spheres before face walls, and the first
 // strictly smaller crossing wins.
@@ -34,7 +34,6 @@ struct Face {
   double q;
   double uw[3];
   int profile;
-  int open;        // an open face at fixed density: its links are marked q = 0
 };
 
 }  // namespace
@@ -184,19 +183,6 @@ int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, c
   if (!g || (n > 0 && (!centres || !radii))) return gfail(LBM_EINVAL, "null argument");
   for (int64_t k = 0; k < n; ++k)
     if (int e = lbm_geometry_add_sphere(g, centres + 3 * k, radii[k], 1, nullptr, nullptr)) return e;
-  return LBM_OK;
-}
-
-int lbm_geometry_add_pressure_face(lbm_geometry g, int32_t face) {
-  if (!g) return gfail(LBM_EINVAL, "null geometry");
-  if (face < 0 || face > 5 || g->per[face >> 1]) return gfail(LBM_EINVAL, "face must lie on a non-periodic axis");
-  if (g->outlet == face) return gfail(LBM_EINVAL, "the face is the zero-gradient outlet");
-  Face f{};
-  f.face = face;
-  f.q = 0.5;
-  f.open = 1;
-  g->faces.push_back(f);
-  g->built = false;
   return LBM_OK;
 }
 
@@ -382,11 +368,10 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links) {
             for (int a = 0; a < 3; ++a) u[a] = f.uw[a] * scale;
           }
           if (g->D == 2) u[2] = 0.0;
-          const bool open = owner >= (int)g->sph.size() && g->faces[owner - g->sph.size()].open;
           g->node.push_back(n);
           g->dir.push_back((int8_t)i);
           g->shape.push_back(owner);
-          g->q.push_back(open ? 0.0 : best);
+          g->q.push_back(best);
           g->uw.insert(g->uw.end(), u, u + 3);
         }
       }

@@ -8,10 +8,13 @@
 //              node x pulls in direction i lives in slot (x - c_i, i); after a
 //              step slot (x, i) of a fluid node holds its post-collision h*_i.
 //   compact    (static geometry) only fluid nodes are stored, in node order:
-//              the slot of fluid node x is 1 + (number of fluid nodes before
+//              the slot of fluid node x is G + (number of fluid nodes before
 //              x), found from the segment masks and their prefix counts
-//              seg_fbase; element 0 and the tail are guards.  Solid nodes cost
-//              neither memory nor bandwidth.
+//              seg_fbase; the G = 64 slots in front and the tail are guards
+//              (a segment whose fluid count before it is a multiple of 64
+//              then starts on a cache line, as every segment of an all-fluid
+//              row of 64 k nodes does).  Solid nodes cost neither memory nor
+//              bandwidth.
 //   dense      (moving geometry) [NZ][NY][NX] with NX = nx + 2 px etc.: one
 //              halo layer on each non-periodic axis.
 // outlet       a zero-gradient outlet face is a clamp of the pull source onto
@@ -65,6 +68,7 @@ namespace lbm {
 constexpr int SEG = 64;          // lanes per segment (one wavefront)
 constexpr int WAVES_PER_BLOCK = 4;
 constexpr int BLOCK = SEG * WAVES_PER_BLOCK;
+constexpr int GUARD = 64;        // compact layout: slots in front of the first fluid node
 
 // Division by a run-time constant d < 2^31 for dividends n < 2^31:
 // n / d = (umulhi(n, m) + n) >> s  (m, s chosen on the host).
@@ -88,6 +92,7 @@ struct GridGeom {
   int32_t perx, pery, perz;      // periodic flags
   int32_t nseg_x;                // segments per row
   int64_t nseg;                  // total segments (< 2^31)
+  int32_t guard;                 // compact layout: slot of the first fluid node
   FastDiv div_nseg_x, div_ny;    // fast division by nseg_x and ny
   int32_t xcd_remap;             // 1: each XCD walks a contiguous eighth of the rows
   int32_t compact;               // 1: compact (fluid-only) layout
@@ -128,8 +133,6 @@ struct StepParams {
   int32_t outlet_face;
   int32_t wall_neq;              // 0: bounced non-equilibrium (eq. neqbb-s); 1: regularised (eq. fi_neq);
                                  // selects the kernel variant (batches group by it)
-  double rho_out;                // density of open links (q = 0)
-  int32_t open_links;            // the domain may hold open links (its outlet density is set)
 };
 
 struct InitParams {
@@ -155,8 +158,9 @@ struct MacroParams {
   double force[3];
   double* rho;                   // [N] or null
   double* u;                     // [N*D] or null
-  double* uprev;                 // [N*D] previous velocity (updated)
-  double* partials;              // [nblocks][NPART]
+  double* uprev;                 // [N*D] previous velocity (updated), or null: no residual
+  double* partials;              // [gridDim.x][NPART]
+  int64_t nblocks;               // logical blocks of the lattice (grid_blocks)
 };
 constexpr int NPART = 8;         // mass, mom x/y/z, |du|^2, |u|^2, non-finite count, pad
 
@@ -165,7 +169,9 @@ struct ForceParams {
   const void* pop;               // current population buffer
   LinkView lk;                   // lv_in: the link values of the current time
   const double* luw;             // [3 nl] wall velocity per link, or null (walls at rest)
-  double* contrib;               // [3 nl] per-link force
+  const int32_t* group;          // [nl] group of each link, or null (one group)
+  const double* centre;          // [3 n_groups] torque reference points, or null (origin)
+  double* contrib;               // [6 nl] force and torque per link
   int64_t nl;
 };
 
@@ -234,8 +240,8 @@ hipError_t launch_init_links(int lattice, int storage, const InitParams& p, hipS
 hipError_t launch_export(int lattice, int storage, const ExportParams& p, hipStream_t s);
 hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t nblocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
-hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, const int32_t* group,
-                        double* out, hipStream_t s);
+hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, double* out,
+                        hipStream_t s);
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);
 hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
@@ -288,7 +294,6 @@ struct lbm_domain_s {
   int32_t variant;
   double q_cut;
   int32_t wall_neq;              // LBM_NEQ_BOUNCEBACK or LBM_NEQ_REGULARIZED
-  double rho_out;                // density of open links (q = 0); 0 = not set
   void* luv;                     // [6][nl or link_cap] u_w(t), u_w(t+1) per link (moving walls), or null
   // reductions
   double* partials;
@@ -299,6 +304,7 @@ struct lbm_domain_s {
   int64_t red_blocks;
   int64_t steps;
   bool state_set;                // lbm_set_state was called (the state is not the initial one)
+  int64_t state_step;            // steps when the state was last imported (set_state, links)
   // moving sphere (lbm_set_moving_sphere)
   bool moving;
   double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
@@ -313,8 +319,8 @@ struct lbm_domain_s {
   double* luw;                       // [3 nl] wall velocity at t, or null
   int32_t* lgrp;                     // [nl] group of each stored link, or null (one group)
   int32_t n_groups;
-  double* lforce;                    // [3 nl] scratch
-  double* gforce;                    // [3 n_groups]
+  double* lforce;                    // [6 nl] scratch: force and torque per link
+  double* gforce;                    // [6 n_groups] sums, then [3 n_groups] torque reference points
   int64_t links_step;                // steps when the links were installed
 };
 

@@ -374,7 +374,9 @@ __device__ __forceinline__ DenseIndex dense_index(const GridGeom& g, Coords c) {
   return p;
 }
 
-// Compact layout: slot of fluid node (x, row r) = 1 + fbase[seg] + popc(mask below x).
+// Compact layout: slot of fluid node (x, row r) = G + fbase[seg] + popc(mask below x),
+// G = the guard (64 slots, so that a segment whose fluid count before it is a
+// multiple of the line size starts on a cache line).
 // For each source row (y - cy, z - cz) the lane keeps P = slot the node x would
 // have in that row and B = whether (x, row) is fluid; then the source slot of
 // direction i is P (cx = 0), P - 1 (cx = +1, node x - 1) or P + B (cx = -1,
@@ -414,14 +416,14 @@ __device__ __forceinline__ CompactIndex<L> compact_index(const GridGeom& g, cons
       const uint32_t row = yy + (uint32_t)g.ny * zz;
       const uint32_t s0 = row * (uint32_t)g.nseg_x;
       const uint64_t fm = load_const(lk.seg_fluid + s0 + sx);
-      const uint32_t fb = (uint32_t)load_const(lk.seg_fbase + s0 + sx) + 1u;
+      const uint32_t fb = (uint32_t)load_const(lk.seg_fbase + s0 + sx) + (uint32_t)g.guard;
       // number of fluid nodes of this segment below the lane (one mbcnt pair)
       const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
       p.P[a][b] = fb + below;
       p.B[a][b] = (uint32_t)((fm >> si.lane) & 1ull);
       if (wrap) {
-        p.lo[a][b] = (uint32_t)load_const(lk.seg_fbase + s0 + (uint32_t)g.nseg_x);   // last fluid node of the row
-        p.hi[a][b] = (uint32_t)load_const(lk.seg_fbase + s0) + 1u;                     // first fluid node of the row
+        p.lo[a][b] = (uint32_t)load_const(lk.seg_fbase + s0 + (uint32_t)g.nseg_x) + (uint32_t)g.guard - 1u;   // last fluid node of the row
+        p.hi[a][b] = (uint32_t)load_const(lk.seg_fbase + s0) + (uint32_t)g.guard;                        // first fluid node of the row
       } else {
         p.lo[a][b] = p.P[a][b];
         p.hi[a][b] = p.P[a][b];
@@ -695,12 +697,6 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       }
       R v = a.a4 * n_pre + a.a5 * n_post + a.a2 * hs_b + w * (mb.drho * (a.a4 + a.a5) + mb.rho * gw);
       v += a.a3 * hs_i;
-      if (p.open_links && q == R(0)) {
-        // open link (q = 0) at the outlet density: anti-bounce-back with the node's
-        // velocity, h_i = -h*_ibar + 2 (w rho_out [1 + 4.5 (c.u)^2 - 1.5 u.u] - w)
-        const R cu = cx * mb.ux + cy * mb.uy + cz * mb.uz;
-        v = R(2) * (w * (R(p.rho_out) * (R(1) + R(4.5) * cu * cu - R(1.5) * mb.uu)) - w) - hs_b;
-      }
       if (list_mode) {
         lvo[k] = v;
       } else {
@@ -914,57 +910,65 @@ __device__ __forceinline__ void block_sum_fixed(double (*sh)[BLOCK], double* v, 
   }
 }
 
+// Moments of every node and block partial sums of mass, momentum and (with a
+// previous field) the residual.  Workgroup b walks the logical blocks b,
+// b + gridDim.x, ... (one each when the grid covers the lattice), so the
+// partials have one row per workgroup.
 template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void macros_kernel(MacroParams p) {
   using R = typename Storage<S>::R;
   __shared__ double sh[NPART][BLOCK];
   __shared__ R stage[L::Q][BLOCK];
   const GridGeom& g = p.g;
-  const SegInfo si = seg_info(g);
   double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const bool seg_ok = si.seg < g.nseg;
-  const bool in = seg_ok && si.c.x < g.nx;
-  const bool fluid = in && ((p.lk.seg_fluid[si.seg] >> si.lane) & 1ull);
-  R h[L::Q];
-  if (seg_ok) gather_state<L, S, COMPACT>(g, p.lk, p.src, si, fluid, h, stage);
-  if (in) {
-    const Coords c = si.c;
-    const int64_t n = c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * c.z);
-    double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
-    if (fluid) {
-      double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int64_t b = blockIdx.x; b < p.nblocks; b += gridDim.x) {
+    const SegInfo si = seg_info(g, (uint32_t)b);
+    const bool seg_ok = si.seg < g.nseg;
+    const bool in = seg_ok && si.c.x < g.nx;
+    const bool fluid = in && ((p.lk.seg_fluid[si.seg] >> si.lane) & 1ull);
+    R h[L::Q];
+    if (seg_ok) gather_state<L, S, COMPACT>(g, p.lk, p.src, si, fluid, h, stage);
+    if (in) {
+      const Coords c = si.c;
+      const int64_t n = c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * c.z);
+      double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+      if (fluid) {
+        double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
-        const double hi = double(h[i]);
-        drho += hi;
-        jx += L::cx(i) * hi;
-        jy += L::cy(i) * hi;
-        jz += L::cz(i) * hi;
+        for (int i = 0; i < L::Q; ++i) {
+          const double hi = double(h[i]);
+          drho += hi;
+          jx += L::cx(i) * hi;
+          jy += L::cy(i) * hi;
+          jz += L::cz(i) * hi;
+        }
+        rho = 1.0 + drho;
+        ux = (jx + 0.5 * p.force[0]) / rho;
+        uy = (jy + 0.5 * p.force[1]) / rho;
+        uz = (jz + 0.5 * p.force[2]) / rho;
+        v[0] += rho;
+        v[1] += rho * ux;
+        v[2] += rho * uy;
+        v[3] += rho * uz;
+        v[5] += ux * ux + uy * uy + (L::D == 3 ? uz * uz : 0.0);
+        v[6] += (isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz)) ? 0.0 : 1.0;
+        if (p.uprev) {
+          double* up = p.uprev + n * L::D;
+          const double dx = ux - up[0], dy = uy - up[1], dz = L::D == 3 ? uz - up[2] : 0.0;
+          v[4] += dx * dx + dy * dy + dz * dz;
+          up[0] = ux;
+          up[1] = uy;
+          if (L::D == 3) up[2] = uz;
+        }
       }
-      rho = 1.0 + drho;
-      ux = (jx + 0.5 * p.force[0]) / rho;
-      uy = (jy + 0.5 * p.force[1]) / rho;
-      uz = (jz + 0.5 * p.force[2]) / rho;
-      const double* up = p.uprev + n * L::D;
-      const double dx = ux - up[0], dy = uy - up[1], dz = L::D == 3 ? uz - up[2] : 0.0;
-      v[0] = rho;
-      v[1] = rho * ux;
-      v[2] = rho * uy;
-      v[3] = rho * uz;
-      v[4] = dx * dx + dy * dy + dz * dz;
-      v[5] = ux * ux + uy * uy + (L::D == 3 ? uz * uz : 0.0);
-      v[6] = (isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(uz)) ? 0.0 : 1.0;
-      double* upw = p.uprev + n * L::D;
-      upw[0] = ux;
-      upw[1] = uy;
-      if (L::D == 3) upw[2] = uz;
+      if (p.rho) p.rho[n] = rho;
+      if (p.u) {
+        p.u[n * L::D + 0] = ux;
+        p.u[n * L::D + 1] = uy;
+        if (L::D == 3) p.u[n * L::D + 2] = uz;
+      }
     }
-    if (p.rho) p.rho[n] = rho;
-    if (p.u) {
-      p.u[n * L::D + 0] = ux;
-      p.u[n * L::D + 1] = uy;
-      if (L::D == 3) p.u[n * L::D + 2] = uz;
-    }
+    wave_lds_sync();   // the next block reuses the wave's LDS columns
   }
   block_sum_fixed(sh, v, threadIdx.x);
   if (threadIdx.x == 0) {
@@ -987,16 +991,19 @@ __global__ __launch_bounds__(BLOCK) void reduce_kernel(const double* partials, i
 #endif  // LBM_COMMON
 
 // ---------------------------------------------------------------------------
-// Momentum-exchange force of the last step (Sec. II "Force computation",
-// Galilean-invariant form): per cut link (x_F, i)
+// Momentum-exchange force and torque of the last step (Sec. II "Force
+// computation", Galilean-invariant form): per cut link (x_F, i)
 //   F = (c_ibar - u_w) f*_ibar(x_F, t-1) - (c_i - u_w) f_i(x_F, t),
+//   T = r x F,  r = x_W - x_ref (minimum image), x_W = x_F - q c_i the wall point,
 // with f*_ibar(x_F, t-1) the post-collision value the step left in x_F's own
-// slot of direction ibar, and f_i(x_F, t) the link value it rebuilt.
+// slot of direction ibar (no node pulls it: x_F - c_i is not fluid), and
+// f_i(x_F, t) the link value it rebuilt.
 // ---------------------------------------------------------------------------
 template <class L, int S, bool COMPACT>
 __global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams p) {
   using St = Storage<S>;
   using T = typename St::T;
+  using R = typename St::R;
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (k >= p.nl) return;
   const GridGeom& g = p.g;
@@ -1006,42 +1013,63 @@ __global__ __launch_bounds__(BLOCK) void force_kernel(ForceParams p) {
   const int64_t node = p.lk.lnode[k];
   const int64_t row = node / g.nx;
   const int x = (int)(node - row * g.nx);
+  const int64_t y = row % g.ny, z = row / g.ny;
   int64_t slot;
   if constexpr (COMPACT) {
     const int64_t seg = row * g.nseg_x + x / SEG;
     const uint64_t below = p.lk.seg_fluid[seg] & ((1ull << (x % SEG)) - 1ull);
-    slot = 1 + (int64_t)p.lk.seg_fbase[seg] + __popcll(below);
+    slot = g.guard + (int64_t)p.lk.seg_fbase[seg] + __popcll(below);
   } else {
-    const int64_t y = row % g.ny, z = row / g.ny;
     slot = (x + g.px) + (int64_t)g.NX * ((y + g.py) + (int64_t)g.NY * (z + g.pz));
   }
   const double w = dyn_w<L, double>(i);
   const double fs = (double)St::template load<L>(static_cast<const T*>(p.pop) + (size_t)ib * g.npad + slot, ib) + w;
-  const double fn = (S == ST_F64 ? static_cast<const double*>(p.lk.lv_in)[k]
-                                 : (double)static_cast<const float*>(p.lk.lv_in)[k]) + w;
+  const double fn = (double)static_cast<const R*>(p.lk.lv_in)[k] + w;
   const double c[3] = {(double)dyn_c<L, 0>(i), (double)dyn_c<L, 1>(i), (double)dyn_c<L, 2>(i)};
+  double F[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double u = p.luw ? p.luw[3 * k + a] : 0.0;
-    p.contrib[3 * k + a] = (-c[a] - u) * fs - (c[a] - u) * fn;
+    F[a] = (-c[a] - u) * fs - (c[a] - u) * fn;
   }
+  // lever arm from the group's reference point to the wall point
+  const double q = (double)static_cast<const R*>(p.lk.lq)[k];
+  const int grp = p.group ? p.group[k] : 0;
+  const double xw[3] = {x - q * c[0], (double)y - q * c[1], (double)z - q * c[2]};
+  const int n3[3] = {g.nx, g.ny, g.nz}, per[3] = {g.perx, g.pery, g.perz};
+  double r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = xw[a] - (p.centre ? p.centre[3 * grp + a] : 0.0);
+    if (per[a]) r[a] -= n3[a] * rint(r[a] / n3[a]);
+  }
+  if (L::D == 2) r[2] = 0.0;
+  double* o = p.contrib + 6 * k;
+  o[0] = F[0];
+  o[1] = F[1];
+  o[2] = F[2];
+  o[3] = r[1] * F[2] - r[2] * F[1];
+  o[4] = r[2] * F[0] - r[0] * F[2];
+  o[5] = r[0] * F[1] - r[1] * F[0];
 }
 
-// Sum of the contributions of the links of group blockIdx.x (all links when
-// group is null), in a fixed order.
+// Sum of the contributions (6 per link: force, torque) of the links of group
+// blockIdx.x (all links when group is null), in a fixed order.  The link count
+// is nl, or *nl_dev when that is given (counts held on the device).
 #ifdef LBM_COMMON
 __global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib, const int32_t* group, int64_t nl,
-                                                          double* out) {
+                                                          const int32_t* nl_dev, double* out) {
   __shared__ double sh[NPART][BLOCK];
   double v[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int gid = blockIdx.x;
-  for (int64_t k = threadIdx.x; k < nl; k += BLOCK) {
+  const int64_t n = nl_dev ? (int64_t)*nl_dev : nl;
+  for (int64_t k = threadIdx.x; k < n; k += BLOCK) {
     if (group && group[k] != gid) continue;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] += contrib[3 * k + a];
+    for (int a = 0; a < 6; ++a) v[a] += contrib[6 * k + a];
   }
   block_sum_fixed(sh, v, threadIdx.x);
-  if (threadIdx.x < 3) out[3 * gid + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < 6) out[6 * gid + threadIdx.x] = sh[threadIdx.x][0];
 }
 #endif  // LBM_COMMON
 
@@ -1188,8 +1216,7 @@ hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t
   LBM_BY_LATTICE(lattice, macros(storage, p, nblocks, s));
 }
 
-hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, const int32_t* group,
-                        double* out, hipStream_t s) {
+hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, double* out, hipStream_t s) {
   if (p.nl > 0) {
     hipError_t e;
     switch (lattice) {
@@ -1199,7 +1226,7 @@ hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t 
     }
     if (e != hipSuccess) return e;
   }
-  group_sum_kernel<<<n_groups, BLOCK, 0, s>>>(p.contrib, group, p.nl, out);
+  group_sum_kernel<<<n_groups, BLOCK, 0, s>>>(p.contrib, p.group, p.nl, nullptr, out);
   return hipGetLastError();
 }
 

@@ -41,18 +41,15 @@ def couette3d_domain(p, lattice="D3Q19", nz=4, storage="f64", variant="FQ", coll
     return d, mask, links
 
 
-def channel_geometry(p, outlet="zero-gradient"):
+def channel_geometry(p):
     """Channel with a cylinder: parabolic inlet at x = -1/2, walls at y = -1/2 and
-    ny - 1/2, outlet at +x: zero-gradient, or open at fixed density ("pressure")."""
+    ny - 1/2, zero-gradient outlet at +x."""
     nx, ny = p["nx"], p["ny"]
-    zg = outlet == "zero-gradient"
-    g = B.Geometry("D2Q9", nx, ny, 1, periodic=(False, False, True), outlet_face="+x" if zg else None)
+    g = B.Geometry("D2Q9", nx, ny, 1, periodic=(False, False, True), outlet_face="+x")
     g.add_sphere(p["centre"], p["radius"], True)
     g.add_face_wall("-x", 0.5, uw=(p["u_max"], 0, 0), profile=1)
     g.add_face_wall("-y", 0.5)
     g.add_face_wall("+y", 0.5)
-    if not zg:
-        g.add_pressure_face("+x")
     mask, links = g.build()
     g.close()
     return mask, links
@@ -76,14 +73,10 @@ def couette_domain(p, storage="f64", variant="FQ", layout="compact", collision="
     return d, mask, links
 
 
-def channel_domain(p, storage="f32", variant="FQ", layout="compact", wall_neq="bounceback", outlet="zero-gradient",
-                   rho_out=1.0):
-    mask, links = channel_geometry(p, outlet)
-    zg = outlet == "zero-gradient"
+def channel_domain(p, storage="f32", variant="FQ", layout="compact", wall_neq="bounceback"):
+    mask, links = channel_geometry(p)
     d = B.Domain("D2Q9", p["nx"], p["ny"], 1, mask, p["tau"], storage=storage,
-                 periodic=(False, False, True), outlet_face="+x" if zg else None, layout=layout)
-    if not zg:
-        d.set_outlet_density(rho_out)
+                 periodic=(False, False, True), outlet_face="+x", layout=layout)
     d.set_boundary_links(links, variant=variant)
     d.set_wall_neq(wall_neq)
     return d, mask, links

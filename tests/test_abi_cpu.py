@@ -86,20 +86,6 @@ def test_builder_matches_oracle_channel(B):
     _compare(mask, links, fluid, G.cut_links(dom, fluid, [cyl], faces))
 
 
-def test_builder_matches_oracle_pressure_outlet(B):
-    from paper_2009_04604_amd import workloads as W
-    p = synth.cylinder_channel(nx=300, ny=120, radius=9.0, centre=(60.0, 60.0))
-    mask, links = W.channel_geometry(p, outlet="pressure")
-    dom = G.Domain(lattice.D2Q9, p["nx"], p["ny"], 1, periodic=(False, False, True))
-    cyl = G.Sphere(p["centre"], p["radius"], True)
-    faces = [G.FaceWall(0, 0.5, G.parabolic_inlet(p["ny"], p["u_max"])), G.FaceWall(2, 0.5), G.FaceWall(3, 0.5),
-             G.PressureFace(1)]
-    fluid = G.classify(dom, [cyl])
-    _compare(mask, links, fluid, G.cut_links(dom, fluid, [cyl], faces))
-    n_open = int((links["q"] == 0.0).sum())
-    assert n_open == 3 * p["ny"] - 2            # (-1, y), (-1, y +- 1) at x = nx - 1, walls take the corners
-
-
 def test_builder_matches_oracle_packing(B):
     from paper_2009_04604_amd import workloads as W
     n = 64
@@ -173,14 +159,5 @@ def test_builder_rejects_bad_shapes(B):
         assert e.value.code == B.LBM_EINVAL
     with pytest.raises(B.LBMError) as e:
         g.add_cylinder((8.0, float("nan"), 0.0), 3.0)
-    assert e.value.code == B.LBM_EINVAL
-    with pytest.raises(B.LBMError) as e:
-        g.add_pressure_face("+x")                      # periodic axis
-    assert e.value.code == B.LBM_EINVAL
-    g.add_pressure_face("+y")
-    g.close()
-    g = B.Geometry("D2Q9", 32, 16, 1, periodic=(False, False, True), outlet_face="+x")
-    with pytest.raises(B.LBMError) as e:
-        g.add_pressure_face("+x")                      # the zero-gradient outlet's face
     assert e.value.code == B.LBM_EINVAL
     g.close()

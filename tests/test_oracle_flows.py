@@ -170,47 +170,30 @@ def test_wall_distance_matters_little_for_elibb_and_much_for_hwbb():
         assert err["HWBB", q] > 5 * err["FQ", q]
 
 
-def _inlet_channel(outlet, nx=60, ny=12, u_max=0.02, tau=0.8):
+def _inlet_channel(nx=60, ny=12, u_max=0.02, tau=0.8):
     per = (False, False, True)
     faces = [G.FaceWall(0, 0.5, G.parabolic_inlet(ny, u_max)), G.FaceWall(2, 0.5), G.FaceWall(3, 0.5)]
-    if outlet == "pressure":
-        dom = G.Domain(lattice.D2Q9, nx, ny, 1, periodic=per)
-        faces.append(G.PressureFace(1))
-        sim = solver.Simulation(dom, tau, rho_out=1.0)
-    else:
-        dom = G.Domain(lattice.D2Q9, nx, ny, 1, periodic=per, outlet_face=1)
-        sim = solver.Simulation(dom, tau)
+    dom = G.Domain(lattice.D2Q9, nx, ny, 1, periodic=per, outlet_face=1)
+    sim = solver.Simulation(dom, tau)
     fluid = np.ones(dom.shape, bool)
     sim.set_geometry(fluid, G.cut_links(dom, fluid, [], faces), "FQ")
     sim.init_equilibrium()
     return sim
 
 
-def test_pressure_outlet_keeps_mass_and_develops_poiseuille():
+def test_zero_gradient_outlet_mass_grows_under_velocity_inlet():
     """A straight channel fed with the Poiseuille profile (velocity inlet, walls at
-    q = 1/2): with the fixed-density outlet (anti-bounce-back, open links q = 0)
-    the flow reaches a steady state with bounded mass, the developed parabola
-    mid-channel, and the Poiseuille pressure gradient dp/dx = 8 rho nu u_max / H^2
-    (p = rho / 3); with the zero-gradient outlet the mass grows without bound
-    (the outflow falls short of the inflow and the inlet's momentum term scales
-    with the density)."""
-    nx, ny, u_max, tau = 60, 12, 0.02, 0.8
-    nu = (tau - 0.5) / 3
-    sim = _inlet_channel("pressure")
-    sim.run(6000)
-    m1 = sim.macros()[0].sum()
-    sim.run(600)
-    rho, u = sim.macros()
-    assert abs(rho.sum() / m1 - 1.0) < 1e-9                     # steady, mass bounded
-    y = np.arange(ny) + 0.5
-    uth = 4 * u_max * y * (ny - y) / ny ** 2
-    ux = u[0].reshape(ny, nx)
-    assert np.abs(ux[:, nx // 2] - uth).max() / u_max < 0.015
-    r = rho.reshape(ny, nx).mean(axis=0)
-    dpdx = (r[5] - r[nx - 6]) / 3 / (nx - 11)
-    assert abs(dpdx / (8 * nu * u_max / ny ** 2) - 1.0) < 0.05
-    zg = _inlet_channel("zero-gradient")
+    q = 1/2) and the zero-gradient outlet: the mass keeps growing (the outflow
+    falls short of the inflow and the inlet's momentum term scales with the
+    density) while the flow stays symmetric.  A finding about the outlet reading,
+    asserted so that the GPU path is held to the same behaviour."""
+    nx, ny = 60, 12
+    zg = _inlet_channel(nx, ny)
     zg.run(6000)
     m_a = zg.macros()[0].sum()
     zg.run(600)
-    assert zg.macros()[0].sum() > 1.02 * m_a                      # keeps growing
+    rho, u = zg.macros()
+    assert rho.sum() > 1.02 * m_a                                   # keeps growing
+    ux = u[0].reshape(ny, nx)
+    np.testing.assert_allclose(ux, ux[::-1], rtol=1e-10, atol=1e-15)   # symmetric about the centre line
+    assert np.all(ux[:, nx // 2] > 0)

@@ -229,6 +229,22 @@ int lbm_momentum_exchange(lbm_domain d, double* force);
  * D2Q9).  Same errors as lbm_momentum_exchange. */
 int lbm_force_torque(lbm_domain d, const double* centres, double* force, double* torque);
 
+/* Force and torque on a moving sphere (lbm_set_moving_sphere), Sec. II "Force
+ * computation": its links are rebuilt every step, so the momentum exchange of a
+ * step must be taken before the rebuild.  With tracking on (on = 1), every
+ * lbm_step call evaluates, after its last step and over the links of the
+ * geometry that step used (time t),
+ *   F = sum (c_ibar - u_w) f*_ibar(x_F, t) - (c_i - u_w) f_i(x_F, t+1),
+ *   T = sum r x F_link,  r = x_W - x_c(t) (minimum image), x_W = x_F - q c_i,
+ * u_w = V(t) + omega x r, summed in FP64 in a fixed order; lbm_moving_force
+ * copies the result out (force, torque: 3 doubles each, caller-owned;
+ * synchronises the stream).  Batched steps (lbm_batch_step) do not evaluate it.
+ * Errors: LBM_ESTATE without a moving sphere, with tracking off, or when the
+ * last step was not taken by lbm_step with tracking on; LBM_ENOMEM when the
+ * per-link scratch cannot be allocated (done by lbm_set_force_tracking). */
+int lbm_set_force_tracking(lbm_domain d, int32_t on);
+int lbm_moving_force(lbm_domain d, double* force, double* torque);
+
 /* Change the stream used by later calls. */
 int lbm_set_stream(lbm_domain d, void* stream);
 

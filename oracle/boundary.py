@@ -268,7 +268,7 @@ def reconstruct(coef, P):
     return (coef.T * P).sum(axis=0)
 
 
-def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups):
+def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups, arm=None):
     """Force exerted by the fluid on the walls during one step, per link group
     (Sec. II "Force computation", the Galilean-invariant momentum exchange of
     Wen et al.).  For a cut link (x_F, i) the population f*_ibar(x_F, t) leaves
@@ -276,10 +276,14 @@ def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups):
         F_link = (c_ibar - u_w) f*_ibar(x_F, t) - (c_i - u_w) f_i(x_F, t+1).
     (The printed formula writes the outgoing post-collision population with the
     index i; it is read as ibar, the direction pointing into the wall.)
+    The torque is T = sum over the group's links of r x F_link with the lever
+    arm r given per link (the paper names the torque without fixing the arm;
+    the caller passes the wall point's offset from the group's reference).
 
     i: (n,) missing directions; fstar_F: (Q, n) post-collision populations of the
     links' nodes at t; f_new: (n,) rebuilt f_i(x_F, t+1); uw_t: (3, n) wall
-    velocity at x_W; group: (n,) group ids.  Returns (n_groups, 3).
+    velocity at x_W; group: (n,) group ids; arm: (3, n) or None.  Returns
+    (n_groups, 3) forces, and with an arm also (n_groups, 3) torques.
     """
     ib = lat.opp[i]
     n = np.arange(i.size)
@@ -287,8 +291,11 @@ def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups):
     out_ = fstar_F[ib, n]
     contrib = (c[ib].T - uw_t) * out_[None, :] - (c[i].T - uw_t) * f_new[None, :]   # (3, n)
     F = np.zeros((n_groups, 3))
+    T = np.zeros((n_groups, 3))
+    tq = None if arm is None else np.cross(arm.T, contrib.T).T
     for g in range(n_groups):
         sel = group == g
         F[g] = contrib[:, sel].sum(axis=1)
-    return F
-
+        if tq is not None:
+            T[g] = tq[:, sel].sum(axis=1)
+    return F if arm is None else (F, T)

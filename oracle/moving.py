@@ -71,6 +71,8 @@ class MovingSphereSim:
         self.sim.set_geometry(fluid, links, self.variant, self.q_cut, wall_neq=self.wall_neq)
 
     def step(self):
+        # torques about the sphere's centre at the geometry's time t
+        self.sim.centres = self.kin.centre(self.t)[None, :].copy()
         self.sim.step()
         self.t += 1
         self._install()

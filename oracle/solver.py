@@ -116,8 +116,10 @@ class Simulation:
         self.fluid = None
         self.t = 0
         self.last_force = None     # (n_groups, 3): wall forces of the last step
+        self.last_torque = None    # (n_groups, 3): wall torques of the last step about the group centres
         self.link_group = None
         self.n_groups = 1
+        self.centres = np.zeros((1, 3))
 
     # -- geometry -----------------------------------------------------------------
     def set_geometry(self, fluid, links, variant="FQ", q_cut=0.01, wall_neq="bounceback"):
@@ -203,17 +205,25 @@ class Simulation:
                                      self.wall_neq)
             fnew[d, n] = boundary.reconstruct(self.coef, P)
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
-            self.last_force = boundary.momentum_exchange(lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp,
-                                                         self.n_groups)
+            # lever arm: wall point x_W = x_F - q c_i relative to the group's centre (minimum image)
+            xw = self.dom.coords(n).astype(np.float64) - L["q"][None, :] * lat.c[d].T
+            arm = self.dom.min_image(xw - self.centres[grp].T)
+            if lat.d == 2:
+                arm[2] = 0.0
+            self.last_force, self.last_torque = boundary.momentum_exchange(
+                lat, d, fstar[:, n], fnew[d, n], L["uw_t"], grp, self.n_groups, arm)
         self.f = fnew
         self.t += 1
 
-    def set_link_groups(self, group, n_groups):
-        """Group ids (one per link, in the link list's order) for the forces."""
+    def set_link_groups(self, group, n_groups, centres=None):
+        """Group ids (one per link, in the link list's order) for the forces, and
+        the reference point of each group's torque (default: the origin)."""
         g = np.asarray(group, dtype=np.int64).reshape(-1)
         if g.size != self.links["node"].size or (g.size and (g.min() < 0 or g.max() >= n_groups)):
             raise ValueError("bad link groups")
         self.link_group, self.n_groups = g, int(n_groups)
+        self.centres = np.zeros((self.n_groups, 3)) if centres is None else \
+            np.asarray(centres, dtype=np.float64).reshape(self.n_groups, 3)
 
     def run(self, n):
         for _ in range(int(n)):

@@ -35,7 +35,8 @@ EXPORTED = [
     "lbm_geometry_add_face_wall", "lbm_geometry_build", "lbm_geometry_get", "lbm_geometry_free",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
-    "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque",
+    "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque", "lbm_set_force_tracking",
+    "lbm_moving_force",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -119,6 +120,8 @@ def lib():
         "lbm_set_wall_neq": (I32, [P, I32]),
         "lbm_geometry_add_cylinder": (I32, [P, P, DBL, I32, P, P]),
         "lbm_force_torque": (I32, [P, P, P, P]),
+        "lbm_set_force_tracking": (I32, [P, I32]),
+        "lbm_moving_force": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -330,6 +333,17 @@ class Domain:
         c = None if centres is None else np.ascontiguousarray(centres, dtype=np.float64).reshape(n, 3)
         f, t = np.zeros((n, 3)), np.zeros((n, 3))
         _check(lib().lbm_force_torque(self.h, _ptr(c), _ptr(f), _ptr(t)))
+        return f, t
+
+    def set_force_tracking(self, on=True):
+        """Moving sphere: evaluate the force and torque of the last step of every
+        step() call (before its links are rebuilt)."""
+        _check(lib().lbm_set_force_tracking(self.h, 1 if on else 0))
+
+    def moving_force(self):
+        """(force (3,), torque (3,)) on the moving sphere during the last step."""
+        f, t = np.zeros(3), np.zeros(3)
+        _check(lib().lbm_moving_force(self.h, _ptr(f), _ptr(t)))
         return f, t
 
     def set_launch_option(self, option, value):

@@ -732,6 +732,15 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
     d->cur ^= 1;
     ++d->steps;
     if (d->moving) {
+      if (d->track_force && s == n_steps - 1) {
+        // force and torque on the links of the geometry this step used, before the rebuild
+        MovingParams mp = moving_params(d, d->cur);
+        mp.k = moving_kin(d, d->steps - 1);
+        e = launch_moving_force(d->desc.lattice, d->desc.storage, mp, d->mforce, d->mforce + 6 * d->link_cap,
+                                d->stream);
+        if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("moving force: ") + hipGetErrorString(e));
+        d->force_step = d->steps;
+      }
       e = rebuild_moving(d, d->steps, true);
       if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("moving geometry: ") + hipGetErrorString(e));
     }
@@ -894,6 +903,34 @@ int lbm_force_torque(lbm_domain d, const double* centres, double* force, double*
   return force_torque(d, centres, force, torque);
 }
 
+int lbm_set_force_tracking(lbm_domain d, int32_t on) {
+  if (!d) return fail(LBM_EINVAL, "null domain");
+  if (!d->moving) return fail(LBM_ESTATE, "force tracking is for moving spheres (static links: lbm_force_torque)");
+  if (on != 0 && on != 1) return fail(LBM_EINVAL, "on must be 0 or 1");
+  if (on && !d->mforce)
+    if (int e = dalloc(d->mforce, ((size_t)d->link_cap + 1) * 6 * 8)) return e;
+  d->track_force = on != 0;
+  d->force_step = -1;
+  clear_error();
+  return LBM_OK;
+}
+
+int lbm_moving_force(lbm_domain d, double* force, double* torque) {
+  if (!d || !force || !torque) return fail(LBM_EINVAL, "null argument");
+  if (!d->moving || !d->track_force) return fail(LBM_ESTATE, "force tracking is not on (lbm_set_force_tracking)");
+  if (d->force_step != d->steps)
+    return fail(LBM_ESTATE, "the last step was not taken by lbm_step with tracking on (or none was taken)");
+  double h[6];
+  HIP_TRY(hipMemcpyAsync(h, d->mforce + 6 * d->link_cap, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIP_TRY(hipStreamSynchronize(d->stream));
+  for (int a = 0; a < 3; ++a) {
+    force[a] = h[a];
+    torque[a] = h[3 + a];
+  }
+  clear_error();
+  return LBM_OK;
+}
+
 int lbm_set_stream(lbm_domain d, void* stream) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   d->stream = static_cast<hipStream_t>(stream);
@@ -959,6 +996,7 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->seg_prev);
   dfree(d->reg_count);
   dfree(d->reg_cut);
+  dfree(d->mforce);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

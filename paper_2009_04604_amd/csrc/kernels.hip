@@ -1230,6 +1230,12 @@ hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t 
   return hipGetLastError();
 }
 
+hipError_t launch_group_sum(const double* contrib, const int32_t* group, int64_t nl, const int32_t* nl_dev,
+                            int32_t n_groups, double* out, hipStream_t s) {
+  group_sum_kernel<<<n_groups, BLOCK, 0, s>>>(contrib, group, nl, nl_dev, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s) {
   reduce_kernel<<<1, BLOCK, 0, s>>>(partials, nblocks, out);
   return hipGetLastError();

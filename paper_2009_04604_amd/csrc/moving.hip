@@ -283,6 +283,72 @@ __device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave)
   }
 }
 
+// Momentum-exchange force and torque of the step that used geometry t (Sec. II
+// "Force computation", Galilean-invariant form), per link of that geometry,
+// evaluated after the step and before the links are rebuilt:
+//   F = (c_ibar - u_w) f*_ibar(x_F, t) - (c_i - u_w) f_i(x_F, t+1),  T = r x F,
+// r = x_W - x_c(t) (minimum image), u_w = V(t) + Omega x r; f*_ibar(x_F, t) is
+// x_F's own post-collision slot (no node pulls it), f_i(x_F, t+1) the value the
+// step stored in the solid-side slot x_F - c_i.  `pop` is the buffer the step
+// wrote; out receives 6 doubles per link.
+template <class L, int S>
+__device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, double* out) {
+  using St = Storage<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  if (p.reg_count[wave] == 0) return;
+  const Site s = region_site(p, wave);
+  const GridGeom& g = p.g;
+  const T* pop = static_cast<const T*>(p.pop);
+  const size_t np = (size_t)g.npad;
+  auto slot = [&](int x, int y, int z) -> size_t {
+    return (size_t)(x + g.px) + (size_t)g.NX * ((size_t)(y + g.py) + (size_t)g.NY * (size_t)(z + g.pz));
+  };
+  const int lb0 = p.seg_lbase[s.seg], lb1 = p.seg_lbase[s.seg + 1];
+  const R* lq = static_cast<const R*>(p.lq);
+  for (int k = lb0 + s.lane; k < lb1; k += 64) {
+    const int ld = p.lld[k];
+    const int nl = ld & 63, i = ld >> 8;
+    const int x = s.x - s.lane + nl;
+    int cx = 0, cy = 0, cz = 0, ib = 0;
+    double w = 0.0;
+#pragma unroll
+    for (int j = 1; j < L::Q; ++j)
+      if (j == i) {
+        cx = L::cx(j);
+        cy = L::cy(j);
+        cz = L::cz(j);
+        ib = L::opp(j);
+        w = L::w(j);
+      }
+    double fs = 0.0, fn = 0.0;
+#pragma unroll
+    for (int j = 1; j < L::Q; ++j) {
+      if (j == ib) fs = (double)St::template load<L>(pop + j * np + slot(x, s.y, s.z), j) + w;
+      if (j == i)
+        fn = (double)St::template load<L>(pop + j * np + slot(wrap(x - cx, g.nx, g.perx), wrap(s.y - cy, g.ny, g.pery),
+                                                               wrap(s.z - cz, g.nz, g.perz)), j) + w;
+    }
+    const double q = (double)lq[k];
+    double r[3], u[3];
+    rel(p, x - q * cx, s.y - q * cy, s.z - q * cz, r);
+    const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
+    body_velocity(p, V, r, u);
+    if (L::D == 2) u[2] = r[2] = 0.0;
+    const double c[3] = {(double)cx, (double)cy, (double)cz};
+    double F[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = (-c[a] - u[a]) * fs - (c[a] - u[a]) * fn;
+    double* o = out + 6 * (int64_t)k;
+    o[0] = F[0];
+    o[1] = F[1];
+    o[2] = F[2];
+    o[3] = r[1] * F[2] - r[2] * F[1];
+    o[4] = r[2] * F[0] - r[0] * F[2];
+    o[5] = r[0] * F[1] - r[1] * F[0];
+  }
+}
+
 // Single sphere: one wave per region segment.
 template <class L>
 __global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
@@ -302,6 +368,12 @@ template <class L, int S>
 __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
   const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (wave < p.nreg) refill_body<L, S>(p, wave);
+}
+
+template <class L, int S>
+__global__ __launch_bounds__(256) void moving_force_kernel(MovingParams p, double* out) {
+  const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (wave < p.nreg) force_body<L, S>(p, wave, out);
 }
 
 // Entry of the sphere table with its pointers read through the constant address
@@ -416,6 +488,30 @@ hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p,
   }
 #undef LBM_REFILL
   return hipGetLastError();
+}
+
+hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, double* contrib, double* out,
+                               hipStream_t s) {
+  if (p.nreg > 0) {
+#define LBM_MFORCE(LAT)                                                                            \
+  switch (storage) {                                                                               \
+    case ST_F64: moving_force_kernel<LAT, ST_F64><<<region_grid(p), 256, 0, s>>>(p, contrib); break;  \
+    case ST_F32: moving_force_kernel<LAT, ST_F32><<<region_grid(p), 256, 0, s>>>(p, contrib); break;  \
+    case ST_F16S: moving_force_kernel<LAT, ST_F16S><<<region_grid(p), 256, 0, s>>>(p, contrib); break;\
+    default: moving_force_kernel<LAT, ST_BF16S><<<region_grid(p), 256, 0, s>>>(p, contrib); break;    \
+  }
+    if (lattice == LBM_D2Q9) {
+      LBM_MFORCE(D2Q9)
+    } else if (lattice == LBM_D3Q19) {
+      LBM_MFORCE(D3Q19)
+    } else {
+      LBM_MFORCE(D3Q27)
+    }
+#undef LBM_MFORCE
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_group_sum(contrib, nullptr, 0, p.seg_lbase + p.g.nseg, 1, out, s);
 }
 
 hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s) {

@@ -1,7 +1,8 @@
-"""GPU momentum-exchange force (lbm_set_link_groups, lbm_momentum_exchange)
-against the oracle's per-step force, per object, and the momentum balance of
-the whole packing at full size (force on the walls = body force on the fluid
-minus the change of the fluid's momentum, from the library's own FP64 sums)."""
+"""GPU momentum-exchange force and torque (lbm_set_link_groups,
+lbm_momentum_exchange, lbm_force_torque) against the oracle's per-step force
+and torque, per object, and the momentum balance of the whole packing at full
+size (force on the walls = body force on the fluid minus the change of the
+fluid's momentum, from the library's own FP64 sums)."""
 import numpy as np
 import pytest
 
@@ -27,15 +28,19 @@ def test_channel_cylinder_forces_per_object(gpu_lib, storage, tol, layout):
     d, mask, links = case.gpu(gpu_lib, storage, layout=layout)
     sim = case.oracle()
     groups = links["shape"]                   # 0 cylinder, 1 inlet, 2 bottom, 3 top
+    centres = np.array([[40.3, 40.6, 0.0], [0.0, 40.0, 0.0], [100.0, 0.0, 0.0], [100.0, 80.0, 0.0]])
     d.set_link_groups(groups, 4)
-    sim.set_link_groups(sim.links["shape"], 4)
+    sim.set_link_groups(sim.links["shape"], 4, centres=centres)
     for n in (1, 60):
         d.step(n)
         sim.run(n)
         Fg, Fo = d.force(), sim.last_force
         err = _force_error(Fg, Fo)
-        _say("step", sim.t, "cylinder force", Fg[0], "max rel err", err)
-        assert err <= tol
+        Fg2, Tg = d.force_torque(centres)
+        terr = _force_error(Tg, sim.last_torque)
+        _say("step", sim.t, "cylinder force", Fg[0], "torque", Tg[0], "max rel err", err, terr)
+        assert err <= tol and terr <= tol
+        assert np.array_equal(Fg, Fg2)
     d.close()
 
 
@@ -48,13 +53,16 @@ def test_moving_walls_force(gpu_lib, storage, tol):
     _say("case force ragged 3D", storage)
     d, _, links = case.gpu(gpu_lib, storage)
     sim = case.oracle()
+    centres = np.array([[30.4, 14.2, 11.7], [33.0, -0.5, 11.0], [33.0, 28.5, 11.0]])
     d.set_link_groups(links["shape"], 3)
-    sim.set_link_groups(sim.links["shape"], 3)
+    sim.set_link_groups(sim.links["shape"], 3, centres=centres)
     d.step(25)
     sim.run(25)
     err = _force_error(d.force(), sim.last_force)
-    _say("max rel err", err)
-    assert err <= tol
+    F, T = d.force_torque(centres)
+    terr = _force_error(T, sim.last_torque)
+    _say("max rel err force", err, "torque", terr)
+    assert err <= tol and terr <= tol
     d.close()
 
 
@@ -89,4 +97,15 @@ def test_force_validation(gpu_lib):
     with pytest.raises(B.LBMError) as e:
         d.set_link_groups(np.full(len(links["node"]), 5), 4)
     assert e.value.code == B.LBM_EINVAL
+    d.step(2)
+    f = d.get_state()
+    d.set_state(f)
+    with pytest.raises(B.LBMError) as e:
+        d.force_torque()                 # no step since the state was set
+    assert e.value.code == B.LBM_ESTATE
+    d.step(1)
+    with pytest.raises(B.LBMError) as e:
+        d.force_torque(np.array([[np.nan, 0.0, 0.0]]))
+    assert e.value.code == B.LBM_EINVAL
+    d.force_torque(np.zeros((1, 3)))
     d.close()

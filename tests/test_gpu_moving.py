@@ -76,3 +76,34 @@ def test_moving_sphere_requires_dense_periodic(gpu_lib):
         d.set_moving_sphere((12, 12, 12), 9.0, 4.0, 50.0, (1, 0, 0), (0, 0, 0))   # sweep too large
     assert e.value.code == B.LBM_EINVAL
     d.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_moving_sphere_force_and_torque_match_oracle(gpu_lib, storage, tol):
+    """Force and torque on the moving sphere (momentum exchange over the links of
+    the geometry each step used, taken before the rebuild) against the oracle's
+    per-step force and torque about the sphere centre."""
+    B = gpu_lib
+    c = _case()
+    _say("case moving sphere force 40^3", storage)
+    d = _gpu(B, c, storage)
+    d.set_force_tracking(True)
+    with pytest.raises(B.LBMError) as e:
+        d.moving_force()                                  # no step with tracking yet
+    assert e.value.code == B.LBM_ESTATE
+    m = _oracle(c)
+    for n in (1, 7, 12):
+        d.step(n)
+        m.run(n)
+        F, T = d.moving_force()
+        Fo, To = m.sim.last_force[0], m.sim.last_torque[0]
+        ferr = np.abs(F - Fo).max() / np.abs(Fo).max()
+        terr = np.abs(T - To).max() / np.abs(To).max()
+        _say("t", m.t, "force", F, "torque", T, "rel err", ferr, terr)
+        assert ferr <= tol and terr <= tol
+    d.close()
+    static = B.Domain("D3Q19", 16, 16, 16, np.ones(16 ** 3, np.uint8), 0.8, storage="f32")
+    with pytest.raises(B.LBMError) as e:
+        static.set_force_tracking(True)                   # static links: lbm_force_torque
+    assert e.value.code == B.LBM_ESTATE
+    static.close()

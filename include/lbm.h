@@ -192,6 +192,24 @@ int lbm_step(lbm_domain d, int32_t n_steps);
  * LBM_EDEVICE on allocation or device errors. */
 int lbm_macros(lbm_domain d, double* rho, double* u, double* sums);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the moments and FP64 sums of
+ * lbm_macros with no allocation, no host transfer and no synchronisation.
+ * rho [N], u [N*D] (node-major; either may be NULL) and sums [8] are DEVICE
+ * pointers owned by the caller; everything is enqueued on the domain's stream
+ * and is complete when that stream is.  sums = {mass, mom_x, mom_y, mom_z, 0,
+ * sum |u|^2, number of fluid nodes with a NaN/Inf moment, 0} (mom_z = 0 for
+ * D2Q9; no residual: its previous field would need N*D doubles of storage).
+ * The block partial sums live in a 64 KiB file-scope device array (one per
+ * GPU, held until the process ends; any lattice size fits, the kernel walks
+ * the lattice with at most 1024 workgroups), so calls that overlap on one GPU
+ * (several streams, several threads) race on it and must be serialised by the
+ * caller.  Field values are identical to lbm_macros'; the sums agree to
+ * rounding (another summation tree).  Errors: LBM_EINVAL for a null domain or
+ * sums, LBM_EDEVICE when the scratch address could not be found on the
+ * domain's device or a launch fails. */
+int lbm_macros_noalloc(lbm_domain d, double* rho, double* u, double* sums);
+
 /* Export / import the pre-collision populations f_i(x, t) as [Q][N] float64
  * (solid nodes read as 0 and are ignored on import).  For 16-bit storage the
  * import rounds to the storage format.  At a zero-gradient outlet an inward

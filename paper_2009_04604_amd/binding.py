@@ -36,7 +36,7 @@ EXPORTED = [
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
     "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque", "lbm_set_force_tracking",
-    "lbm_moving_force",
+    "lbm_moving_force", "lbm_macros_noalloc",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -122,6 +122,7 @@ def lib():
         "lbm_force_torque": (I32, [P, P, P, P]),
         "lbm_set_force_tracking": (I32, [P, I32]),
         "lbm_moving_force": (I32, [P, P, P]),
+        "lbm_macros_noalloc": (I32, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -334,6 +335,13 @@ class Domain:
         f, t = np.zeros((n, 3)), np.zeros((n, 3))
         _check(lib().lbm_force_torque(self.h, _ptr(c), _ptr(f), _ptr(t)))
         return f, t
+
+    def macros_noalloc(self, rho, u, sums):
+        """lbm_macros_noalloc into caller-owned device tensors (float64, CUDA):
+        rho (N,) or None, u (N, D) or None, sums (8,); asynchronous on the
+        domain's stream."""
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _check(lib().lbm_macros_noalloc(self.h, ptr(rho), ptr(u), ptr(sums)))
 
     def set_force_tracking(self, on=True):
         """Moving sphere: evaluate the force and torque of the last step of every

@@ -27,6 +27,7 @@ SOURCES = [
     ("kernels.hip", "kernels_d3q19.o", ["-DLBM_LATTICE=D3Q19"]),
     ("kernels.hip", "kernels_d3q27.o", ["-DLBM_LATTICE=D3Q27"]),
     ("moving.hip", "moving.o", []),
+    ("noalloc.hip", "noalloc.o", []),
     ("api.cpp", "api.o", []),
     ("batch.cpp", "batch.o", []),
     ("geometry.cpp", "geometry.o", []),

@@ -353,8 +353,14 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(LBM_EDEVICE, "no HIP device");
 
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(LBM_EDEVICE, "no current HIP device");
+  // per-device set-up of the no-allocation entry point's scratch address; a
+  // failure only disables lbm_macros_noalloc (it reports the error)
+  (void)noalloc_setup(dev);
   auto* dm = new lbm_domain_s();   // value-initialised: every pointer null, counters 0
   dm->desc = d;
+  dm->device = dev;
   dm->desc.periodic = per;
   const Lat& L = lat_of(d.lattice);
   dm->Q = L.Q;

@@ -268,11 +268,15 @@ struct MovingBatch {
 };
 hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s);
 hipError_t launch_advance(int64_t* ctr, hipStream_t s);
+// Address of the no-allocation scratch array on a device, looked up once per
+// device (noalloc.hip); called by lbm_init_domain with that device current.
+hipError_t noalloc_setup(int device);
 
 }  // namespace lbm
 
 struct lbm_domain_s {
   lbm_domain_desc desc;
+  int device;                    // HIP device current when the domain was created
   uint64_t uid;                  // unique per domain, renewed when its device layout changes
   int Q, D;
   lbm::GridGeom g;

@@ -263,6 +263,33 @@ def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq="bounc
     return np.stack([P0, P1, P2, P3])
 
 
+def bfl_value(lat, i, q, rho_F, fstar_F, fstar_FF, ff_ok, uw_t):
+    """Linear BFL (eq. bfl), the two-node interpolated bounce-back the paper
+    compares the ELIBB with: for the cut link (x_F, i), with x_FF = x_F + c_i the
+    next node along the link, away from the wall,
+        q <  1/2:  f_i(x_F, t+1) = 2q f*_ibar(x_F) + (1 - 2q) f*_ibar(x_FF) + m,
+        q >= 1/2:  f_i(x_F, t+1) = f*_ibar(x_F) / (2q) + (2q - 1)/(2q) f*_i(x_F) + m / (2q),
+    (weights from bfl_coefficients, i.e. the paper's printed ones), m = 2 w_i rho_F
+    c_i.u_w / c_s^2 the moving-wall term of eq. ME-solid-to-fluid, added where the
+    bounce happens (in full before the bounce-back streaming when q < 1/2, carried
+    with the bounced population's weight 1/(2q) when q >= 1/2; the paper states BFL
+    for resting walls).  Where x_FF is not a fluid node (ff_ok false; a gap one
+    node wide) the link falls back to half-way bounce-back, f*_ibar(x_F) + m.
+
+    i: (n,); q: (n,); rho_F: (n,); fstar_F, fstar_FF: (Q, n); ff_ok: (n,) bool;
+    uw_t: (3, n).  Returns (n,)."""
+    ib = lat.opp[i]
+    n = np.arange(i.size)
+    c = lat.c[i].T.astype(np.float64)
+    m = 2.0 * lat.w[i] * rho_F * (c * uw_t).sum(axis=0) / lat.cs2
+    w = bfl_coefficients(q)
+    lo = q < 0.5
+    f_lo = w["P2"] * fstar_F[ib, n] + w["PFF"] * np.where(ff_ok, fstar_FF[ib, n], 0.0) + m
+    f_hi = w["P2"] * (fstar_F[ib, n] + m) + w["P3"] * fstar_F[i, n]
+    hw = fstar_F[ib, n] + m
+    return np.where(lo, np.where(ff_ok, f_lo, hw), f_hi)
+
+
 def reconstruct(coef, P):
     """f_i(x_F, t+1) = sum_k a_k P_k  (eq. interpolated_bb_equation)."""
     return (coef.T * P).sum(axis=0)

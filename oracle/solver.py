@@ -133,7 +133,23 @@ class Simulation:
         self.variant, self.q_cut, self.wall_neq = variant, float(q_cut), wall_neq
         L = {k: np.asarray(v) for k, v in links.items()}
         self.links = L
-        self.coef = boundary.coefficients(variant, L["q"], q_cut)
+        # BFL (oracle-only comparator, eq. bfl) also reads the next node along the
+        # link, x_FF = x_F + c_i; the ELIBB variants use their Lagrange weights
+        if variant == "BFL":
+            self.coef = None
+            if L["node"].size:
+                from .geometry import _index
+                xs = dom.coords(L["node"]) + lat.c[L["dir"]].T
+                ok = np.ones(xs.shape[1], dtype=bool)
+                for a in range(3):
+                    if dom.periodic[a]:
+                        xs[a] = np.mod(xs[a], dom.n[a])
+                    else:
+                        ok &= (xs[a] >= 0) & (xs[a] < dom.n[a])
+                self.ff = np.where(ok, _index(dom, np.where(ok, xs, 0)), 0)
+                self.ff_ok = ok & fl[self.ff]
+        else:
+            self.coef = boundary.coefficients(variant, L["q"], q_cut)
         cut = np.zeros((lat.q, dom.N), dtype=bool)
         if L["node"].size:
             if not fl[L["node"]].all():
@@ -201,9 +217,13 @@ class Simulation:
         L = self.links
         if L["node"].size:
             n, d = L["node"], L["dir"]
-            P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"],
-                                     self.wall_neq)
-            fnew[d, n] = boundary.reconstruct(self.coef, P)
+            if self.variant == "BFL":
+                fnew[d, n] = boundary.bfl_value(lat, d, L["q"], rho[n], fstar[:, n], fstar[:, self.ff], self.ff_ok,
+                                                L["uw_t"])
+            else:
+                P = boundary.link_points(lat, d, rho[n], feq[:, n], f[:, n], fstar[:, n], L["uw_t"], L["uw_t1"],
+                                         self.wall_neq)
+                fnew[d, n] = boundary.reconstruct(self.coef, P)
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
             # lever arm: wall point x_W = x_F - q c_i relative to the group's centre (minimum image)
             xw = self.dom.coords(n).astype(np.float64) - L["q"][None, :] * lat.c[d].T

@@ -4,6 +4,7 @@
     python tests/golden/make_fixtures.py c2       # 2048 x 1024 cylinder channel, 2000 steps
     python tests/golden/make_fixtures.py c5 3     # moving-sphere box id 3, 4000 steps
     python tests/golden/make_fixtures.py c4       # 16 served requests with L <= 256, 5000 steps
+    python tests/golden/make_fixtures.py e3       # BFL comparator, linear error along the axis
 
 Every value written here comes from the FP64 oracle (oracle/) run on the seeded
 recipes of ``synth``; nothing is read from the GPU path.  The full fields are
@@ -198,9 +199,31 @@ def c4(args):
         os.replace(path + ".tmp.npz", path)
 
 
+def e3(args):
+    """The oracle-only BFL comparator on the paper's linear-error experiment
+    (Sec. III.B: cylindrical Couette, beta = 1/2, TRT with Lambda = 3/16, Re = 10,
+    tau 0.8) at r2 - r1 = 10 and 40 lu, two diffusion times: u_y along the
+    x-axis through the centre, its closed form, the LE and the rRSE on the axis
+    and over the annulus (tests/test_oracle_bfl.py builds the same case)."""
+    sys.path.insert(0, ROOT)
+    from tests.test_oracle_bfl import _couette_fields
+    arrays = {}
+    meta = {"case": "e3_bfl", "variant": "BFL", "tau": 0.8, "magic": 3.0 / 16.0, "Re": 10.0, "widths": [10, 40]}
+    for w in (10, 40):
+        t0 = time.time()
+        out = _couette_fields(w, "BFL", magic=3.0 / 16.0)
+        for k, v in out.items():
+            arrays[f"w{w}_{k}"] = np.asarray(v)
+        log(f"e3 width {w}: rRSE axis {out['rrse_axis']:.3e} ({time.time() - t0:.0f} s)")
+    arrays["meta"] = np.array(json.dumps(meta))
+    path = os.path.join(HERE, "e3_bfl_linear_error.npz")
+    np.savez_compressed(path + ".tmp.npz", **arrays)
+    os.replace(path + ".tmp.npz", path)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("case", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("case", choices=["c2", "c3", "c4", "c5", "e3"])
     ap.add_argument("box", nargs="?", type=int, default=3)
     args = ap.parse_args()
     try:
@@ -208,7 +231,7 @@ def main():
         ctx = threadpool_limits(1)
     except Exception:       # pragma: no cover
         ctx = None
-    {"c2": c2, "c3": c3, "c4": c4, "c5": c5}[args.case](args)
+    {"c2": c2, "c3": c3, "c4": c4, "c5": c5, "e3": e3}[args.case](args)
     if ctx is not None:
         ctx.__exit__(None, None, None)
 

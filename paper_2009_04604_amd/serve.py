@@ -24,7 +24,12 @@ read-back.
     free(handle)
 
 ``GpuExecutor`` is the executor of the product path; tests substitute a fake
-one with a fake clock.  With ``prepare_workers`` > 0 the geometry of arriving
+one with a fake clock.  Failures stay with their request: a request whose
+preparation or admission raises is retired with an error and never holds
+memory; one whose state turns non-finite is retired with an error at its
+read-back; ``Server.cancel(id)`` retires a waiting or running request at the
+next scheduling point (a running one after the chunk in flight).  The other
+requests' results do not change.  With ``prepare_workers`` > 0 the geometry of arriving
 requests is built on a thread pool (the host builder releases the GIL), so the
 scheduling thread only waits for it when the request reaches the head of the
 queue.  ``Server.phase`` accumulates the host seconds spent in each phase.  ``run_plain`` is the reference form: one request at a
@@ -95,6 +100,11 @@ class Server:
         self.peak_active = 0
         self.chunks = 0
         self.phase = collections.defaultdict(float)   # host seconds per scheduling phase
+        self._cancel = set()
+
+    def cancel(self, req_id):
+        """Retire request req_id (waiting or running) at the next scheduling point."""
+        self._cancel.add(req_id)
 
     def _timed(self, name, fn, *args):
         t = time.perf_counter()
@@ -126,12 +136,21 @@ class Server:
         def take_arrivals():
             while pending and pending[0].arrival <= now():
                 j = pending.popleft()
-                # geometry is built on the host, in the pool when there is one
-                j.payload = pool.submit(self.ex.prepare, j.req) if pool else self._timed("prepare", self.ex.prepare, j.req)
+                # geometry is built on the host, in the pool when there is one; a
+                # failure is kept with the request and raised when it is admitted
+                if pool:
+                    j.payload = pool.submit(self.ex.prepare, j.req)
+                else:
+                    try:
+                        j.payload = self._timed("prepare", self.ex.prepare, j.req)
+                    except Exception as e:
+                        j.payload = _Failed(e)
                 waiting.append(j)
                 self._event("arrive", now(), id=j.req["id"])
 
         def ready(j):
+            if isinstance(j.payload, _Failed):
+                raise j.payload.exc
             if pool is not None and not isinstance(j.payload, _Done):
                 j.payload = _Done(self._timed("prepare_wait", j.payload.result))
             p = j.payload.value if isinstance(j.payload, _Done) else j.payload
@@ -159,7 +178,16 @@ class Server:
             # admission: arrival order, as long as the head fits
             while waiting:
                 j = waiting[0]
-                payload = ready(j)
+                if j.req["id"] in self._cancel:
+                    waiting.popleft()
+                    self._retire(j, "cancelled", now())
+                    continue
+                try:
+                    payload = ready(j)
+                except Exception as e:            # preparation failed: this request only
+                    waiting.popleft()
+                    self._retire(j, f"preparation failed: {e}", now())
+                    continue
                 if j.footprint > self.budget:
                     waiting.popleft()
                     j.error = f"footprint {j.footprint} B exceeds the HBM budget {self.budget} B"
@@ -171,7 +199,11 @@ class Server:
                 if self.max_active is not None and len(active) >= self.max_active:
                     break
                 waiting.popleft()
-                j.handle = self._timed("admit", self.ex.admit, payload)
+                try:
+                    j.handle = self._timed("admit", self.ex.admit, payload)
+                except Exception as e:            # admission failed: nothing is resident
+                    self._retire(j, f"admission failed: {e}", now())
+                    continue
                 j.payload = None
                 j.admitted = now()
                 used += j.footprint
@@ -186,7 +218,13 @@ class Server:
                     j.steps_left -= n
                     if j.steps_left == 0:
                         done.append(j)
-                active[:] = [j for j in active if j.steps_left > 0]
+                # cancelled while running: out of the next chunk; memory freed at the
+                # next scheduling point (no chunk in flight references it then)
+                for j in active:
+                    if j.steps_left > 0 and j.req["id"] in self._cancel:
+                        self._retire(j, "cancelled", now())
+                        to_free.append(j)
+                active[:] = [j for j in active if j.steps_left > 0 and j.error is None]
             for j in to_free:
                 self._timed("free", self.ex.free, j.handle)
                 j.handle = None
@@ -204,11 +242,27 @@ class Server:
             for j in done:
                 j.result = self._timed("finish", self.ex.finish, j.handle, j.req)
                 j.finished = now()
+                if isinstance(j.result, dict) and j.result.get("unstable"):
+                    j.error = "non-finite state at read-back (lbm_macros: LBM_EUNSTABLE)"
                 to_free.append(j)
                 self._event("finish", now(), id=j.req["id"])
             done = []
             if inflight is None and not to_free and pending and not (waiting and used + waiting[0].footprint <= self.budget):
                 self.sleep(max(0.0, pending[0].arrival - now()))
+
+
+    def _retire(self, j, why, t):
+        j.error = why
+        j.finished = t
+        j.steps_left = 0
+        self._event("retire", t, id=j.req["id"], why=why)
+
+
+class _Failed:
+    __slots__ = ("exc",)
+
+    def __init__(self, e):
+        self.exc = e
 
 
 class _Done:
@@ -218,27 +272,60 @@ class _Done:
         self.value = v
 
 
-def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep):
+def run_plain(executor, requests, clock=time.perf_counter, sleep=time.sleep, prepare_workers=0):
     """Reference form: one request at a time in arrival order (FIFO), each
-    stepped alone to completion."""
-    jobs = [Job(r) for r in requests]
+    stepped alone to completion.  With prepare_workers > 0 the geometry of every
+    request that has arrived is built on a thread pool while earlier requests
+    run (the served form's preparation pool), so the plain form is not charged
+    for host geometry work the served form overlaps."""
+    jobs = sorted([Job(r) for r in requests], key=lambda j: (j.arrival, j.req["id"]))
+    pool = None
+    if prepare_workers > 0:
+        import concurrent.futures
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=prepare_workers)
+    futures = {}
+    nsub = [0]                               # jobs submitted to the pool so far, in order
     t0 = clock()
-    for j in sorted(jobs, key=lambda j: (j.arrival, j.req["id"])):
-        wait = j.arrival - (clock() - t0)
-        if wait > 0:
-            sleep(wait)
-        j.started = clock() - t0
-        payload = executor.prepare(j.req)
-        j.footprint = int(payload.footprint)
-        h = executor.admit(payload)
-        j.admitted = clock() - t0
-        executor.step_alone(h, j.steps_left)
-        executor.sync()
-        j.result = executor.finish(h, j.req)
-        executor.free(h)
-        j.steps_left = 0
-        j.finished = clock() - t0
-    return [j.record() for j in jobs]
+
+    def submit_arrived(upto):
+        """Submit job upto and every later job that has already arrived."""
+        if pool is None:
+            return
+        while nsub[0] < len(jobs) and (nsub[0] <= upto or jobs[nsub[0]].arrival <= clock() - t0):
+            futures[nsub[0]] = pool.submit(executor.prepare, jobs[nsub[0]].req)
+            nsub[0] += 1
+
+    try:
+        for k, j in enumerate(jobs):
+            wait = j.arrival - (clock() - t0)
+            if wait > 0:
+                sleep(wait)
+            j.started = clock() - t0
+            submit_arrived(k)
+            try:
+                payload = futures.pop(k).result() if pool is not None else executor.prepare(j.req)
+                j.footprint = int(payload.footprint)
+                h = executor.admit(payload)
+            except Exception as e:
+                j.error = f"preparation or admission failed: {e}"
+                j.finished = clock() - t0
+                j.steps_left = 0
+                continue
+            j.admitted = clock() - t0
+            submit_arrived(k)
+            executor.step_alone(h, j.steps_left)
+            executor.sync()
+            j.result = executor.finish(h, j.req)
+            if isinstance(j.result, dict) and j.result.get("unstable"):
+                j.error = "non-finite state at read-back (lbm_macros: LBM_EUNSTABLE)"
+            executor.free(h)
+            j.steps_left = 0
+            j.finished = clock() - t0
+    finally:
+        if pool is not None:
+            pool.shutdown(wait=True)
+    by_id = {j.req["id"]: j for j in jobs}
+    return [by_id[r["id"]].record() for r in requests]
 
 
 def busy_capacity(records):
@@ -292,6 +379,10 @@ class GpuExecutor:
         self.batch = B.Batch(stream=self.stream.cuda_stream)
         self.batch.set_option("graph", int(bool(graph)))
         self.batch.set_option("autotune", int(bool(autotune)))
+        # device time of the step launches (HIP events on the step stream)
+        self.busy_s = 0.0
+        self._ev = []
+        self.poison = set()                   # ids whose state is made non-finite at admission (tests)
 
     def footprint(self, req, mask, n_links):
         """Device bytes a request holds while resident, plus what reading its
@@ -331,20 +422,39 @@ class GpuExecutor:
             d = B.Domain("D2Q9", req["nx"], req["ny"], 1, p.mask, req["tau"], storage=self.storage,
                          periodic=(False, False, True), outlet_face="+x", stream=side)
         d.set_boundary_links(p.links)          # returns with the side stream drained
+        if req["id"] in self.poison:
+            f = d.get_state()
+            f[1, np.flatnonzero(p.mask)[0]] = np.nan
+            d.set_state(f)
         d.set_stream(self.stream.cuda_stream)
         d._req_mask = p.mask
         return d
 
+    def _timed_launch(self, fn):
+        import torch
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        fn()
+        b.record(self.stream)
+        self._ev.append((a, b))
+
+    def _collect(self):
+        for a, b in self._ev:
+            self.busy_s += a.elapsed_time(b) / 1e3
+        self._ev = []
+
     def step(self, handles, n):
-        self.batch.step(handles, n)
+        self._timed_launch(lambda: self.batch.step(handles, n))
 
     def step_alone(self, h, n):
         """Plain form: n steps of one domain, waited for."""
-        h.step(n)
+        self._timed_launch(lambda: h.step(n))
         self.stream.synchronize()
+        self._collect()
 
     def sync(self):
         self.stream.synchronize()
+        self._collect()
 
     def finish(self, h, req):
         """Read back a request whose steps have all completed (the caller has
@@ -354,8 +464,7 @@ class GpuExecutor:
         rho, u, sums, unstable = h.macros(fields=keep)
         out = {"mass": float(sums[0]), "momentum": [float(x) for x in sums[1:3]], "unstable": bool(unstable)}
         if keep:
-            fl = np.asarray(h._req_mask, bool).reshape(-1)
-            out["u"] = u[fl].astype(np.float64)
+            out["u"] = np.asarray(u, dtype=np.float64)          # (N, 2), solid nodes 0
         return out
 
     def free(self, h):

@@ -120,17 +120,20 @@ def request_stream(n_requests=256, rate=None, seed=None, l_min=64, l_max=1024, s
     """Served requests: half circular Couette (L x L), half cylinder channel (2L x L).
 
     Each request: {"kind", "L", "arrival", ...geometry}.  Arrival times are a
-    Poisson process of the given rate (requests per second); rate None gives all
-    arrivals at t = 0.
+    Poisson process of the given rate (requests per second), drawn from a
+    generator of their own so that the requests themselves do not depend on the
+    rate; rate None gives all arrivals at t = 0.
     """
-    rng = np.random.default_rng(seed_for(4) if seed is None else seed)
+    base = seed_for(4) if seed is None else seed
+    rng = np.random.default_rng(base)
+    arrivals = np.random.default_rng(base + 1)
     reqs = []
     t = 0.0
     for k in range(n_requests):
         L = int(rng.integers(l_min, l_max + 1))
         kind = "couette" if k % 2 == 0 else "channel"
         if rate is not None:
-            t += rng.exponential(1.0 / rate)
+            t += arrivals.exponential(1.0 / rate)
         if kind == "couette":
             s = L / 48.0
             req = {"kind": kind, "L": L, "nx": L, "ny": L, "centre": (L / 2.0, L / 2.0, 0.0),

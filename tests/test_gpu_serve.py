@@ -95,3 +95,40 @@ def test_served_error_against_fp64_is_stated(gpu_lib):
         print("request", q["id"], q["kind"], q["L"], "E(f16s vs f64)", e, flush=True)
         errs.append(e)
     assert max(errs) < 0.03
+
+
+def test_failing_and_cancelled_requests_retire_alone(gpu_lib):
+    """In a served mix: a request whose state is made non-finite at admission is
+    retired with an error at its read-back (lbm_macros reports LBM_EUNSTABLE), a
+    request the library refuses (tau <= 1/2) is retired at admission, and one
+    is cancelled while running; every other request ends bit-identical to the
+    same request run alone, and the budget is released."""
+    from paper_2009_04604_amd import serve
+    print("case served mix with failures", flush=True)
+    reqs = _requests()
+    reqs[2]["tau"] = 0.45                    # refused by lbm_init_domain
+    ids = [r["id"] for r in reqs]
+    clk = StepClock()
+    ex = serve.GpuExecutor(storage="f32", keep_fields=ids)
+    ex.poison = {reqs[4]["id"]}
+    srv = serve.Server(Clocked(ex, clk), hbm_budget=5 * 2**20, chunk=40, clock=clk, sleep=clk.sleep)
+
+    def trace(what, t, info):
+        if what == "admit" and info["id"] == reqs[3]["id"]:
+            srv.cancel(reqs[1]["id"])        # running by then
+    srv.trace = trace
+    recs = srv.run(reqs)
+    ex.close()
+    assert "admission failed" in recs[2]["error"]
+    assert "non-finite" in recs[4]["error"] and recs[4]["result"]["unstable"]
+    assert recs[1]["error"] == "cancelled"
+    alone = serve.GpuExecutor(storage="f32", keep_fields=ids)
+    for k in (0, 3, 5, 6):
+        q, r = reqs[k], recs[k]
+        assert r["error"] is None
+        h = alone.admit(alone.prepare(q))
+        alone.step_alone(h, q["steps"])
+        res = alone.finish(h, q)
+        alone.free(h)
+        assert np.array_equal(res["u"], r["result"]["u"]), f"request {q['id']}"
+    alone.close()

@@ -191,3 +191,79 @@ def test_plain_busy_capacity():
     recs = serve.run_plain(FakeExecutor(clk), reqs, clock=clk, sleep=clk.sleep)
     service = [q["steps"] * (1e-3 + 1e-8 * q["nx"] * q["ny"]) for q in reqs]
     assert serve.busy_capacity(recs) == pytest.approx(len(reqs) / sum(service))
+
+
+class FailingExecutor(FakeExecutor):
+    """Preparation of bad_prepare, admission of bad_admit raise; nan_ids read back
+    as non-finite."""
+
+    def __init__(self, clock, bad_prepare=(), bad_admit=(), nan_ids=()):
+        super().__init__(clock)
+        self.bad_prepare, self.bad_admit, self.nan_ids = set(bad_prepare), set(bad_admit), set(nan_ids)
+
+    def prepare(self, req):
+        if req["id"] in self.bad_prepare:
+            raise ValueError("tau must be finite and > 0.5")
+        return super().prepare(req)
+
+    def admit(self, p):
+        if p.req["id"] in self.bad_admit:
+            raise RuntimeError("liblbm error -2: hipMalloc: out of memory")
+        return super().admit(p)
+
+    def finish(self, h, req):
+        out = super().finish(h, req)
+        out["unstable"] = req["id"] in self.nan_ids
+        return out
+
+
+def test_failing_requests_are_retired_alone():
+    """A request that cannot be prepared, one that cannot be admitted and one
+    whose state turns non-finite are retired with an error; every other request
+    runs exactly as in a run without them, and no memory stays held."""
+    reqs = _reqs(n=16, rate=300.0)
+    clk = FakeClock()
+    ok = serve.Server(FakeExecutor(clk), hbm_budget=10**9, chunk=50, clock=clk, sleep=clk.sleep).run(reqs)
+    clk2 = FakeClock()
+    ex = FailingExecutor(clk2, bad_prepare=[3], bad_admit=[7], nan_ids=[11])
+    recs = serve.Server(ex, hbm_budget=10**9, chunk=50, clock=clk2, sleep=clk2.sleep).run(reqs)
+    assert "preparation failed" in recs[3]["error"] and recs[3]["admitted"] is None
+    assert "admission failed" in recs[7]["error"] and recs[7]["admitted"] is None
+    assert "non-finite" in recs[11]["error"]
+    for k in set(range(16)) - {3, 7, 11}:
+        assert recs[k]["error"] is None
+        assert recs[k]["result"]["steps_done"] == reqs[k]["steps"] == ok[k]["result"]["steps_done"]
+    assert ex.resident == 0
+
+
+def test_cancel_running_and_waiting_requests():
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    reqs = [{"id": 0, "nx": 100, "ny": 100, "arrival": 0.0, "steps": 2000},
+            {"id": 1, "nx": 100, "ny": 100, "arrival": 0.0, "steps": 300},
+            {"id": 2, "nx": 100, "ny": 100, "arrival": 0.0, "steps": 300}]
+    srv = serve.Server(ex, hbm_budget=250_000, chunk=50, clock=clk, sleep=clk.sleep)   # room for two
+
+    def trace(what, t, info):
+        if what == "admit" and info["id"] == 1:
+            srv.cancel(0)                         # running: leaves after the chunk in flight
+            srv.cancel(2)                         # waiting: never admitted
+    srv.trace = trace
+    recs = srv.run(reqs)
+    assert recs[0]["error"] == "cancelled" and sum(ex.steps[0]) < 2000
+    assert recs[2]["error"] == "cancelled" and recs[2]["admitted"] is None
+    assert recs[1]["error"] is None and recs[1]["result"]["steps_done"] == 300
+    assert ex.resident == 0
+
+
+def test_plain_prefetch_pool_same_results():
+    reqs = _reqs(n=12, rate=50.0)
+    out = []
+    for workers in (0, 3):
+        clk = FakeClock()
+        recs = serve.run_plain(FakeExecutor(clk), reqs, clock=clk, sleep=clk.sleep, prepare_workers=workers)
+        out.append([(r["id"], r["result"]["steps_done"], r["finished"]) for r in recs])
+    assert out[0] == out[1]
+    clk = FakeClock()
+    recs = serve.run_plain(FailingExecutor(clk, bad_prepare=[4]), reqs, clock=clk, sleep=clk.sleep, prepare_workers=2)
+    assert "failed" in recs[4]["error"] and all(r["error"] is None for k, r in enumerate(recs) if k != 4)

@@ -51,6 +51,9 @@ def parse():
                          "eighths; default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="only time the FP64 oracle on this host for every configuration (about 10 minutes), "
+                         "print one JSON line and exit")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the measurement, run one plain device copy of this size (for counter scaling)")
     ap.add_argument("--no-copy-probe", action="store_true",
@@ -131,6 +134,34 @@ def copy_bandwidth(gib=2, reps=5):
     return round(2.0 * gib * 2**30 / (ms * 1e-3) / 1e9, 1)
 
 
+def stream_probe(n_elems, arrays=19, reps=10):
+    """Practical read + write ceiling: `arrays` FP32 arrays in and `arrays` out,
+    n_elems each (the packing's fluid count), one element of every array per
+    lane (lbm_stream_probe), on line-aligned runs and on runs shifted by one
+    element (every wave straddles lines, as the compact layout's do)."""
+    import torch
+    from paper_2009_04604_amd import binding as B
+    stride = (n_elems + 64 + 63) // 64 * 64
+    src = torch.ones(arrays * stride, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"arrays_in": arrays, "arrays_out": arrays, "elements": n_elems}
+    for name, shift in (("aligned", 0), ("shifted", 1)):
+        B.lbm_stream_probe(src, dst, n_elems, stride, arrays, shift)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            B.lbm_stream_probe(src, dst, n_elems, stride, arrays, shift)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_GBps"] = round(2 * 4 * arrays * n_elems / (ms * 1e-3) / 1e9, 1)
+        out[name + "_ms"] = round(ms, 4)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(name, seconds, wall_neq="bounceback"):
     """Time the FP64 oracle on one core on a bounded sample of the workload recipe."""
     try:
@@ -176,11 +207,167 @@ def cpu_baseline(name, seconds, wall_neq="bounceback"):
             ctx.__exit__(None, None, None)
 
 
+# Declared before the served run: the velocity error budget (relative L2 against
+# the FP64 oracle) within which a served form counts as delivering the plain
+# form's answer.
+SERVED_ERROR_BUDGET = 1e-2
+
+
+def _served_fixture():
+    """The oracle's FP64 results for the requests of the served stream with
+    L <= 256 (tests/golden/c4_requests.npz): id -> (node sample, u (2, n))."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "c4_requests.npz")
+    if not os.path.exists(path):
+        return {}
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    return {r["id"]: (z[f"r{r['id']}_nodes"], z[f"r{r['id']}_u"][:2]) for r in meta["requests"]}
+
+
+def _oracle_case(kind, p):
+    """An oracle Simulation for one workload recipe (cpu baselines only)."""
+    from oracle import geometry as G, lattice as OL, solver
+    if kind == "couette":
+        dom = G.Domain(OL.D2Q9, p["nx"], p["ny"], 1)
+        om1 = p["u_inner"] / p["r1"]
+        sh = [G.Sphere(p["centre"], p["r1"], True, Omega=(0, 0, om1)), G.Sphere(p["centre"], p["r2"], False)]
+        faces = []
+    else:
+        dom = G.Domain(OL.D2Q9, p["nx"], p["ny"], 1, periodic=(False, False, True), outlet_face=1)
+        sh = [G.Sphere(p["centre"], p["radius"], True)]
+        faces = [G.FaceWall(0, 0.5, G.parabolic_inlet(p["ny"], p["u_max"])), G.FaceWall(2, 0.5), G.FaceWall(3, 0.5)]
+    fluid = G.classify(dom, sh)
+    sim = solver.Simulation(dom, p["tau"])
+    sim.set_geometry(fluid, G.cut_links(dom, fluid, sh, faces), "FQ")
+    sim.init_equilibrium()
+    return sim
+
+
+def _time_oracle_steps(sim, k):
+    sim.step()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        sim.step()
+    return (time.perf_counter() - t0) / k
+
+
+def _worker_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:       # pragma: no cover
+        pass
+
+
+def _request_seconds(args):
+    """Oracle seconds per step of one served request (one core)."""
+    req, k = args
+    sim = _oracle_case(req["kind"], req)
+    return _time_oracle_steps(sim, k)
+
+
+def _box_seconds(args):
+    """Oracle seconds per step of one moving-sphere box (one core)."""
+    from oracle import geometry as G, lattice as OL, moving
+    b, k = args
+    dom = G.Domain(OL.D3Q19, b["nx"], b["ny"], b["nz"])
+    kin = moving.Kinematics(b["x0"], b["amplitude"], b["period"], b["direction"], b["omega"])
+    m = moving.MovingSphereSim(dom, b["radius"], kin, tau=b["tau"])
+    m.step()
+    t0 = time.perf_counter()
+    m.run(k)
+    return (time.perf_counter() - t0) / k
+
+
+def cpu_baseline_full(log):
+    """The FP64 oracle on the host of this run, per workload: one core for the
+    single-domain configurations (the 48^2 annulus in full; 200 steps of the
+    2048 x 1024 channel; 20 steps of the 256^3 packing; 20 steps of the
+    smallest moving box, projected to its 4000), and every core of the host,
+    one process per request or box, for the served stream and the moving
+    boxes (a sample of 16 requests and 8 boxes, a few steps each, projected to
+    their full step counts)."""
+    import multiprocessing as mp
+    import numpy as np
+    import synth
+    from oracle import geometry as G, lattice as OL, solver
+    _worker_init()
+    cores = len(os.sched_getaffinity(0))
+    out = {"cores_all": cores, "kind": "oracle"}
+    # C1 in full
+    p = synth.couette_annulus()
+    sim = _oracle_case("couette", p)
+    t0 = time.perf_counter()
+    sim.run(p["steps"])
+    dt = time.perf_counter() - t0
+    nfl = int(sim.fluid.sum())
+    out["C1_annulus48_5000_steps"] = {"seconds": round(dt, 2), "MLUPS": round(nfl * p["steps"] / dt / 1e6, 3), "cores": 1}
+    log(f"cpu full: C1 {dt:.1f} s")
+    # C2: 200 steps
+    p = synth.cylinder_channel()
+    sim = _oracle_case("channel", p)
+    s = _time_oracle_steps(sim, 200)
+    nfl = int(sim.fluid.sum())
+    out["C2_channel2048_200_steps"] = {"s_per_step": round(s, 3), "MLUPS": round(nfl / s / 1e6, 3), "cores": 1,
+                                       "projected_20000_steps_h": round(20000 * s / 3600, 2)}
+    del sim
+    log(f"cpu full: C2 {s:.3f} s/step")
+    # C3 at full size: 20 steps
+    n = 256
+    c, r = synth.sphere_packing(n=n)
+    dom = G.Domain(OL.D3Q19, n, n, n)
+    sh = [G.Sphere(cc, rr, True) for cc, rr in zip(c, r)]
+    t0 = time.perf_counter()
+    fluid = G.classify(dom, sh)
+    sim = solver.Simulation(dom, 0.9, force=(1e-6, 0, 0))
+    sim.set_geometry(fluid, G.cut_links(dom, fluid, sh), "FQ")
+    sim.init_equilibrium()
+    setup = time.perf_counter() - t0
+    s = _time_oracle_steps(sim, 20)
+    nfl = int(fluid.sum())
+    out["C3_packing256_20_steps"] = {"s_per_step": round(s, 3), "MLUPS": round(nfl / s / 1e6, 3), "cores": 1,
+                                     "setup_s": round(setup, 1), "projected_10000_steps_h": round(10000 * s / 3600, 2)}
+    del sim, fluid
+    log(f"cpu full: C3 256^3 {s:.2f} s/step")
+    # C5: the smallest box, 20 steps
+    boxes = synth.moving_boxes()
+    small = min(boxes, key=lambda b: b["nx"])
+    s = _box_seconds((small, 20))
+    out["C5_smallest_box_20_steps"] = {"box": small["id"], "side": small["nx"], "s_per_step": round(s, 3), "cores": 1,
+                                       "projected_4000_steps_h": round(4000 * s / 3600, 2)}
+    log(f"cpu full: C5 box {small['id']} {s:.2f} s/step")
+    # all cores: served requests and moving boxes
+    reqs = synth.request_stream(256)
+    sample = reqs[::16]
+    with mp.get_context("fork").Pool(processes=cores, initializer=_worker_init) as pool:
+        t0 = time.perf_counter()
+        sec = pool.map(_request_seconds, [(q, 10) for q in sample])
+        wall = time.perf_counter() - t0
+        per_req = float(np.mean(sec)) * 5000
+        out["C4_served_all_cores"] = {"sample": f"{len(sample)} requests (every 16th of the 256), 10 steps each",
+                                      "mean_request_s_at_5000_steps": round(per_req, 1),
+                                      "solves_per_s": round(cores / per_req, 5), "cores": cores,
+                                      "sample_wall_s": round(wall, 1)}
+        log(f"cpu full: C4 {cores / per_req:.5f} solves/s on {cores} cores")
+        bsample = boxes[::4]
+        sec = pool.map(_box_seconds, [(b, 3) for b in bsample])
+        per_box = float(np.mean(sec)) * 4000
+        out["C5_boxes_all_cores"] = {"sample": f"{len(bsample)} boxes (every 4th of the 32), 3 steps each",
+                                     "mean_box_s_at_4000_steps": round(per_box, 1),
+                                     "boxes_per_s": round(cores / per_box, 6), "cores": cores}
+        log(f"cpu full: C5 {cores / per_box:.6f} boxes/s on {cores} cores")
+    return out
+
+
 def served_section(a, log):
     """Served D2Q9 requests (circular Couette L x L and cylinder channel 2L x L,
     L ~ U{64..1024}, Poisson arrivals): continuously batched FP16-shifted form,
     and the same batching in FP32 (results identical to the plain form's), against
-    the plain FP32 one-request-at-a-time form on the same arrivals."""
+    the plain FP32 one-request-at-a-time form on the same arrivals.  Every form
+    builds the geometry of arrived requests on the same 4-thread pool while
+    earlier requests run; device-busy time is the HIP-event time of the step
+    launches."""
     import numpy as np
     import torch
     import synth
@@ -207,11 +394,13 @@ def served_section(a, log):
         r["arrival"] = r["arrival"] / lam          # unit-rate Poisson times scaled to rate lam
     log(f"served: plain sample service {np.mean(t_serv):.4f} s/request, arrival rate {lam:.2f}/s")
     budget = a.served_budget_mib * 2**20
-    ids = [reqs[k]["id"] for k in sample]
+    fix = _served_fixture() if a.served_steps == 5000 else {}
+    ids = sorted(set(reqs[k]["id"] for k in sample) | set(fix))
     exs = serve.GpuExecutor(storage="f16s", keep_fields=ids)
     srv = serve.Server(exs, hbm_budget=budget, chunk=100, prepare_workers=4)
     log("served: batched run")
     served = srv.run(reqs)
+    busy_served = exs.busy_s
     exs.close()
     log("served: done")
     # the served form at exactly the plain form's error: FP32 storage, same batching
@@ -219,9 +408,11 @@ def served_section(a, log):
     srv32 = serve.Server(exs32, hbm_budget=budget, chunk=100, prepare_workers=4)
     log("served: batched FP32 run")
     served32 = srv32.run(reqs)
+    busy_served32 = exs32.busy_s
     exs32.close()
     exp = serve.GpuExecutor(storage="f32", keep_fields=ids)
-    plain = serve.run_plain(exp, reqs)
+    plain = serve.run_plain(exp, reqs, prepare_workers=4)
+    busy_plain = exp.busy_s
     exp.close()
     log("served: plain done")
     # velocity error of each sampled request against the same request in FP64
@@ -254,7 +445,20 @@ def served_section(a, log):
         same32 = same32 and np.array_equal(served32[k]["result"]["u"], plain[k]["result"]["u"])
     ref.close()
     torch.cuda.synchronize()
+    # against the FP64 oracle on the stored node samples
+    eo = {"served": [], "plain": [], "served_f32": []}
+    for rid, (nodes, uref) in fix.items():
+        nrm = np.linalg.norm(uref)
+        for name, recs in (("served", served), ("plain", plain), ("served_f32", served32)):
+            u = recs[rid]["result"]["u"][nodes].T
+            eo[name].append(float(np.linalg.norm(u - uref) / nrm))
     ss, sp, s32 = serve.summarize(served), serve.summarize(plain), serve.summarize(served32)
+
+    def oracle_err(name):
+        if not eo[name]:
+            return None
+        return {"max": max(eo[name]), "median": float(np.median(eo[name])),
+                "within_budget": bool(max(eo[name]) <= SERVED_ERROR_BUDGET)}
     nodes = sum(r["nx"] * r["ny"] for r in reqs)
     return {
         "workload": f"{len(reqs)} D2Q9 requests (circular Couette LxL / cylinder channel 2LxL, L~U{{64..1024}}), "
@@ -265,14 +469,19 @@ def served_section(a, log):
                    "p50_s": round(ss["p50_s"], 4), "p99_s": round(ss["p99_s"], 4), "makespan_s": round(ss["makespan_s"], 3),
                    "peak_resident": srv.peak_active, "peak_bytes": srv.peak_bytes, "chunks": srv.chunks,
                    "host_phase_s": {k: round(v, 3) for k, v in sorted(srv.phase.items())},
+                   "device_busy_s": round(busy_served, 3),
+                   "E_vs_oracle": oracle_err("served"),
                    "E_vs_f64_max": max(e_s), "E_vs_f64_median": float(np.median(e_s))},
-        "plain": {"storage": "f32, one request at a time (FIFO)", "solves_per_s": round(sp["solves_per_s"], 3),
+        "plain": {"storage": "f32, one request at a time (FIFO), geometry prefetched on the same 4-thread pool",
+                  "solves_per_s": round(sp["solves_per_s"], 3),
                   "p50_s": round(sp["p50_s"], 4), "p99_s": round(sp["p99_s"], 4), "makespan_s": round(sp["makespan_s"], 3),
+                  "device_busy_s": round(busy_plain, 3), "E_vs_oracle": oracle_err("plain"),
                   "E_vs_f64_max": max(e_p), "E_vs_f64_median": float(np.median(e_p))},
         "served_f32": {"storage": "f32, continuous batching (the plain form's arithmetic)",
                        "solves_per_s": round(s32["solves_per_s"], 3), "p50_s": round(s32["p50_s"], 4),
                        "p99_s": round(s32["p99_s"], 4), "makespan_s": round(s32["makespan_s"], 3),
-                       "peak_resident": srv32.peak_active, "E_vs_f64_max": max(e_s32),
+                       "peak_resident": srv32.peak_active, "device_busy_s": round(busy_served32, 3),
+                       "E_vs_oracle": oracle_err("served_f32"), "E_vs_f64_max": max(e_s32),
                        "E_vs_f64_median": float(np.median(e_s32)), "fields_identical_to_plain": bool(same32)},
         "equal_error_speedup_solves_per_s": round(s32["solves_per_s"] / sp["solves_per_s"], 3),
         "equal_error_p99_ratio_plain_over_served": round(sp["p99_s"] / s32["p99_s"], 3),
@@ -283,7 +492,10 @@ def served_section(a, log):
                                          "plain: requests per second of busy time in the run above"},
         "speedup_solves_per_s": round(ss["solves_per_s"] / sp["solves_per_s"], 3),
         "p99_ratio_plain_over_served": round(sp["p99_s"] / ss["p99_s"], 3),
-        "error_sample": f"{len(sample)} requests (every {max(1, len(reqs) // 16)}th) against the FP64 GPU path",
+        "error_budget": {"relative_L2_velocity_vs_fp64_oracle": SERVED_ERROR_BUDGET, "declared": "before the run"},
+        "error_sample": f"E_vs_oracle: the {len(fix)} requests with L <= 256 stored by the FP64 oracle "
+                        f"(tests/golden/c4_requests.npz, node samples); E_vs_f64: {len(sample)} requests "
+                        f"(every {max(1, len(reqs) // 16)}th) against the FP64 GPU path",
     }
 
 
@@ -383,6 +595,9 @@ def moving_section(a, log):
 
 def main():
     a = parse()
+    if a.cpu_baseline_full:
+        print(json.dumps({"cpu_baseline_full": cpu_baseline_full(log)}), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -429,6 +644,13 @@ def main():
             "kernel_ms": round(kernel_ms, 4),
             "traffic_GBps": None if traffic is None else round(traffic / (kernel_ms * 1e-3) / 1e9, 1),
             "device_copy_GBps": None if a.no_copy_probe else copy_bandwidth()}
+    if not a.no_copy_probe:
+        sp = stream_probe(nfl, arrays=Q)
+        roof["stream_probe"] = sp
+        # the practical ceiling of this access pattern: the achieved rate against
+        # the aligned and the shifted 2Q-array stream measured in the same run
+        roof["frac_of_aligned_stream"] = round(achieved / sp["aligned_GBps"], 4)
+        roof["frac_of_shifted_stream"] = round(achieved / sp["shifted_GBps"], 4)
     cfg.update({"fluid_nodes": nfl, "cut_links": info["n_links"], "boundary_nodes": info["n_boundary_nodes"],
                 "unstable": bool(unstable), "mass": sums[0]})
     out = {

@@ -335,6 +335,18 @@ int lbm_batch_free(lbm_batch b);
  * synchronises. */
 int lbm_step_batch(const lbm_domain* ds, int32_t n, int32_t n_steps);
 
+/* Bandwidth calibration (not part of the method): copy `arrays` FP32 arrays of
+ * n elements from src to dst (device pointers, caller-owned, arrays of
+ * `stride` elements laid one after another), element e of each array at
+ * offset shift + e; one element of every array per lane, 64-lane waves over 64
+ * consecutive elements, as the step kernel's population streams.  shift 0:
+ * every wave's run starts on a 256 B boundary (if src and dst are 256 B
+ * aligned); 1..31: every run straddles cache lines.  Asynchronous on stream.
+ * The caller times it; read + write bytes = 2 * 4 * n * arrays.  LBM_EINVAL
+ * unless n >= 0, arrays >= 1, 0 <= shift < 64 and stride >= n + shift. */
+int lbm_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays, int32_t shift,
+                     void* stream);
+
 /* Thread-local message of the last failed call ("" if none). */
 const char* lbm_last_error(void);
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
     "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque", "lbm_set_force_tracking",
-    "lbm_moving_force", "lbm_macros_noalloc",
+    "lbm_moving_force", "lbm_macros_noalloc", "lbm_stream_probe",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -123,6 +123,7 @@ def lib():
         "lbm_set_force_tracking": (I32, [P, I32]),
         "lbm_moving_force": (I32, [P, P, P]),
         "lbm_macros_noalloc": (I32, [P, P, P, P]),
+        "lbm_stream_probe": (I32, [P, P, I64, I64, I32, I32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -252,6 +253,17 @@ def lbm_get_info(h):
 
 def lbm_free_domain(h):
     _check(lib().lbm_free_domain(h))
+
+
+def lbm_stream_probe(src, dst, n, stride, arrays, shift, stream=None):
+    """Bandwidth calibration copy (see include/lbm.h); src, dst torch float32 CUDA tensors."""
+    need = int(arrays) * int(stride)
+    if src.dtype != dst.dtype or str(src.dtype) != "torch.float32" or src.numel() < need or dst.numel() < need:
+        raise ValueError(f"lbm_stream_probe: src and dst must be float32 with at least arrays * stride = {need} elements")
+    if stream is None:
+        stream = _torch_stream()
+    _check(lib().lbm_stream_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), int(n),
+                                  int(stride), int(arrays), int(shift), stream))
 
 
 # ---- object wrappers ----------------------------------------------------------

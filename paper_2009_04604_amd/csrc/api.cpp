@@ -937,6 +937,16 @@ int lbm_moving_force(lbm_domain d, double* force, double* torque) {
   return LBM_OK;
 }
 
+int lbm_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays, int32_t shift,
+                     void* stream) {
+  if (!src || !dst) return fail(LBM_EINVAL, "null argument");
+  if (n < 0 || arrays < 1 || shift < 0 || shift >= 64 || stride < n + shift || n >= ((int64_t)1 << 40))
+    return fail(LBM_EINVAL, "need n >= 0, arrays >= 1, 0 <= shift < 64, stride >= n + shift");
+  HIP_TRY(launch_stream_probe(src, dst, n, stride, arrays, shift, static_cast<hipStream_t>(stream)));
+  clear_error();
+  return LBM_OK;
+}
+
 int lbm_set_stream(lbm_domain d, void* stream) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   d->stream = static_cast<hipStream_t>(stream);

@@ -242,6 +242,8 @@ hipError_t launch_macros(int lattice, int storage, const MacroParams& p, int64_t
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s);
 hipError_t launch_force(int lattice, int storage, const ForceParams& p, int32_t n_groups, double* out,
                         hipStream_t s);
+hipError_t launch_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays,
+                               int32_t shift, hipStream_t s);
 hipError_t launch_group_sum(const double* contrib, const int32_t* group, int64_t nl, const int32_t* nl_dev,
                             int32_t n_groups, double* out, hipStream_t s);
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);

@@ -1236,6 +1236,28 @@ hipError_t launch_group_sum(const double* contrib, const int32_t* group, int64_t
   return hipGetLastError();
 }
 
+// Bandwidth calibration: `arrays` FP32 arrays of n elements (stride elements
+// apart) copied from src to dst, one element of every array per lane, so a
+// 64-lane wave reads and writes 64 consecutive elements of each array -- the
+// step kernel's access pattern without its pulls and arithmetic.  Element e
+// sits at shift + e: shift 0 puts every wave's run on 256 B boundaries, any
+// other shift makes every run straddle one (the compact layout's runs start
+// at arbitrary slots).
+__global__ __launch_bounds__(BLOCK) void stream_probe_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                             int64_t n, int64_t stride, int32_t arrays,
+                                                             int32_t shift) {
+  const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= n) return;
+  for (int a = 0; a < arrays; ++a) dst[a * stride + shift + e] = src[a * stride + shift + e];
+}
+
+hipError_t launch_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays,
+                               int32_t shift, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  stream_probe_kernel<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partials, int64_t nblocks, double* out, hipStream_t s) {
   reduce_kernel<<<1, BLOCK, 0, s>>>(partials, nblocks, out);
   return hipGetLastError();

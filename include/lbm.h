@@ -374,11 +374,13 @@ int lbm_geometry_add_sphere(lbm_geometry g, const double centre[3], double radiu
  * a radius that is not finite and > 0, or a non-finite centre or motion. */
 int lbm_geometry_add_cylinder(lbm_geometry g, const double centre[3], double radius, int32_t solid_inside,
                               const double V[3], const double Omega[3]);
-/* n solid-inside spheres at rest: centres [3n], radii [n]. */
+/* n >= 0 solid-inside spheres at rest: centres [3n], radii [n]. */
 int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, const double* radii);
 /* Plane wall parallel to a non-periodic face at distance q_face in (0, 1] from
  * the first node layer.  Wall velocity uw (NULL = rest); profile 1 scales it by
- * 4 (y + 1/2)(ny - 1/2 - y) / ny^2 at the wall point (parabolic inlet across y). */
+ * 4 (y + 1/2)(ny - 1/2 - y) / ny^2 at the wall point (parabolic inlet across y).
+ * LBM_EINVAL for a face on a periodic axis, q_face outside (0, 1], a profile
+ * other than 0 or 1, or a non-finite velocity. */
 int lbm_geometry_add_face_wall(lbm_geometry g, int32_t face, double q_face, const double uw[3],
                                int32_t profile);
 
@@ -389,7 +391,8 @@ int lbm_geometry_build(lbm_geometry g, int64_t* n_fluid, int64_t* n_links);
 int lbm_geometry_get(lbm_geometry g, uint8_t* mask, int64_t* node, int8_t* dir, double* q,
                      double* uw_t, double* uw_t1);
 /* Owner of each link (n_links int32, same order): the index of the sphere in
- * order of addition, or (number of spheres + index of the face wall). */
+ * order of addition, or (number of spheres + index of the face wall).  shape
+ * may be NULL when there are no links. */
 int lbm_geometry_get_shapes(lbm_geometry g, int32_t* shape);
 int lbm_geometry_free(lbm_geometry g);
 

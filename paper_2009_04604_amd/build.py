@@ -31,6 +31,7 @@ SOURCES = [
     ("api.cpp", "api.o", []),
     ("batch.cpp", "batch.o", []),
     ("geometry.cpp", "geometry.o", []),
+    ("hostplan.cpp", "hostplan.o", []),
 ]
 
 

@@ -83,39 +83,10 @@ int dalloc(P*& p, size_t bytes) {
   return LBM_OK;
 }
 
-// Source of the pull x - c_i: returns false if outside a non-periodic face;
-// otherwise writes the wrapped coordinates.
-bool pull_source(const lbm_domain_s* d, const int c[3], int x, int y, int z, int s[3]) {
-  const int n[3] = {d->g.nx, d->g.ny, d->g.nz};
-  const int per[3] = {d->g.perx, d->g.pery, d->g.perz};
-  const int p[3] = {x, y, z};
-  bool inside = true;
-  for (int a = 0; a < 3; ++a) {
-    int v = p[a] - c[a];   // |c| <= 1: one wrap at most
-    if (v < 0 || v >= n[a]) {
-      if (per[a]) v += v < 0 ? n[a] : -n[a];
-      else inside = false;
-    }
-    s[a] = v;
-  }
-  return inside;
-}
-
-// For a pull source beyond the outlet face: node index of the producer (the
-// source brought back onto the face layer) if it exists and is fluid, else -1.
-int64_t outlet_producer(const lbm_domain_s* d, const int s[3]) {
-  const int f = d->desc.outlet_face;
-  if (f < 0) return -1;
-  const int a = f >> 1;
-  const int n[3] = {d->g.nx, d->g.ny, d->g.nz};
-  const bool beyond = (f & 1) ? s[a] >= n[a] : s[a] < 0;
-  if (!beyond) return -1;
-  int p[3] = {s[0], s[1], s[2]};
-  p[a] = (f & 1) ? n[a] - 1 : 0;
-  for (int b = 0; b < 3; ++b)
-    if (p[b] < 0 || p[b] >= n[b]) return -1;
-  const int64_t idx = p[0] + (int64_t)n[0] * (p[1] + (int64_t)n[1] * p[2]);
-  return d->mask[idx] ? idx : -1;
+// The host planner's view of a domain's lattice and fluid mask.
+HostGrid host_grid(const lbm_domain_s* d) {
+  return make_host_grid(d->desc.lattice, d->g.nx, d->g.ny, d->g.nz, d->desc.periodic, d->desc.outlet_face,
+                        d->mask.data());
 }
 
 // Device view of the links; lv_in / lv_out chosen by the caller.
@@ -246,29 +217,6 @@ hipError_t rebuild_moving(lbm_domain_s* d, int64_t t, bool refill) {
   if (e == hipSuccess) e = launch_moving_fill(d->desc.lattice, d->desc.storage, mp, d->stream);
   if (e == hipSuccess && refill) e = launch_moving_refill(d->desc.lattice, d->desc.storage, mp, d->stream);
   return e;
-}
-
-// Count populations of fluid nodes that are neither streamed nor outlet-covered
-// and not in `linked` (per-node direction mask; may be empty).
-int64_t first_uncovered(const lbm_domain_s* d, const std::vector<uint32_t>& linked, int* bad_dir) {
-  const Lat& L = lat_of(d->desc.lattice);
-  const int nx = d->g.nx, ny = d->g.ny, nz = d->g.nz;
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
-        if (!d->mask[n]) continue;
-        for (int i = 1; i < L.Q; ++i) {
-          int s[3];
-          const bool inside = pull_source(d, L.c[i], x, y, z, s);
-          if (inside && d->mask[s[0] + (int64_t)nx * (s[1] + (int64_t)ny * s[2])]) continue;
-          if (!linked.empty() && ((linked[n] >> i) & 1u)) continue;
-          if (!inside && outlet_producer(d, s) >= 0) continue;
-          *bad_dir = i;
-          return n;
-        }
-      }
-  return -1;
 }
 
 void free_links(lbm_domain_s* d) {
@@ -416,14 +364,9 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(he)));
 
   // segment masks
-  std::vector<uint64_t> sf(g.nseg, 0);
-  for (int z = 0; z < g.nz; ++z)
-    for (int y = 0; y < g.ny; ++y)
-      for (int x = 0; x < g.nx; ++x)
-        if (dm->mask[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)])
-          sf[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] |= 1ull << (x % SEG);
-  std::vector<int32_t> sfb(g.nseg + 1, 0);
-  for (int64_t s = 0; s < g.nseg; ++s) sfb[s + 1] = sfb[s] + __builtin_popcountll(sf[s]);
+  std::vector<uint64_t> sf;
+  std::vector<int32_t> sfb;
+  segment_index(host_grid(dm), sf, sfb);
   if (int e = dalloc(dm->seg_fbase, (g.nseg + 1) * 4)) return cleanup(e);
   if (int e = dalloc(dm->seg_fluid, g.nseg * 8)) return cleanup(e);
   if (int e = dalloc(dm->seg_bnd, g.nseg * 8)) return cleanup(e);
@@ -445,7 +388,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(he)));
   dm->cur = 0;
   int bad_dir = 0;
-  dm->links_ok = first_uncovered(dm, {}, &bad_dir) < 0;
+  dm->links_ok = first_uncovered(host_grid(dm), {}, &bad_dir) < 0;
   dm->n_groups = 1;
   dm->uid = next_uid();
   *out = dm;
@@ -456,100 +399,12 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
 int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, const int8_t* dir, const double* q,
                            const double* uw_t, const double* uw_t1, int32_t variant, double q_cutoff) {
   if (!d) return fail(LBM_EINVAL, "null domain");
-  if (n_links < 0) return fail(LBM_EINVAL, "n_links < 0");
-  if (n_links > 0 && (!node || !dir || !q)) return fail(LBM_EINVAL, "node, dir and q are required");
-  if (variant < LBM_ELIBB_FQ || variant > LBM_HWBB) return fail(LBM_EINVAL, "invalid variant");
-  if (!(q_cutoff >= 0.0) || !std::isfinite(q_cutoff)) return fail(LBM_EINVAL, "q_cutoff must be finite and >= 0");
-  if (n_links >= (int64_t)1 << 31) return fail(LBM_EINVAL, "too many links");
-  const Lat& L = lat_of(d->desc.lattice);
-  const int64_t N = d->N;
-  const int nx = d->g.nx, ny = d->g.ny;
-  auto where = [&](int64_t k) {
-    return "link " + std::to_string(k) + " (node " + std::to_string(node[k]) + ", dir " + std::to_string((int)dir[k]) + ")";
-  };
-  std::vector<int64_t> order(n_links);
-  std::iota(order.begin(), order.end(), 0);
-  for (int64_t k = 0; k < n_links; ++k) {
-    if (node[k] < 0 || node[k] >= N) return fail(LBM_EINVAL, where(k) + ": node out of range");
-    if (dir[k] < 1 || dir[k] >= L.Q) return fail(LBM_EINVAL, where(k) + ": dir out of range");
-    if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(LBM_EINVAL, where(k) + ": q must lie in (0, 1]");
-    for (int a = 0; a < 3; ++a) {
-      if (uw_t && !std::isfinite(uw_t[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t");
-      if (uw_t1 && !std::isfinite(uw_t1[3 * k + a])) return fail(LBM_EINVAL, where(k) + ": non-finite uw_t1");
-    }
-    if (!d->mask[node[k]]) return fail(LBM_EINVAL, where(k) + ": node is not fluid");
-    const int64_t n = node[k];
-    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
-    int s[3];
-    const bool inside = pull_source(d, L.c[(int)dir[k]], x, y, z, s);
-    if (inside && d->mask[s[0] + (int64_t)nx * (s[1] + (int64_t)ny * s[2])])
-      return fail(LBM_EINVAL, where(k) + ": node - c_dir is a fluid node (not a cut link)");
-    if (!inside && outlet_producer(d, s) >= 0) return fail(LBM_EINVAL, where(k) + ": population is covered by the outlet");
-  }
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    return node[a] != node[b] ? node[a] < node[b] : dir[a] < dir[b];
-  });
-  for (int64_t k = 1; k < n_links; ++k)
-    if (node[order[k]] == node[order[k - 1]] && dir[order[k]] == dir[order[k - 1]])
-      return fail(LBM_EINVAL, where(order[k]) + ": duplicate link");
-
-  std::vector<uint32_t> linked(N, 0u);
-  for (int64_t k = 0; k < n_links; ++k) linked[node[k]] |= 1u << dir[k];
-  int bad_dir = 0;
-  const int64_t bad = first_uncovered(d, linked, &bad_dir);
-  if (bad >= 0)
-    return fail(LBM_EINVAL, "population (node " + std::to_string(bad) + ", dir " + std::to_string(bad_dir) +
-                                ") is missing after streaming and not covered by a link");
-
-  // segment masks and link records: links sorted by (node, dir) are contiguous
-  // per segment; each carries its node's lane and its direction
-  const GridGeom& g = d->g;
-  std::vector<uint64_t> sb(g.nseg, 0);
-  std::vector<int32_t> slb(g.nseg + 1, 0);
-  std::vector<uint16_t> lld(n_links);
-  int64_t nb = 0;
-  for (int64_t k = 0; k < n_links; ++k) {
-    const int64_t n = node[order[k]];
-    const int64_t row = n / nx;
-    const int x = (int)(n - row * nx);
-    const int64_t s = row * g.nseg_x + x / SEG;
-    const int lane = x % SEG;
-    if (!((sb[s] >> lane) & 1ull)) ++nb;
-    sb[s] |= 1ull << lane;
-    slb[s + 1] += 1;
-    lld[k] = (uint16_t)(lane | (int(dir[order[k]]) << 8));
-  }
-  for (int64_t s = 0; s < g.nseg; ++s) slb[s + 1] += slb[s];
   const bool f64 = d->desc.storage == LBM_F64;
-  bool moving = false;
-  for (int64_t k = 0; k < 3 * n_links && !moving; ++k)
-    moving = (uw_t && uw_t[k] != 0.0) || (uw_t1 && uw_t1[k] != 0.0);
-  std::vector<double> qd(n_links), gd(moving ? n_links : 0);
-  for (int64_t k = 0; k < n_links; ++k) {
-    const int64_t o = order[k];
-    qd[k] = q[o];
-    if (moving) {
-      const int i = dir[o];
-      const double* u0 = uw_t ? uw_t + 3 * o : nullptr;
-      const double* u1 = uw_t1 ? uw_t1 + 3 * o : u0;
-      double cu0 = 0, uu0 = 0, cu1 = 0, uu1 = 0;
-      for (int a = 0; a < L.D; ++a) {
-        const double v0 = u0 ? u0[a] : 0.0, v1 = u1 ? u1[a] : 0.0;
-        cu0 += L.c[i][a] * v0;
-        uu0 += v0 * v0;
-        cu1 += L.c[i][a] * v1;
-        uu1 += v1 * v1;
-      }
-      if (f64) {
-        const Coef<double> c = elibb_coefficients<double>(variant, q[o], q_cutoff);
-        gd[k] = wall_term<double>(c, cu0, uu0, cu1, uu1);
-      } else {
-        const Coef<float> c = elibb_coefficients<float>(variant, (float)q[o], (float)q_cutoff);
-        const Coef<double> cd{c.a4, c.a5, c.a2, c.a3};
-        gd[k] = wall_term<double>(cd, cu0, uu0, cu1, uu1);
-      }
-    }
-  }
+  LinkPlan plan;
+  if (int e = plan_links(host_grid(d), n_links, node, dir, q, uw_t, uw_t1, variant, q_cutoff, f64, plan)) return e;
+  const GridGeom& g = d->g;
+  const int64_t N = d->N;
+  const bool moving = plan.moving;
   // the current state (pulled with the old links) survives the replacement; a
   // domain still in its initial state is simply initialised again
   const bool initial = d->steps == 0 && !d->state_set;
@@ -566,53 +421,37 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   free_links(d);
   d->links_ok = false;
   const size_t rs = f64 ? 8 : 4;
-  std::vector<int32_t> lnode(n_links);
-  for (int64_t k = 0; k < n_links; ++k) lnode[k] = (int32_t)node[order[k]];
   auto up = [&]() -> int {
-    if (int e = dalloc(d->lld, lld.size() * 2)) return e;
-    if (int e = dalloc(d->lnode, lnode.size() * 4)) return e;
-    if (int e = dalloc(d->lq, qd.size() * rs)) return e;
-    if (int e = dalloc(d->lv[0], qd.size() * rs)) return e;
-    if (int e = dalloc(d->lv[1], qd.size() * rs)) return e;
+    if (int e = dalloc(d->lld, plan.lld.size() * 2)) return e;
+    if (int e = dalloc(d->lnode, plan.lnode.size() * 4)) return e;
+    if (int e = dalloc(d->lq, plan.q.size() * rs)) return e;
+    if (int e = dalloc(d->lv[0], plan.q.size() * rs)) return e;
+    if (int e = dalloc(d->lv[1], plan.q.size() * rs)) return e;
     if (moving) {
-      if (int e = dalloc(d->lg, gd.size() * rs)) return e;
-      if (int e = dalloc(d->luv, 6 * qd.size() * rs)) return e;
+      if (int e = dalloc(d->lg, plan.gw.size() * rs)) return e;
+      if (int e = dalloc(d->luv, plan.uv.size() * rs)) return e;
     }
-    HIP_TRY(hipMemcpy(d->lld, lld.data(), lld.size() * 2, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d->lnode, lnode.data(), lnode.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->lld, plan.lld.data(), plan.lld.size() * 2, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->lnode, plan.lnode.data(), plan.lnode.size() * 4, hipMemcpyHostToDevice));
     auto upload_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
       if (f64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
       std::vector<float> f(v.begin(), v.end());
       return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
     };
-    HIP_TRY(upload_real(d->lq, qd));
+    HIP_TRY(upload_real(d->lq, plan.q));
     if (moving) {
-      HIP_TRY(upload_real(d->lg, gd));
+      HIP_TRY(upload_real(d->lg, plan.gw));
       // u_w(t) and u_w(t+1) of every stored link, [6][nl] (regularised wall non-equilibrium)
-      std::vector<double> uv(6 * (size_t)n_links, 0.0);
-      for (int64_t k = 0; k < n_links; ++k) {
-        const int64_t o = order[k];
-        for (int a = 0; a < L.D; ++a) {
-          const double v0 = uw_t ? uw_t[3 * o + a] : 0.0;
-          uv[a * n_links + k] = v0;
-          uv[(3 + a) * n_links + k] = uw_t1 ? uw_t1[3 * o + a] : v0;
-        }
-      }
-      HIP_TRY(upload_real(d->luv, uv));
+      HIP_TRY(upload_real(d->luv, plan.uv));
     }
-    HIP_TRY(hipMemcpy(d->seg_bnd, sb.data(), g.nseg * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d->seg_lbase, slb.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->seg_bnd, plan.seg_bnd.data(), g.nseg * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->seg_lbase, plan.seg_lbase.data(), (g.nseg + 1) * 4, hipMemcpyHostToDevice));
     // wall velocities at t, for the momentum-exchange force (only when a wall moves)
-    bool uw_any = false;
-    for (int64_t k = 0; uw_t && k < 3 * n_links && !uw_any; ++k) uw_any = uw_t[k] != 0.0;
-    if (uw_any) {
-      std::vector<double> uv(3 * n_links);
-      for (int64_t k = 0; k < n_links; ++k)
-        for (int a = 0; a < 3; ++a) uv[3 * k + a] = uw_t[3 * order[k] + a];
-      if (int e = dalloc(d->luw, uv.size() * 8)) return e;
-      HIP_TRY(hipMemcpy(d->luw, uv.data(), uv.size() * 8, hipMemcpyHostToDevice));
+    if (plan.uw_any) {
+      if (int e = dalloc(d->luw, plan.uw.size() * 8)) return e;
+      HIP_TRY(hipMemcpy(d->luw, plan.uw.data(), plan.uw.size() * 8, hipMemcpyHostToDevice));
     }
-    d->nb = nb;
+    d->nb = plan.n_boundary;
     d->nl = n_links;
     HIP_TRY(import_state(d, fstate));
     HIP_TRY(hipStreamSynchronize(d->stream));
@@ -621,7 +460,7 @@ int lbm_set_boundary_links(lbm_domain d, int64_t n_links, const int64_t* node, c
   const int code = up();
   if (fstate) (void)hipFree(fstate);
   if (code != LBM_OK) return code;
-  d->link_order = order;
+  d->link_order = std::move(plan.order);
   d->links_step = d->steps;
   d->nl = n_links;
   d->variant = variant;

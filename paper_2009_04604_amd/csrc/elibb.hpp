@@ -68,6 +68,7 @@ LBM_HD Coef<T> elibb_coefficients(int variant, T q, T q_cut) {
   return c;
 }
 
+#if defined(__HIPCC__)
 // Branch-free form of elibb_coefficients for the kernels.  FP32 uses the
 // hardware reciprocal (1 ulp); FP64 divides exactly.
 template <typename T>
@@ -114,6 +115,7 @@ __device__ __forceinline__ Coef<T> elibb_coefficients_fast(int variant, T q, T q
   }
   return c;
 }
+#endif  // __HIPCC__
 
 // Wall-velocity term of a link.  With P0 = w rho e0 + n_pre,
 // P1 = w rho e1 + n_post, P2 = f*_ibar + w rho m (eq. ELIBB-general, eq.

@@ -181,6 +181,7 @@ int lbm_geometry_add_cylinder(lbm_geometry g, const double centre[3], double rad
 
 int lbm_geometry_add_spheres(lbm_geometry g, int64_t n, const double* centres, const double* radii) {
   if (!g || (n > 0 && (!centres || !radii))) return gfail(LBM_EINVAL, "null argument");
+  if (n < 0) return gfail(LBM_EINVAL, "n < 0");
   for (int64_t k = 0; k < n; ++k)
     if (int e = lbm_geometry_add_sphere(g, centres + 3 * k, radii[k], 1, nullptr, nullptr)) return e;
   return LBM_OK;
@@ -190,6 +191,9 @@ int lbm_geometry_add_face_wall(lbm_geometry g, int32_t face, double q_face, cons
   if (!g) return gfail(LBM_EINVAL, "null geometry");
   if (face < 0 || face > 5 || g->per[face >> 1]) return gfail(LBM_EINVAL, "face must lie on a non-periodic axis");
   if (!(q_face > 0.0 && q_face <= 1.0)) return gfail(LBM_EINVAL, "q_face must lie in (0, 1]");
+  if (profile != 0 && profile != 1) return gfail(LBM_EINVAL, "profile must be 0 or 1");
+  for (int a = 0; uw && a < 3; ++a)
+    if (!std::isfinite(uw[a])) return gfail(LBM_EINVAL, "non-finite wall velocity");
   Face f{};
   f.face = face;
   f.q = q_face;
@@ -394,8 +398,9 @@ int lbm_geometry_get(lbm_geometry g, uint8_t* mask, int64_t* node, int8_t* dir, 
 }
 
 int lbm_geometry_get_shapes(lbm_geometry g, int32_t* shape) {
-  if (!g || !shape) return gfail(LBM_EINVAL, "null argument");
+  if (!g) return gfail(LBM_EINVAL, "null geometry");
   if (!g->built) return gfail(LBM_ESTATE, "geometry not built");
+  if (!shape && !g->shape.empty()) return gfail(LBM_EINVAL, "null shape array");
   std::copy(g->shape.begin(), g->shape.end(), shape);
   return LBM_OK;
 }

@@ -49,6 +49,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "hostplan.hpp"
 #include "lattice.hpp"
 
 namespace lbm {
@@ -64,11 +65,6 @@ __device__ __forceinline__ T load_const(const T* ptr) {
 }  // namespace lbm
 
 namespace lbm {
-
-constexpr int SEG = 64;          // lanes per segment (one wavefront)
-constexpr int WAVES_PER_BLOCK = 4;
-constexpr int BLOCK = SEG * WAVES_PER_BLOCK;
-constexpr int GUARD = 64;        // compact layout: slots in front of the first fluid node
 
 // Division by a run-time constant d < 2^31 for dividends n < 2^31:
 // n / d = (umulhi(n, m) + n) >> s  (m, s chosen on the host).

@@ -38,6 +38,8 @@ reduction to textbook half-way bounce-back with Ladd's correction.
 """
 import numpy as np
 
+from . import precision as prec
+
 VARIANTS = ("FQ", "F", "UQ", "U", "HWBB")
 
 # s-coordinate of each interpolation point as a function of q (eq. x_to_s_helper)
@@ -58,7 +60,7 @@ def bfl_coefficients(q):
     q < 1/2: points {PFF (s=-q), P2 (s=1-q)};  q >= 1/2: points {P2, P3 (s=1+q)}.
     Returns dict point -> weight array.
     """
-    q = np.asarray(q, dtype=np.float64)
+    q = np.asarray(q, dtype=prec.REAL)
     out = {"PFF": np.zeros_like(q), "P2": np.zeros_like(q), "P3": np.zeros_like(q)}
     for sel, key in ((q < 0.5, ("PFF", "P2")), (q >= 0.5, ("P2", "P3"))):
         if sel.any():
@@ -101,7 +103,7 @@ def lagrange_weights(s_nodes, s_ref):
 
 def point_set_groups(variant, q, q_cut=0.01):
     """Vectorised form of point_set: list of (mask, point set) covering all q."""
-    q = np.asarray(q, dtype=np.float64)
+    q = np.asarray(q, dtype=prec.REAL)
     lo, hi = q < 0.5, q >= 0.5
     f_sets = [(lo, ("P0", "P2")), (hi, ("P2", "P1"))]
     if variant == "HWBB":
@@ -125,8 +127,8 @@ def coefficients(variant, q, q_cut=0.01):
     Links are grouped by point set; within a group the generic Lagrange product
     is evaluated with s_ref = q.
     """
-    q = np.asarray(q, dtype=np.float64).reshape(-1)
-    out = np.zeros((q.size, 4), dtype=np.float64)
+    q = np.asarray(q, dtype=prec.REAL).reshape(-1)
+    out = np.zeros((q.size, 4), dtype=prec.REAL)
     for sel, key in point_set_groups(variant, q, q_cut):
         if not sel.any():
             continue
@@ -151,7 +153,7 @@ def equilibrium_dir(lat, i, rho, u):
 
     i: int array (n,), rho: (n,), u: (3, n).
     """
-    c = lat.c[i].T.astype(np.float64)          # (3, n)
+    c = lat.c[i].T.astype(prec.REAL)          # (3, n)
     w = lat.w[i]
     cu = (c * u).sum(axis=0)
     uu = (u * u).sum(axis=0)
@@ -165,7 +167,7 @@ WALL_NEQ = ("bounceback", "regularized")
 def _hermite2_of(lat):
     """H_ab = c_a c_b - cs2 delta_ab of every direction, over the lattice's D axes: (Q, D, D)."""
     D = lat.d
-    c = lat.c[:, :D].astype(np.float64)
+    c = lat.c[:, :D].astype(prec.REAL)
     return np.einsum("na,nb->nab", c, c) - lat.cs2 * np.eye(D)[None]
 
 
@@ -173,7 +175,7 @@ def _hermite3_of(lat):
     """H_abg = c_a c_b c_g - cs2 (delta_ab c_g + delta_ag c_b + delta_bg c_a) of
     every direction: (Q, D, D, D)."""
     D = lat.d
-    c = lat.c[:, :D].astype(np.float64)
+    c = lat.c[:, :D].astype(prec.REAL)
     I = np.eye(D)
     ccc = np.einsum("na,nb,ng->nabg", c, c, c)
     dc = (np.einsum("ab,ng->nabg", I, c) + np.einsum("ag,nb->nabg", I, c) + np.einsum("bg,na->nabg", I, c))
@@ -186,7 +188,7 @@ _TABLES = {}
 def _tables(lat):
     """Per-lattice tables: H2, H3 and c c of every direction (computed once)."""
     if lat.name not in _TABLES:
-        c = lat.c[:, :lat.d].astype(np.float64)
+        c = lat.c[:, :lat.d].astype(prec.REAL)
         _TABLES[lat.name] = (_hermite2_of(lat), _hermite3_of(lat), np.einsum("ja,jb->jab", c, c))
     return _TABLES[lat.name]
 
@@ -224,7 +226,7 @@ def regularized_neq(lat, i, Pi, u):
     """
     D = lat.d
     cs2 = lat.cs2
-    uD = np.asarray(u, dtype=np.float64)[:D].T                   # (n, D)
+    uD = np.asarray(u, dtype=prec.REAL)[:D].T                   # (n, D)
     a3 = (np.einsum("na,nbg->nabg", uD, Pi) + np.einsum("nb,nag->nabg", uD, Pi)
           + np.einsum("ng,nab->nabg", uD, Pi))
     t2 = np.einsum("nab,nab->n", hermite2(lat, i), Pi) / (2.0 * cs2 ** 2)
@@ -257,7 +259,7 @@ def link_points(lat, i, rho_F, feq_F, f_F, fstar_F, uw_t, uw_t1, wall_neq="bounc
         raise ValueError(f"unknown wall non-equilibrium {wall_neq!r}")
     P0 = equilibrium_dir(lat, i, rho_F, uw_t1) + n_pre
     P1 = equilibrium_dir(lat, i, rho_F, uw_t) + n_post
-    cu_w = (lat.c[i].T.astype(np.float64) * uw_t).sum(axis=0)
+    cu_w = (lat.c[i].T.astype(prec.REAL) * uw_t).sum(axis=0)
     P2 = fstar_F[ib, n] + 2.0 * lat.w[i] * rho_F * cu_w / lat.cs2   # eq. ME-solid-to-fluid
     P3 = fstar_F[i, n]
     return np.stack([P0, P1, P2, P3])
@@ -280,7 +282,7 @@ def bfl_value(lat, i, q, rho_F, fstar_F, fstar_FF, ff_ok, uw_t):
     uw_t: (3, n).  Returns (n,)."""
     ib = lat.opp[i]
     n = np.arange(i.size)
-    c = lat.c[i].T.astype(np.float64)
+    c = lat.c[i].T.astype(prec.REAL)
     m = 2.0 * lat.w[i] * rho_F * (c * uw_t).sum(axis=0) / lat.cs2
     w = bfl_coefficients(q)
     lo = q < 0.5
@@ -314,11 +316,11 @@ def momentum_exchange(lat, i, fstar_F, f_new, uw_t, group, n_groups, arm=None):
     """
     ib = lat.opp[i]
     n = np.arange(i.size)
-    c = lat.c.astype(np.float64)
+    c = lat.c.astype(prec.REAL)
     out_ = fstar_F[ib, n]
     contrib = (c[ib].T - uw_t) * out_[None, :] - (c[i].T - uw_t) * f_new[None, :]   # (3, n)
-    F = np.zeros((n_groups, 3))
-    T = np.zeros((n_groups, 3))
+    F = np.zeros((n_groups, 3), dtype=prec.REAL)
+    T = np.zeros((n_groups, 3), dtype=prec.REAL)
     tq = None if arm is None else np.cross(arm.T, contrib.T).T
     for g in range(n_groups):
         sel = group == g

@@ -17,6 +17,8 @@ from fractions import Fraction
 
 import numpy as np
 
+from . import precision as prec
+
 CS2 = 1.0 / 3.0
 
 
@@ -29,13 +31,25 @@ class Lattice:
         self.c = np.array(velocities, dtype=np.int64)
         self.q = len(velocities)
         self.w_exact = [Fraction(x) for x in weights]
-        self.w = np.array([float(x) for x in self.w_exact], dtype=np.float64)
         # opposite direction: the unique j with c_j = -c_i
         self.opp = np.array(
             [int(np.flatnonzero((self.c == -self.c[i]).all(axis=1))[0]) for i in range(self.q)],
             dtype=np.int64,
         )
-        self.cs2 = CS2
+
+    @property
+    def w(self):
+        """Weights in the oracle's current arithmetic type (each fraction rounded once)."""
+        cache = self.__dict__.setdefault("_w", {})
+        if prec.REAL not in cache:
+            cache[prec.REAL] = np.array([prec.scalar(x) for x in self.w_exact], dtype=prec.REAL)
+            cache[prec.REAL].setflags(write=False)
+        return cache[prec.REAL]
+
+    @property
+    def cs2(self):
+        """c_s^2 = 1/3 in the current arithmetic type."""
+        return prec.scalar(Fraction(1, 3))
 
 
 def _d2q9():

@@ -34,12 +34,13 @@ zero-gradient outlet only as far as its mass growth under a velocity inlet.
 import numpy as np
 
 from . import boundary
+from . import precision as prec
 
 
 def equilibrium(lat, rho, u):
     """f^eq_i(rho, u) for all i (eq. Eq2ndOrder).  rho (n,), u (3, n) -> (Q, n)."""
     cs2 = lat.cs2
-    c = lat.c.astype(np.float64)                 # (Q, 3)
+    c = lat.c.astype(prec.REAL)                 # (Q, 3)
     cu = c @ u                                   # (Q, n)
     uu = (u * u).sum(axis=0)                     # (n,)
     return lat.w[:, None] * rho[None, :] * (1.0 + cu / cs2 + (cu * cu - cs2 * uu[None, :]) / (2.0 * cs2 * cs2))
@@ -48,16 +49,16 @@ def equilibrium(lat, rho, u):
 def moments(lat, f, force):
     """rho and u of populations f (Q, n); u includes the F/2 shift of Guo's scheme."""
     rho = f.sum(axis=0)
-    j = lat.c.astype(np.float64).T @ f           # (3, n)
-    u = (j + 0.5 * np.asarray(force, dtype=np.float64)[:, None]) / rho[None, :]
+    j = lat.c.astype(prec.REAL).T @ f           # (3, n)
+    u = (j + 0.5 * np.asarray(force, dtype=prec.REAL)[:, None]) / rho[None, :]
     return rho, u
 
 
 def guo_source(lat, u, force):
     """S_i = w_i [ (c_i - u)/cs2 + (c_i . u) c_i / cs2^2 ] . F   (Guo, Zheng & Shi 2002)."""
     cs2 = lat.cs2
-    F = np.asarray(force, dtype=np.float64)
-    c = lat.c.astype(np.float64)
+    F = np.asarray(force, dtype=prec.REAL)
+    c = lat.c.astype(prec.REAL)
     cF = c @ F                                   # (Q,)
     uF = F @ u                                   # (n,)
     cu = c @ u                                   # (Q, n)
@@ -67,7 +68,7 @@ def guo_source(lat, u, force):
 def trt_omega_minus(tau, magic):
     """omega^- of the TRT model from the magic parameter (eq. magic-parameter):
     Lambda = (1/omega^+ - 1/2)(1/omega^- - 1/2) with omega^+ = 1/tau."""
-    return 1.0 / (magic / (tau - 0.5) + 0.5)
+    return prec.scalar(1) / (prec.scalar(magic) / (prec.scalar(tau) - prec.scalar(0.5)) + prec.scalar(0.5))
 
 
 def collide(lat, f, tau, force, magic=None):
@@ -81,7 +82,7 @@ def collide(lat, f, tau, force, magic=None):
              + (1 - omega^+/2) S^+ + (1 - omega^-/2) S^-,
     Guo's source split the same way (the paper has no body force).
     """
-    omega = 1.0 / tau
+    omega = prec.scalar(1) / prec.scalar(tau)
     rho, u = moments(lat, f, force)
     feq = equilibrium(lat, rho, u)
     has_force = np.any(np.asarray(force) != 0.0)
@@ -109,9 +110,9 @@ class Simulation:
         self.lat = dom.lat
         self.tau = float(tau)
         self.magic = None if magic is None else float(magic)   # TRT magic parameter, None = BGK
-        self.force = np.asarray(force, dtype=np.float64).reshape(3)
+        self.force = np.asarray(force, dtype=prec.REAL).reshape(3)
         self.rho0 = float(rho0)
-        self.u0 = np.asarray(u0, dtype=np.float64).reshape(3)
+        self.u0 = np.asarray(u0, dtype=prec.REAL).reshape(3)
         self.f = None
         self.fluid = None
         self.t = 0
@@ -190,9 +191,9 @@ class Simulation:
     # -- state --------------------------------------------------------------------
     def init_equilibrium(self, rho=None, u=None):
         lat, N = self.lat, self.dom.N
-        rho = np.full(N, self.rho0) if rho is None else np.asarray(rho, dtype=np.float64).reshape(N)
-        u = np.repeat(self.u0.reshape(3, 1), N, axis=1) if u is None else np.asarray(u, dtype=np.float64).reshape(3, N)
-        self.f = np.full((lat.q, N), np.nan)
+        rho = np.full(N, self.rho0, dtype=prec.REAL) if rho is None else np.asarray(rho, dtype=prec.REAL).reshape(N)
+        u = np.repeat(self.u0.reshape(3, 1), N, axis=1) if u is None else np.asarray(u, dtype=prec.REAL).reshape(3, N)
+        self.f = np.full((lat.q, N), np.nan, dtype=prec.REAL)
         fl = self.fluid
         self.f[:, fl] = equilibrium(lat, rho[fl], u[:, fl])
         self.t = 0
@@ -204,8 +205,8 @@ class Simulation:
         f = self.f
         fstar = np.full_like(f, np.nan)
         feq = np.full_like(f, np.nan)
-        rho = np.full(f.shape[1], np.nan)
-        u = np.full((3, f.shape[1]), np.nan)
+        rho = np.full(f.shape[1], np.nan, dtype=f.dtype)
+        u = np.full((3, f.shape[1]), np.nan, dtype=f.dtype)
         fs, r, uu, fe = collide(lat, f[:, nodes], self.tau, self.force, self.magic)
         fstar[:, nodes], rho[nodes], u[:, nodes], feq[:, nodes] = fs, r, uu, fe
         fnew = np.full_like(f, np.nan)
@@ -226,7 +227,7 @@ class Simulation:
                 fnew[d, n] = boundary.reconstruct(self.coef, P)
             grp = np.zeros(n.size, np.int64) if self.link_group is None else self.link_group
             # lever arm: wall point x_W = x_F - q c_i relative to the group's centre (minimum image)
-            xw = self.dom.coords(n).astype(np.float64) - L["q"][None, :] * lat.c[d].T
+            xw = self.dom.coords(n).astype(prec.REAL) - L["q"][None, :] * lat.c[d].T
             arm = self.dom.min_image(xw - self.centres[grp].T)
             if lat.d == 2:
                 arm[2] = 0.0
@@ -243,7 +244,7 @@ class Simulation:
             raise ValueError("bad link groups")
         self.link_group, self.n_groups = g, int(n_groups)
         self.centres = np.zeros((self.n_groups, 3)) if centres is None else \
-            np.asarray(centres, dtype=np.float64).reshape(self.n_groups, 3)
+            np.asarray(centres, dtype=prec.REAL).reshape(self.n_groups, 3)
 
     def run(self, n):
         for _ in range(int(n)):
@@ -272,8 +273,8 @@ class Simulation:
         f = self.f.copy()
         f[:, ~new_fl] = np.nan
         if idx.size:
-            tot = np.zeros(idx.size)
-            cnt = np.zeros(idx.size)
+            tot = np.zeros(idx.size, dtype=prec.REAL)
+            cnt = np.zeros(idx.size, dtype=prec.REAL)
             from .geometry import _source, _index
             for j in range(1, lat.q):
                 nb, inside = _source(dom, X[:, idx].copy(), -lat.c[j])     # x + c_j
@@ -303,8 +304,8 @@ def step_at(dom, f, fluid, links, nodes, tau, force=(0.0, 0.0, 0.0), variant="FQ
     nodes = np.asarray(nodes, dtype=np.int64)
     X = dom.coords()
     xs = X[:, nodes]
-    out = np.full((lat.q, nodes.size), np.nan)
-    force = np.asarray(force, dtype=np.float64)
+    out = np.full((lat.q, nodes.size), np.nan, dtype=prec.REAL)
+    force = np.asarray(force, dtype=prec.REAL)
     # the nodes' own collision (needed by their links)
     fs_self, rho_s, u_s, feq_s = collide(lat, f[:, nodes], tau, force, magic)
     L = {k: np.asarray(v) for k, v in links.items()}

@@ -5,9 +5,16 @@
     python tests/golden/make_fixtures.py c5 3     # moving-sphere box id 3, 4000 steps
     python tests/golden/make_fixtures.py c4       # 16 served requests with L <= 256, 5000 steps
     python tests/golden/make_fixtures.py e3       # BFL comparator, linear error along the axis
+    python tests/golden/make_fixtures.py c3 --extended   # the same in extended precision
 
 Every value written here comes from the FP64 oracle (oracle/) run on the seeded
-recipes of ``synth``; nothing is read from the GPU path.  The full fields are
+recipes of ``synth``; nothing is read from the GPU path.  With --extended (c2,
+c3, c4) the oracle computes in the host's long double (oracle.precision) and
+the file is named *_ext.npz: its results carry the exact solution of the
+discrete problem to ~1e-15 of the velocity, where the FP64 oracle's own
+rounding of f = w + O(u) leaves ~1e-12 after 1000 steps of the packing.
+
+The full fields are
 too large to keep, so each file holds the velocity and density at a fixed,
 seeded sample of fluid nodes (uniform over the fluid plus boundary nodes, whose
 populations the ELIBB rebuilds), and the full-field norm of u, the mass and the
@@ -30,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle import geometry as G, lattice as OL, moving, solver  # noqa: E402
+from oracle import geometry as G, lattice as OL, moving, precision, solver  # noqa: E402
 
 SAMPLE_FLUID = 16384
 SAMPLE_BND = 4096
@@ -62,11 +69,21 @@ def snapshot(sim, nodes, dim):
     }
 
 
+def _out(v):
+    """Stored values are float64 (an extended result rounded once)."""
+    a = np.asarray(v)
+    return a.astype(np.float64) if a.dtype == np.longdouble else a
+
+
+def fixture_path(name, args):
+    return os.path.join(HERE, name + ("_ext" if getattr(args, "extended", False) else "") + ".npz")
+
+
 def save(path, meta, nodes, snaps):
     arrays = {"nodes": nodes, "meta": np.array(json.dumps(meta))}
     for t, s in snaps.items():
         for k, v in s.items():
-            arrays[f"t{t}_{k}"] = np.asarray(v)
+            arrays[f"t{t}_{k}"] = _out(v)
     np.savez_compressed(path + ".tmp.npz", **arrays)
     os.replace(path + ".tmp.npz", path)
 
@@ -99,7 +116,8 @@ def c3(args):
     nodes = sample_nodes(fluid.reshape(-1), links["node"], synth.seed_for(3) + 7)
     meta = {"case": "packing64", "lattice": "D3Q19", "n": [n, n, n], "tau": 0.9, "force": [1e-6, 0, 0],
             "variant": "FQ", "steps": 10000, "n_links": int(links["node"].size)}
-    run_static(sim, nodes, 3, [1000, 10000], os.path.join(HERE, "c3_packing64.npz"), meta)
+    meta["precision"] = str(np.dtype(precision.REAL))
+    run_static(sim, nodes, 3, [1000, 10000], fixture_path("c3_packing64", args), meta)
 
 
 def c2(args):
@@ -122,7 +140,8 @@ def c2(args):
     meta = {"case": "channel2048", "lattice": "D2Q9", "n": [p["nx"], p["ny"], 1], "tau": p["tau"],
             "centre": list(p["centre"]), "radius": p["radius"], "u_max": p["u_max"], "variant": "FQ",
             "steps": 2000, "n_links": int(links["node"].size)}
-    run_static(sim, nodes, 2, [1000, 2000], os.path.join(HERE, "c2_channel2048.npz"), meta)
+    meta["precision"] = str(np.dtype(precision.REAL))
+    run_static(sim, nodes, 2, [1000, 2000], fixture_path("c2_channel2048", args), meta)
 
 
 def c5(args):
@@ -164,9 +183,9 @@ def c4(args):
     """C4 sample: 16 requests of the served stream with L <= 256 (circular Couette
     L x L, tau 0.8; cylinder channel 2L x L, tau 0.6), D2Q9 BGK FP64, ELIBB-FQ,
     5000 steps each."""
-    path = os.path.join(HERE, "c4_requests.npz")
+    path = fixture_path("c4_requests", args)
     arrays = {}
-    meta = {"case": "served_requests", "steps": 5000, "requests": []}
+    meta = {"case": "served_requests", "steps": 5000, "requests": [], "precision": str(np.dtype(precision.REAL))}
     t0 = time.time()
     for req in c4_requests():
         if req["kind"] == "couette":
@@ -191,7 +210,7 @@ def c4(args):
         k = f"r{req['id']}_"
         arrays[k + "nodes"] = nodes
         for name, v in s.items():
-            arrays[k + name] = np.asarray(v)
+            arrays[k + name] = _out(v)
         meta["requests"].append({kk: (list(v) if isinstance(v, tuple) else v) for kk, v in req.items()})
         log(f"request {req['id']} ({req['kind']}, L {req['L']}): done ({time.time() - t0:.0f} s)")
         arrays["meta"] = np.array(json.dumps(meta))
@@ -225,13 +244,21 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("case", choices=["c2", "c3", "c4", "c5", "e3"])
     ap.add_argument("box", nargs="?", type=int, default=3)
+    ap.add_argument("--extended", action="store_true", help="oracle in long double (c2, c3, c4)")
     args = ap.parse_args()
+    if args.extended and args.case not in ("c2", "c3", "c4"):
+        ap.error("--extended applies to c2, c3 and c4")
     try:
         from threadpoolctl import threadpool_limits
         ctx = threadpool_limits(1)
     except Exception:       # pragma: no cover
         ctx = None
-    {"c2": c2, "c3": c3, "c4": c4, "c5": c5, "e3": e3}[args.case](args)
+    run = {"c2": c2, "c3": c3, "c4": c4, "c5": c5, "e3": e3}[args.case]
+    if args.extended:
+        with precision.extended():
+            run(args)
+    else:
+        run(args)
     if ctx is not None:
         ctx.__exit__(None, None, None)
 

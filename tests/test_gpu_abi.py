@@ -59,3 +59,32 @@ def test_invalid_links_rejected(gpu_lib, mutate):
     assert e.value.code == B.LBM_EINVAL
     assert "link" in str(e.value) or "variant" in str(e.value) or "population" in str(e.value)
     d.close()
+
+
+def test_non_finite_population_reports_unstable_through_the_abi(gpu_lib):
+    """A NaN put into one population through lbm_set_state spreads to its
+    neighbours in a step; lbm_macros then returns LBM_EUNSTABLE (not LBM_OK)
+    and its message counts the non-finite nodes, which the moments it wrote
+    show."""
+    import ctypes
+    B = gpu_lib
+    d, mask, links = _domain(B)
+    d.set_boundary_links(links)
+    d.step(5)
+    f = d.get_state()
+    n = int(np.flatnonzero(mask)[len(np.flatnonzero(mask)) // 2])
+    f[1, n] = np.nan
+    d.set_state(f)
+    d.step(1)
+    rho = np.empty(d.N)
+    u = np.empty(d.N * d.D)
+    sums = np.empty(d.D + 2)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    code = B.lib().lbm_macros(d.h, p(rho), p(u), p(sums))
+    assert code == B.LBM_EUNSTABLE
+    msg = B.lib().lbm_last_error().decode()
+    bad = int(msg.split(" at ")[1].split()[0])
+    assert "non-finite" in msg and 1 <= bad <= 9          # the node and the neighbours it streamed to
+    fl = mask.astype(bool)
+    assert int((~(np.isfinite(rho[fl]) & np.isfinite(u.reshape(-1, d.D)[fl]).all(1))).sum()) == bad
+    d.close()

@@ -111,17 +111,31 @@ def test_failing_and_cancelled_requests_retire_alone(gpu_lib):
     clk = StepClock()
     ex = serve.GpuExecutor(storage="f32", keep_fields=ids)
     ex.poison = {reqs[4]["id"]}
-    srv = serve.Server(Clocked(ex, clk), hbm_budget=5 * 2**20, chunk=40, clock=clk, sleep=clk.sleep)
+    victim = reqs[1]["id"]
+    seen = {"admitted": False, "chunks": 0}
+
+    class CancelAfterTwoChunks(Clocked):
+        """Cancels the victim once two chunks have run since its admission (it
+        needs at least five), so it is cancelled while running."""
+
+        def step(self, handles, n):
+            super().step(handles, n)
+            if seen["admitted"]:
+                seen["chunks"] += 1
+                if seen["chunks"] == 2:
+                    srv.cancel(victim)
+
+    srv = serve.Server(CancelAfterTwoChunks(ex, clk), hbm_budget=5 * 2**20, chunk=40, clock=clk, sleep=clk.sleep)
 
     def trace(what, t, info):
-        if what == "admit" and info["id"] == reqs[3]["id"]:
-            srv.cancel(reqs[1]["id"])        # running by then
+        if what == "admit" and info["id"] == victim:
+            seen["admitted"] = True
     srv.trace = trace
     recs = srv.run(reqs)
     ex.close()
     assert "admission failed" in recs[2]["error"]
     assert "non-finite" in recs[4]["error"] and recs[4]["result"]["unstable"]
-    assert recs[1]["error"] == "cancelled"
+    assert seen["chunks"] >= 2 and recs[1]["error"] == "cancelled"
     alone = serve.GpuExecutor(storage="f32", keep_fields=ids)
     for k in (0, 3, 5, 6):
         q, r = reqs[k], recs[k]

@@ -51,9 +51,22 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 };
 enum { LBM_BGK = 0, LBM_TRT = 1 };
 
 /* Storage of the populations.  Collision arithmetic is FP64 for LBM_F64 and
- * FP32 for the others; the 16-bit forms store h_i = f_i - w_i rounded to
- * nearest even and convert back to FP32 on load. */
+ * FP32 for the others; the 16-bit forms store h_i = f_i - w_i rounded as
+ * lbm_domain_desc.rounding says and convert back to FP32 on load. */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16_SHIFTED = 2, LBM_BF16_SHIFTED = 3 };
+
+/* Rounding of the 16-bit stores of the node update (lbm_domain_desc.rounding).
+ * LBM_ROUND_NEAREST: to nearest even.  LBM_ROUND_STOCHASTIC: up or down with
+ * probabilities proportional to the distances, so the rounding error has zero
+ * mean; a per-step change of a population smaller than half a unit in the last
+ * place then survives on average instead of being discarded every step, which
+ * is what stalls a slowly converging flow stored in BF16 (stochastic rounding
+ * against this stagnation: Croci and Giles, IMA J. Numer. Anal. 2022, on the heat
+ * equation in low precision).  The random bits come from a counter-based hash
+ * of the node's slot and the domain's own step count, so results are
+ * deterministic and the same for a domain stepped alone or in a batch.  Only
+ * for the 16-bit storages; initial and imported states round to nearest. */
+enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 
 /* Boundary variants (Sec. II.D).  ELIBB-FQ is the default.  UQ and FQ fall back
  * to ELIBB-F below q_cutoff.  LBM_HWBB is half-way bounce-back with Ladd's
@@ -95,6 +108,8 @@ typedef struct {
                             omega+ = 1/tau relaxes the symmetric parts,
                             omega- with (1/omega+ - 1/2)(1/omega- - 1/2) = Lambda the
                             antisymmetric parts; the paper uses 3/16.  Ignored by BGK. */
+  int32_t rounding;      /* LBM_ROUND_NEAREST (default) or LBM_ROUND_STOCHASTIC
+                            (16-bit storages only)                                     */
 } lbm_domain_desc;
 
 enum { LBM_LAYOUT_COMPACT = 0, LBM_LAYOUT_DENSE = 1 };
@@ -339,7 +354,8 @@ int lbm_step_batch(const lbm_domain* ds, int32_t n, int32_t n_steps);
  * n elements from src to dst (device pointers, caller-owned, arrays of
  * `stride` elements laid one after another), element e of each array at
  * offset shift + e; one element of every array per lane, 64-lane waves over 64
- * consecutive elements, as the step kernel's population streams.  shift 0:
+ * consecutive elements, as the step kernel's population streams; for 9, 19
+ * and 27 arrays a lane issues all its loads before its stores.  shift 0:
  * every wave's run starts on a 256 B boundary (if src and dst are 256 B
  * aligned); 1..31: every run straddles cache lines.  Asynchronous on stream.
  * The caller times it; read + write bytes = 2 * 4 * n * arrays.  LBM_EINVAL

@@ -21,7 +21,9 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 LAYOUTS = {"compact": 0, "dense": 1}
 COLLISIONS = {"BGK": 0, "TRT": 1}
-STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3, "f16s-sr": 2, "bf16s-sr": 3}
+# storage names with stochastic rounding of the 16-bit stores (LBM_ROUND_STOCHASTIC)
+STOCHASTIC = {"f16s-sr", "bf16s-sr"}
 VARIANTS = {"FQ": 0, "F": 1, "UQ": 2, "U": 3, "HWBB": 4}
 WALL_NEQ = {"bounceback": 0, "regularized": 1}
 FACES = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
@@ -54,7 +56,7 @@ class DomainDesc(ctypes.Structure):
         ("force", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 3),
         ("outlet_face", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
         ("arena_bytes", ctypes.c_size_t), ("layout", ctypes.c_int32), ("collision", ctypes.c_int32),
-        ("magic", ctypes.c_double),
+        ("magic", ctypes.c_double), ("rounding", ctypes.c_int32),
     ]
 
 
@@ -161,6 +163,7 @@ def make_desc(lattice, nx, ny, nz, tau, storage="f32", periodic=(True, True, Tru
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.periodic = sum(int(bool(p)) << a for a, p in enumerate(periodic))
     d.storage = STORAGE[storage]
+    d.rounding = 1 if storage in STOCHASTIC else 0
     d.tau = float(tau)
     for a in range(3):
         d.force[a] = float(force[a])

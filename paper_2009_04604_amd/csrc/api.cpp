@@ -94,6 +94,7 @@ LinkView link_view(const lbm_domain_s* d, const void* lv_in, void* lv_out) {
   LinkView lk{};
   lk.seg_fluid = d->seg_fluid;
   lk.seg_fbase = d->seg_fbase;
+  lk.row_src = d->row_src;
   lk.seg_bnd = d->seg_bnd;
   lk.seg_lbase = d->seg_lbase;
   lk.lld = d->lld;
@@ -128,6 +129,8 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.variant = d->variant;
   p.q_cut = d->q_cut;
   p.outlet_face = d->desc.outlet_face;
+  p.rng_ctr = d->rng_ctr;
+  p.parity = cur;
   p.wall_neq = d->wall_neq;
   return p;
 }
@@ -288,6 +291,10 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (d.collision != LBM_BGK && d.collision != LBM_TRT) return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
   if (d.collision == LBM_TRT && !(d.magic > 0.0 && std::isfinite(d.magic)))
     return fail(LBM_EINVAL, "TRT magic parameter must be finite and > 0");
+  if (d.rounding != LBM_ROUND_NEAREST && d.rounding != LBM_ROUND_STOCHASTIC)
+    return fail(LBM_EINVAL, "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC");
+  if (d.rounding == LBM_ROUND_STOCHASTIC && d.storage != LBM_F16_SHIFTED && d.storage != LBM_BF16_SHIFTED)
+    return fail(LBM_EINVAL, "stochastic rounding needs a 16-bit storage");
   // the kernels index populations and segments with 32-bit integers; checked
   // before any device call
   const int64_t npad = population_stride(desc, fluid_mask);
@@ -338,6 +345,7 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   g.npad = npad;
   dm->N = N;
   dm->elem = storage_bytes(d.storage);
+  dm->skind = d.rounding == LBM_ROUND_STOCHASTIC ? (d.storage == LBM_F16_SHIFTED ? ST_F16SR : ST_BF16SR) : d.storage;
   dm->stream = static_cast<hipStream_t>(d.stream);
   dm->variant = LBM_ELIBB_FQ;
   dm->q_cut = 0.01;
@@ -376,6 +384,18 @@ int lbm_init_domain(const lbm_domain_desc* desc, const uint8_t* fluid_mask, lbm_
   if (he == hipSuccess) he = hipMemsetAsync(dm->seg_bnd, 0, g.nseg * 8, dm->stream);
   if (he == hipSuccess) he = hipMemsetAsync(dm->seg_lbase, 0, (g.nseg + 1) * 4, dm->stream);
   if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
+  if (g.compact) {
+    std::vector<int32_t> rows;
+    source_rows(host_grid(dm), rows);
+    if (int e = dalloc(dm->row_src, rows.size() * 4)) return cleanup(e);
+    he = hipMemcpy(dm->row_src, rows.data(), rows.size() * 4, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("upload: ") + hipGetErrorString(he)));
+  }
+
+  // step count of the stochastic rounding, one entry per buffer parity
+  if (int e = dalloc(dm->rng_ctr, 2 * sizeof(uint32_t))) return cleanup(e);
+  he = hipMemsetAsync(dm->rng_ctr, 0, 2 * sizeof(uint32_t), dm->stream);
+  if (he != hipSuccess) return cleanup(fail(LBM_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(he)));
 
   // reductions and the velocity snapshot of the residual
   dm->red_blocks = grid_blocks(g);
@@ -572,7 +592,7 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
   if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set: some populations would be missing");
   for (int32_t s = 0; s < n_steps; ++s) {
     StepParams p = step_params(d, d->cur);
-    hipError_t e = launch_step(d->desc.lattice, d->desc.storage, p, d->stream);
+    hipError_t e = launch_step(d->desc.lattice, d->skind, p, d->stream);
     if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("step kernel: ") + hipGetErrorString(e));
     d->cur ^= 1;
     ++d->steps;
@@ -843,6 +863,8 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->seg_bnd);
   dfree(d->seg_lbase);
   dfree(d->seg_fbase);
+  dfree(d->rng_ctr);
+  dfree(d->row_src);
   free_links(d);
   dfree(d->partials);
   dfree(d->sums);

@@ -317,7 +317,7 @@ hipError_t enqueue_step(lbm_batch_s* b, int p, hipStream_t s) {
     mb.kin = static_cast<const MovingKin*>(b->kin.p);
     mb.nkin = b->nkin;
     mb.ctr = static_cast<const int64_t*>(b->ctr.p);
-    hipError_t e = launch_moving_batch(g.lattice, g.storage, mb, s);
+    hipError_t e = launch_moving_batch(g.lattice, storage_format(g.storage), mb, s);
     if (e != hipSuccess) return e;
   }
   if (any) return launch_advance(static_cast<int64_t*>(b->ctr.p), s);
@@ -403,14 +403,14 @@ int prepare(lbm_batch_s* b, const lbm_domain* ds, int32_t n) {
       const bool trt = d->desc.collision == LBM_TRT;
       const bool reg = d->wall_neq == LBM_NEQ_REGULARIZED;
       for (Group& x : b->groups)
-        if (x.lattice == d->desc.lattice && x.storage == d->desc.storage && x.compact == (d->g.compact != 0) &&
+        if (x.lattice == d->desc.lattice && x.storage == d->skind && x.compact == (d->g.compact != 0) &&
             x.trt == trt && x.reg == reg)
           g = &x;
       if (!g) {
         b->groups.emplace_back();
         g = &b->groups.back();
         g->lattice = d->desc.lattice;
-        g->storage = d->desc.storage;
+        g->storage = d->skind;
         g->compact = d->g.compact != 0;
         g->trt = trt;
         g->reg = reg;

@@ -121,6 +121,41 @@ void segment_index(const HostGrid& g, std::vector<uint64_t>& fluid, std::vector<
   for (int64_t s = 0; s < g.nseg; ++s) fbase[s + 1] = fbase[s] + __builtin_popcountll(fluid[s]);
 }
 
+int source_rows_per_row(int lattice) { return lattice == LBM_D2Q9 ? 3 : 9; }
+
+namespace {
+// Source coordinate of a pull along one axis (coord - c), as the step kernels
+// form it: wrapped, clamped onto an outlet face, else left outside.
+int axis_source(int coord, int c, int n, int periodic, bool out_lo, bool out_hi) {
+  const int v = coord - c;
+  if (periodic) return v < 0 ? v + n : (v >= n ? v - n : v);
+  if (v < 0 && out_lo) return 0;
+  if (v >= n && out_hi) return n - 1;
+  return v;
+}
+}  // namespace
+
+void source_rows(const HostGrid& g, std::vector<int32_t>& row_src) {
+  const int64_t nsx = g.nseg_x;
+  const int64_t rows = (int64_t)g.n[1] * g.n[2];
+  const int o = g.outlet_face;
+  const bool d2 = g.lattice == LBM_D2Q9;
+  const int nr = source_rows_per_row(g.lattice);
+  row_src.assign(rows * nr, 0);
+  for (int z = 0; z < g.n[2]; ++z)
+    for (int y = 0; y < g.n[1]; ++y) {
+      const int64_t r = y + (int64_t)g.n[1] * z;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          if (d2 && b != 1) continue;
+          const int ys = axis_source(y, a - 1, g.n[1], g.per[1], o == 2, o == 3);
+          const int zs = axis_source(z, b - 1, g.n[2], g.per[2], o == 4, o == 5);
+          const int64_t yy = std::min(std::max(ys, 0), g.n[1] - 1), zz = std::min(std::max(zs, 0), g.n[2] - 1);
+          row_src[r * nr + (d2 ? a : 3 * a + b)] = (int32_t)((yy + (int64_t)g.n[1] * zz) * nsx);
+        }
+    }
+}
+
 int plan_links(const HostGrid& g, int64_t n_links, const int64_t* node, const int8_t* dir, const double* q,
                const double* uw_t, const double* uw_t1, int variant, double q_cutoff, bool f64, LinkPlan& out) {
   out = LinkPlan{};

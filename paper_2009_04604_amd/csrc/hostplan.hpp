@@ -54,6 +54,14 @@ int64_t first_uncovered(const HostGrid& g, const std::vector<uint32_t>& linked, 
 // (nseg + 1 entries).
 void segment_index(const HostGrid& g, std::vector<uint64_t>& fluid, std::vector<int32_t>& fbase);
 
+// Compact layout: source rows of the pulls, per row r = y + ny z: entry k = 3 a + b (a, b in
+// 0..2, D = 3; k = a for D = 2, b = 1) is the first segment of the row
+// (y - (a - 1), z - (b - 1)) -- wrapped on periodic axes, clamped onto the
+// outlet face, and otherwise clamped into the lattice (a row beyond a wall is
+// only reached through cut links, whose pulled values are replaced).
+int source_rows_per_row(int lattice);
+void source_rows(const HostGrid& g, std::vector<int32_t>& row_src);
+
 struct LinkPlan {
   std::vector<int64_t> order;    // caller's index of each stored link, sorted by (node, dir)
   std::vector<int32_t> lnode;    // node of each stored link

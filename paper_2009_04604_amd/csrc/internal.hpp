@@ -20,6 +20,9 @@
 // outlet       a zero-gradient outlet face is a clamp of the pull source onto
 //              the face layer: the outlet population reads the same slot as
 //              its upstream neighbour (read-only sharing).
+// source rows (compact layout) per row the first segment of each of its
+//              pull-source rows (wrapped, clamped), so that a wave finds its
+//              source segments without coordinate arithmetic.
 // segments     one wave (64 lanes) handles 64 consecutive x of one row (y, z):
 //              seg_fluid / seg_bnd are 64-bit lane masks of fluid and boundary
 //              nodes; a segment with boundary nodes has its cut links in
@@ -99,6 +102,7 @@ struct GridGeom {
 struct LinkView {
   const uint64_t* seg_fluid;
   const int32_t* seg_fbase;      // [nseg + 1] fluid nodes before each segment
+  const int32_t* row_src;        // compact layout: [rows][3 or 9] first segment of each pull-source row
   const uint64_t* seg_bnd;
   const int32_t* seg_lbase;      // [nseg + 1]
   const uint16_t* lld;           // link lane | dir << 8
@@ -129,6 +133,9 @@ struct StepParams {
   int32_t outlet_face;
   int32_t wall_neq;              // 0: bounced non-equilibrium (eq. neqbb-s); 1: regularised (eq. fi_neq);
                                  // selects the kernel variant (batches group by it)
+  uint32_t* rng_ctr;             // stochastic rounding: the domain's step count, by buffer parity
+                                 // ([parity] is read, block 0 writes [1 - parity] = [parity] + 1)
+  int32_t parity;                // buffer holding the current state (the domain's cur)
 };
 
 struct InitParams {
@@ -291,6 +298,7 @@ struct lbm_domain_s {
   uint64_t* seg_bnd;
   int32_t* seg_lbase;
   int32_t* seg_fbase;
+  int32_t* row_src;              // compact layout only (source_rows)
   // boundary nodes and links
   int64_t nb, nl;
   uint16_t* lld;
@@ -302,6 +310,9 @@ struct lbm_domain_s {
   int32_t variant;
   double q_cut;
   int32_t wall_neq;              // LBM_NEQ_BOUNCEBACK or LBM_NEQ_REGULARIZED
+  int32_t skind;                 // storage kind of the step kernels (ST_*; the stochastic kinds
+                                 // for 16-bit storage with LBM_ROUND_STOCHASTIC)
+  uint32_t* rng_ctr;             // [2] step count by buffer parity (stochastic rounding)
   void* luv;                     // [6][nl or link_cap] u_w(t), u_w(t+1) per link (moving walls), or null
   // reductions
   double* partials;

@@ -31,6 +31,7 @@ struct Coords {
 struct SegInfo {
   uint32_t seg;      // wave-uniform
   uint32_t sx;       // wave-uniform segment index within the row
+  uint32_t row;      // wave-uniform row y + ny z
   int lane;
   Coords c;          // c.y, c.z wave-uniform
 };
@@ -55,6 +56,7 @@ __device__ __forceinline__ SegInfo seg_info(const GridGeom& g, uint32_t block) {
   const uint32_t sx = __builtin_amdgcn_readfirstlane(wave - row * (uint32_t)g.nseg_x);
   const uint32_t z = __builtin_amdgcn_readfirstlane(fast_div(row, g.div_ny));
   s.sx = sx;
+  s.row = row;
   s.c.x = (int)sx * SEG + s.lane;
   s.c.y = (int)__builtin_amdgcn_readfirstlane(row - z * (uint32_t)g.ny);
   s.c.z = (int)z;
@@ -374,13 +376,16 @@ __device__ __forceinline__ DenseIndex dense_index(const GridGeom& g, Coords c) {
   return p;
 }
 
-// Compact layout: slot of fluid node (x, row r) = G + fbase[seg] + popc(mask below x),
-// G = the guard (64 slots, so that a segment whose fluid count before it is a
-// multiple of the line size starts on a cache line).
-// For each source row (y - cy, z - cz) the lane keeps P = slot the node x would
-// have in that row and B = whether (x, row) is fluid; then the source slot of
-// direction i is P (cx = 0), P - 1 (cx = +1, node x - 1) or P + B (cx = -1,
-// node x + 1), with the periodic wrap of the row ends handled by lo / hi.
+// Compact layout: slot of fluid node (x, row r) = slot0 of its segment + the
+// number of fluid lanes below x (G = 64 guard slots in front, so that a
+// segment whose fluid count before it is a multiple of the line size starts
+// on a cache line).  For each source row (y - cy, z - cz) the lane keeps
+// P = slot the node x would have in that row and B = whether (x, row) is
+// fluid; then the source slot of direction i is P (cx = 0), P - 1 (cx = +1,
+// node x - 1) or P + B (cx = -1, node x + 1), with the periodic wrap of the row
+// ends handled by lo / hi.  The first segment of every source row comes from a
+// host-built table (row_src), so a wave forms its nine source segments with
+// one add each instead of wrapping and clamping coordinates.
 template <class L>
 struct CompactIndex {
   uint32_t P[3][3], B[3][3], lo[3][3], hi[3][3];
@@ -397,33 +402,45 @@ struct CompactIndex {
 
 template <class L>
 __device__ __forceinline__ CompactIndex<L> compact_index(const GridGeom& g, const LinkView& lk, const SegInfo& si) {
+  constexpr int NR = L::D == 2 ? 3 : 9;
   CompactIndex<L> p;
   const uint32_t sx = si.sx;
   // only the first and the last segment of a row hold the x-edge lanes; their
   // pulls wrap (periodic x) or clamp onto the node itself (outlet, walls)
   const bool edge = sx == 0 || sx == (uint32_t)g.nseg_x - 1;
   const bool wrap = edge && g.perx;
-  const int o = g.outlet;
+  const int32_t* rs = lk.row_src + (size_t)si.row * NR;
+  uint64_t fm[3][3];
+  uint32_t f0[3][3], ed[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       if (L::D == 2 && b != 1) continue;
-      const int ys = axis_src(si.c.y, a - 1, g.ny, g.pery, o == 2, o == 3);
-      const int zs = axis_src(si.c.z, b - 1, g.nz, g.perz, o == 4, o == 5);
-      // rows beyond a wall face are never used (cut links): any in-range row will do
-      const uint32_t yy = (uint32_t)min(max(ys, 0), g.ny - 1), zz = (uint32_t)min(max(zs, 0), g.nz - 1);
-      const uint32_t row = yy + (uint32_t)g.ny * zz;
-      const uint32_t s0 = row * (uint32_t)g.nseg_x;
-      const uint64_t fm = load_const(lk.seg_fluid + s0 + sx);
-      const uint32_t fb = (uint32_t)load_const(lk.seg_fbase + s0 + sx) + (uint32_t)g.guard;
-      // number of fluid nodes of this segment below the lane (one mbcnt pair)
-      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
-      p.P[a][b] = fb + below;
-      p.B[a][b] = (uint32_t)((fm >> si.lane) & 1ull);
+      const uint32_t s = (uint32_t)load_const(rs + (L::D == 2 ? a : 3 * a + b)) + sx;
+      fm[a][b] = load_const(lk.seg_fluid + s);
+      f0[a][b] = (uint32_t)load_const(lk.seg_fbase + s) + (uint32_t)g.guard;
       if (wrap) {
-        p.lo[a][b] = (uint32_t)load_const(lk.seg_fbase + s0 + (uint32_t)g.nseg_x) + (uint32_t)g.guard - 1u;   // last fluid node of the row
-        p.hi[a][b] = (uint32_t)load_const(lk.seg_fbase + s0) + (uint32_t)g.guard;                        // first fluid node of the row
+        // first segment: the row's last fluid node; last segment: its first
+        const uint32_t s0 = s - sx;
+        ed[a][b] = sx == 0 ? (uint32_t)load_const(lk.seg_fbase + s0 + (uint32_t)g.nseg_x) + (uint32_t)g.guard - 1u
+                           : (uint32_t)load_const(lk.seg_fbase + s0) + (uint32_t)g.guard;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (L::D == 2 && b != 1) continue;
+      // number of fluid nodes of this segment below the lane (one mbcnt pair)
+      const uint32_t below =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(fm[a][b] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm[a][b], 0u));
+      p.P[a][b] = f0[a][b] + below;
+      p.B[a][b] = (uint32_t)((fm[a][b] >> si.lane) & 1ull);
+      if (wrap) {
+        p.lo[a][b] = ed[a][b];                                     // last fluid node of the row
+        p.hi[a][b] = g.nseg_x == 1 ? f0[a][b] : ed[a][b];          // first fluid node of the row
       } else {
         p.lo[a][b] = p.P[a][b];
         p.hi[a][b] = p.P[a][b];
@@ -468,6 +485,27 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return ((uint64_t)hi << 32) | lo;
+}
+
+// Integer mixing function ("lowbias32", C. Wellons' hash prospector, 2018):
+// xorshift-multiply rounds with full avalanche; the random words of the
+// stochastic rounding are this function of a slot index and the step count.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// A wave-uniform byte address (scalar registers) as a pointer into global
+// memory: the accesses through it stay global memory instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> global_at(uint64_t v) {
+  return reinterpret_cast<gptr<T>>(v);
 }
 
 // Wave-local visibility of LDS writes made by other lanes of the same wave.
@@ -528,6 +566,14 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   __shared__ R stage[NV][BLOCK];
   const GridGeom& g = p.g;
   const LinkView& lk = p.lk;
+  // stochastic rounding: the domain's step count (this launch reads the
+  // current parity's entry, block 0 advances the other one), hashed once
+  uint32_t rstep = 0;
+  if constexpr (St::stochastic) {
+    const uint32_t t = load_const(p.rng_ctr + p.parity);
+    if (block == 0 && threadIdx.x == 0) p.rng_ctr[1 - p.parity] = t + 1u;
+    rstep = mix32(t ^ 0x5bd1e995u);
+  }
   const SegInfo si = seg_info(g, block);
   if (si.seg >= g.nseg) return;
   const uint64_t fm = load_const(lk.seg_fluid + si.seg);
@@ -582,10 +628,17 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   }
 
   const auto ix = make_index<L, COMPACT>(g, lk, si);
+  // byte distance between direction arrays; the direction bases below are
+  // advanced by it in scalar registers (a running sum, no multiplies)
+  const uint64_t npb = (uint64_t)np * sizeof(T);
   R h[L::Q];
   if (fluid) {
+    uint64_t qb = uniform_u64(reinterpret_cast<uint64_t>(src));
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) h[i] = St::template load<L>(src + i * np + ix.template src<L>(i), i);
+    for (int i = 0; i < L::Q; ++i) {
+      h[i] = St::template load<L>((const T*)(global_at<const T>(qb) + ix.template src<L>(i)), i);
+      qb = uniform_u64(qb + npb);
+    }
   }
   const bool bnd = fluid && ((bmask >> si.lane) & 1ull);
   if (has_links && list_mode) patch_links<L, R, 2>(h, stage, bnd, tid, wbase, lb0, lb1, si.lane, lk.lld, lvi, ldp, vp);
@@ -596,40 +649,45 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
     for (int i = 0; i < L::Q; ++i) h[i] = R(0);
   }
   m = moments<L, R>(h, col.Fx, col.Fy, col.Fz);
+  // boundary nodes leave their moments (and, in slot mode, their pre-collision
+  // populations) for the link phase
+  if (bnd) {
+    if (!list_mode) {
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) stage[i][tid] = h[i];
+    }
+    stage[L::Q + 0][tid] = m.drho;
+    stage[L::Q + 1][tid] = m.ux;
+    stage[L::Q + 2][tid] = m.uy;
+    stage[L::Q + 3][tid] = m.uz;
+  }
   // dense layout, list mode: solid lanes of a non-empty segment store zeros so
   // that the shared cache lines are written whole (nothing reads those slots);
   // the compact layout has no solid slots
   if (fluid || (!COMPACT && list_mode && inrow)) {
+    // (every storing lane is fluid in the compact layout)
+    const bool keep = COMPACT || fluid;
     // the slots of the storing lanes grow with the lane, so every address is
-    // a wave-uniform base (scalar registers) plus a small 32-bit lane offset
+    // a wave-uniform base (scalar registers) plus a small 32-bit lane offset;
+    // each pair is stored as soon as it is computed, so that the stores drain
+    // while the rest of the collision runs
     const uint32_t self0 = __builtin_amdgcn_readfirstlane(ix.self);
     const uint32_t off = (ix.self - self0) * (uint32_t)sizeof(T);
     auto at = [&](int i) {
       return reinterpret_cast<T*>(reinterpret_cast<char*>(dst + uniform_u64(i * np + self0)) + off);
     };
-    // (every storing lane is fluid in the compact layout)
-    const bool keep = COMPACT || fluid;
+    // stochastic rounding: one random word per node and step, offset per direction
+    const uint32_t rnode = St::stochastic ? mix32(ix.self * 0x9e3779b1u + rstep) : 0u;
+    auto put = [&](int i, R v) { store_rounded<S, L>(at(i), keep ? v : R(0), i, rnode + (uint32_t)i * 0x9e3779b9u); };
     const Pairs<R> pr(col, m);
-    St::template store<L>(at(0), keep ? pr.rest(h[0], R(L::w(0))) : R(0), 0);
+    put(0, pr.rest(h[0], R(L::w(0))));
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
       if (i > L::opp(i)) continue;
       R v, vb;
       pr.template pair<L, TRT>(i, h[i], h[L::opp(i)], m, col, v, vb);
-      St::template store<L>(at(i), keep ? v : R(0), i);
-      St::template store<L>(at(L::opp(i)), keep ? vb : R(0), L::opp(i));
-    }
-  }
-  if (fluid) {
-    if (bnd) {
-      if (!list_mode) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) stage[i][tid] = h[i];
-      }
-      stage[L::Q + 0][tid] = m.drho;
-      stage[L::Q + 1][tid] = m.ux;
-      stage[L::Q + 2][tid] = m.uy;
-      stage[L::Q + 3][tid] = m.uz;
+      put(i, v);
+      put(L::opp(i), vb);
     }
   }
 
@@ -702,7 +760,9 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
       } else {
         Coords cf = c;
         cf.x = xseg + nl;
-        St::template store<L>(dst + (size_t)i * np + src_index_dyn(g, cf, icx, icy, icz), v, i);
+        const uint32_t at = src_index_dyn(g, cf, icx, icy, icz);
+        store_rounded<S, L>(dst + (size_t)i * np + at, v, i,
+                            St::stochastic ? mix32((at + (uint32_t)i * (uint32_t)np) * 0x9e3779b1u + rstep) : 0u);
       }
     };
 #pragma unroll
@@ -741,6 +801,7 @@ __device__ __forceinline__ StepParams table_entry(const StepParams* e) {
   const LinkView* k = &e->lk;
   p.lk.seg_fluid = load_const(&k->seg_fluid);
   p.lk.seg_fbase = load_const(&k->seg_fbase);
+  p.lk.row_src = load_const(&k->row_src);
   p.lk.seg_bnd = load_const(&k->seg_bnd);
   p.lk.seg_lbase = load_const(&k->seg_lbase);
   p.lk.lld = load_const(&k->lld);
@@ -1109,6 +1170,8 @@ __global__ __launch_bounds__(BLOCK) void group_sum_kernel(const double* contrib,
       case ST_F64: KERNEL<LAT, ST_F64, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;               \
       case ST_F32: KERNEL<LAT, ST_F32, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;               \
       case ST_F16S: KERNEL<LAT, ST_F16S, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;             \
+      case ST_F16SR: KERNEL<LAT, ST_F16SR, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;           \
+      case ST_BF16SR: KERNEL<LAT, ST_BF16SR, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;         \
       default: KERNEL<LAT, ST_BF16S, C, T, G><<<grid, BLOCK, 0, stream>>>(__VA_ARGS__); break;                 \
     }                                                                                                          \
   } while (0)
@@ -1250,18 +1313,35 @@ hipError_t launch_group_sum(const double* contrib, const int32_t* group, int64_t
 // sits at shift + e: shift 0 puts every wave's run on 256 B boundaries, any
 // other shift makes every run straddle one (the compact layout's runs start
 // at arbitrary slots).
+// With the array count known at compile time (the lattices' 9, 19 and 27) a
+// lane issues all its loads before its first store, as the step kernel does.
+template <int A>
 __global__ __launch_bounds__(BLOCK) void stream_probe_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                              int64_t n, int64_t stride, int32_t arrays,
                                                              int32_t shift) {
   const int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (e >= n) return;
-  for (int a = 0; a < arrays; ++a) dst[a * stride + shift + e] = src[a * stride + shift + e];
+  if constexpr (A > 0) {
+    float v[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) v[a] = src[a * stride + shift + e];
+#pragma unroll
+    for (int a = 0; a < A; ++a) dst[a * stride + shift + e] = v[a];
+  } else {
+    for (int a = 0; a < arrays; ++a) dst[a * stride + shift + e] = src[a * stride + shift + e];
+  }
 }
 
 hipError_t launch_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays,
                                int32_t shift, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  stream_probe_kernel<<<(unsigned)((n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift);
+  const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+  switch (arrays) {
+    case 9: stream_probe_kernel<9><<<grid, BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift); break;
+    case 19: stream_probe_kernel<19><<<grid, BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift); break;
+    case 27: stream_probe_kernel<27><<<grid, BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift); break;
+    default: stream_probe_kernel<0><<<grid, BLOCK, 0, s>>>(src, dst, n, stride, arrays, shift); break;
+  }
   return hipGetLastError();
 }
 

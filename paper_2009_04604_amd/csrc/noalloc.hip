@@ -68,6 +68,7 @@ extern "C" int lbm_macros_noalloc(lbm_domain d, double* rho, double* u, double* 
   p.src = d->buf[d->cur];
   p.lk.seg_fluid = d->seg_fluid;
   p.lk.seg_fbase = d->seg_fbase;
+  p.lk.row_src = d->row_src;
   p.lk.seg_bnd = d->seg_bnd;
   p.lk.seg_lbase = d->seg_lbase;
   p.lk.lld = d->lld;

@@ -360,8 +360,9 @@ class _Prepared:
 class GpuExecutor:
     """Requests as lbm domains on the current torch device and stream.
 
-    storage      population storage of every request ("f16s" for the served
-                 form, "f32" for the plain one)
+    storage      population storage of every request (the binding's names:
+                 "f16s" / "f16s-sr" for the served form, nearest or stochastic
+                 rounding of the FP16 stores; "f32" for the plain one)
     keep_fields  ids of requests whose final velocity field is returned
     autotune     run the batch autotuner once per shape class
     """

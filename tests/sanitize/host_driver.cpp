@@ -297,6 +297,69 @@ void bad_calls() {
   std::printf("bad ok\n");
 }
 
+// The compact layout's source-row table: for every fluid node and direction
+// whose pull source is a fluid node (or the node an outlet face clamps it
+// onto), the slot the step kernel forms from it (the source row's segment,
+// its fluid lanes below, the row-end wrap) equals that node's slot counted
+// directly.
+void check_source_rows(const Built& b) {
+  const int periodic = b.periodic | (b.lattice == LBM_D2Q9 ? 4 : 0);
+  const lbm::HostGrid g =
+      lbm::make_host_grid(b.lattice, b.n[0], b.n[1], b.n[2], periodic, b.outlet, b.mask.data());
+  std::vector<uint64_t> fluid;
+  std::vector<int32_t> fbase;
+  lbm::segment_index(g, fluid, fbase);
+  std::vector<int32_t> rows;
+  lbm::source_rows(g, rows);
+  const int nr = lbm::source_rows_per_row(b.lattice);
+  CHECK((int64_t)rows.size() == (int64_t)g.n[1] * g.n[2] * nr, "table size");
+  std::vector<int64_t> slot(g.N, -1);
+  int64_t nf = 0;
+  for (int64_t n = 0; n < g.N; ++n)
+    if (b.mask[n]) slot[n] = lbm::GUARD + nf++;
+  const int Q = lattice_q(b.lattice);
+  const int64_t nsx = g.nseg_x;
+  int64_t checked = 0;
+  for (int z = 0; z < g.n[2]; ++z)
+    for (int y = 0; y < g.n[1]; ++y)
+      for (int x = 0; x < g.n[0]; ++x) {
+        const int64_t n = x + (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
+        if (!b.mask[n]) continue;
+        const int64_t r = y + (int64_t)g.n[1] * z, sx = x / lbm::SEG;
+        const int lane = x % lbm::SEG;
+        const bool edge = sx == 0 || sx == nsx - 1, wrap = edge && g.per[0];
+        const bool xlo = edge && x == 0, xhi = edge && x == g.n[0] - 1;
+        for (int i = 0; i < Q; ++i) {
+          int c[3], s[3];
+          direction(b.lattice, i, c);
+          const bool inside = lbm::pull_source(g, c, x, y, z, s);
+          int64_t src = -1;
+          if (inside) {
+            const int64_t m = s[0] + (int64_t)g.n[0] * (s[1] + (int64_t)g.n[1] * s[2]);
+            if (b.mask[m]) src = m;
+          } else {
+            src = lbm::outlet_producer(g, s);
+          }
+          if (src < 0) continue;
+          const int k = b.lattice == LBM_D2Q9 ? 1 + c[1] : 3 * (1 + c[1]) + (1 + c[2]);
+          const int64_t seg = rows[r * nr + k] + sx;
+          CHECK(seg >= 0 && seg < g.nseg, "source segment out of range");
+          const uint64_t fm = fluid[seg];
+          const int64_t f0 = fbase[seg] + lbm::GUARD, s0 = seg - sx;
+          const int64_t edge = sx == 0 ? fbase[s0 + nsx] + lbm::GUARD - 1 : fbase[s0] + lbm::GUARD;
+          const uint64_t below = lane ? (fm & ((1ull << lane) - 1)) : 0;
+          const int64_t P = f0 + __builtin_popcountll(below);
+          const int64_t B = (int64_t)((fm >> lane) & 1ull);
+          const int64_t lo = wrap ? edge : P, hi = wrap ? (nsx == 1 ? f0 : edge) : P;
+          const int64_t got = c[0] == 0 ? P : (c[0] == 1 ? (xlo ? lo : P - 1) : (xhi ? hi : P + B));
+          CHECK(got == slot[src], "compact slot of node %lld dir %d: %lld, expected %lld", (long long)n, i,
+                (long long)got, (long long)slot[src]);
+          ++checked;
+        }
+      }
+  std::printf("source rows ok %lld\n", (long long)checked);
+}
+
 }  // namespace
 
 int main() {
@@ -369,6 +432,7 @@ int main() {
       std::string qc;
       std::cin >> variant >> qc >> f64;
       plan_case(b, variant, real(qc), f64 != 0);
+      check_source_rows(b);
     } else if (cmd == "bad") {
       bad_calls();
     } else if (cmd == "end") {

@@ -2,7 +2,8 @@
 storage format (the 16-bit shifted formats must keep it): circular Couette
 (Sec. III.B) at 48^2, 96^2 and 192^2 (tau fixed, inner wall speed fixed, steps
 scaled with the square of the resolution to the same steady state), rRSE of
-the velocity norm against the closed form.  The slopes and errors are printed
+the velocity norm against the closed form; the 16-bit formats also with
+stochastic rounding of their stores.  The slopes and errors are printed
 and asserted; the analytic comparison needs no oracle run."""
 import numpy as np
 import pytest
@@ -29,9 +30,9 @@ def _rrse(B, W, scale, storage, **kw):
     return metrics.rrse(np.linalg.norm(u[fl], axis=1), uth)
 
 
-def _errors(B, storage, **kw):
+def _errors(B, storage, scales=(1.0, 2.0, 4.0), **kw):
     from paper_2009_04604_amd import workloads as W
-    scales = np.array([1.0, 2.0, 4.0])
+    scales = np.array(scales)
     errs = np.array([_rrse(B, W, s, storage, **kw) for s in scales])
     # least-squares slope over the three resolutions (the wall's position in the
     # lattice changes with the resolution, so pairwise slopes scatter)
@@ -62,6 +63,27 @@ def test_couette_bf16_error_stated(gpu_lib):
     convergence claim)."""
     errs, _ = _errors(gpu_lib, "bf16s")
     assert errs[0] < 0.005
+
+
+def test_couette_16bit_stochastic_rounding(gpu_lib):
+    """Stochastic rounding of the 16-bit stores (LBM_ROUND_STOCHASTIC) out to
+    384^2, where nearest rounding has lost the solution (FP16 1.8e-2, BF16 0.15:
+    per-step changes below half an ulp are discarded, the flow stalls).  With an
+    unbiased rounding those changes survive on average: FP16 stays second order
+    from 48^2 to 96^2 and keeps improving (3.0e-4 at 192^2, 2.5e-4 at 384^2, near
+    FP64's 2.0e-4 at 192^2); BF16 stops at a floor of ~2e-3 set by its 8-bit
+    significands instead of growing."""
+    scales = (1.0, 2.0, 4.0, 8.0)
+    e16, _ = _errors(gpu_lib, "f16s-sr", scales)
+    e16n, _ = _errors(gpu_lib, "f16s", scales)
+    assert np.log(e16[0] / e16[1]) / np.log(2.0) > 1.8
+    assert e16[2] < e16[1] and e16[2] < 4e-4 and e16[3] < 4e-4
+    assert e16[3] < e16n[3] / 10
+    eb, _ = _errors(gpu_lib, "bf16s-sr", scales)
+    ebn, _ = _errors(gpu_lib, "bf16s", scales)
+    assert eb[0] < 0.005 and eb[1] < 0.6 * eb[0]
+    assert max(eb[1:]) < 3e-3 and max(eb[1:]) < 1.3 * min(eb[1:])
+    assert eb[3] < ebn[3] / 10
 
 
 @pytest.mark.parametrize("kw", [{"collision": "TRT"}, {"wall_neq": "regularized"},

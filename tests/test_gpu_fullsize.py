@@ -58,7 +58,8 @@ def test_cylinder_channel_2048x1024_f32_one_step(gpu_lib):
 
 
 @pytest.mark.parametrize("lattice,collision,storage", [("D3Q19", "BGK", "f32"), ("D3Q27", "TRT", "f32"),
-                                                       ("D3Q19", "BGK", "bf16s"), ("D3Q19", "BGK", "f16s")])
+                                                       ("D3Q19", "BGK", "bf16s"), ("D3Q19", "BGK", "f16s"),
+                                                       ("D3Q19", "BGK", "bf16s-sr"), ("D3Q19", "BGK", "f16s-sr")])
 def test_sphere_packing_256_one_step(gpu_lib, lattice, collision, storage):
     """The benchmark's packing (`bench.py`, with `--lattice D3Q27 --collision TRT`,
     and with `--storage bf16s / f16s`).  FP32: within 1e-6.  16-bit: the stored
@@ -66,7 +67,11 @@ def test_sphere_packing_256_one_step(gpu_lib, lattice, collision, storage):
     significant bits), so |df| <= 2^-8 |h*| (BF16) or 2^-11 |h*| (FP16) plus FP32
     error (the cut links' values stay FP32).  The small body force keeps |h*| near
     1e-5, where FP16 is subnormal (half a step 2^-25 = 3e-8): tested with 1e-9
-    (BF16, FP32's exponent range) and 4e-8 (FP16) added."""
+    (BF16, FP32's exponent range) and 4e-8 (FP16) added.  Stochastic rounding
+    (`-sr`) rounds to either neighbour, so its bound is one whole step (twice
+    the above); its errors must also exceed half a step somewhere (it is not
+    rounding to nearest) and average to zero in units of the step (it is not
+    truncating)."""
     from paper_2009_04604_amd import workloads as W
     n = 256
     magic = 3.0 / 16.0 if collision == "TRT" else None
@@ -93,12 +98,28 @@ def test_sphere_packing_256_one_step(gpu_lib, lattice, collision, storage):
     if storage == "f32":
         _check_one_step(f0, f1, out, nodes, 1e-6)
         return
-    eps, floor = (2.0 ** -8, 1e-9) if storage == "bf16s" else (2.0 ** -11, 4e-8)
+    bf = storage.startswith("bf16s")
+    sr = storage.endswith("-sr")
+    eps, floor = (2.0 ** -8, 1e-9) if bf else (2.0 ** -11, 4e-8)
+    if sr:
+        eps, floor = 2 * eps, 2 * floor
     h = out - OL.get(lattice).w[:, None]
     err = np.abs(f1[:, nodes] - out)
     _say("max |df|", err.max(), "max |df| / bound", (err / (eps * np.abs(h) + floor)).max(), "nodes", nodes.size)
     assert np.isfinite(out).all()
     assert (err <= eps * np.abs(h) + floor).all()
+    if sr:
+        # signed error in units of the 16-bit step at each value (FP16 below
+        # 2^-14 is subnormal: a fixed step of 2^-24)
+        hs = f1[:, nodes] - OL.get(lattice).w[:, None]
+        sig, tiny = (8, 2.0 ** -133) if bf else (11, 2.0 ** -24)
+        big = np.abs(h) > 1e-30
+        ulp = np.maximum(2.0 ** (np.floor(np.log2(np.abs(h[big]))) - (sig - 1)), tiny)
+        e = (hs[big] - h[big]) / ulp
+        _say("stochastic rounding: mean error", e.mean(), "ulp; share above half a step", (np.abs(e) > 0.5).mean(),
+             "values", e.size)
+        assert (np.abs(e) > 0.55).mean() > 0.05
+        assert abs(e.mean()) < 0.02
 
 
 def test_moving_boxes_32_bf16_batched_one_step(gpu_lib):

@@ -3,8 +3,10 @@ sanitizers, on the CPU: the geometry builder (geometry.cpp) and the cut-link
 validation and planning (hostplan.cpp) are compiled with g++
 -fsanitize=address,undefined together with a driver (tests/sanitize/
 host_driver.cpp) that builds the workloads' geometries, plans their links,
-checks every planned record, and feeds corrupted link lists that must be
-refused.  Any sanitizer report aborts the driver.  The builder's output is
+checks every planned record, checks the compact layout's source-row table by
+forming every pull's slot the way the step kernel does and comparing it with
+the source node's slot counted directly, and feeds corrupted link lists that
+must be refused.  Any sanitizer report aborts the driver.  The builder's output is
 also compared, to the bit, with the production library's (hipcc build) on the
 same shapes."""
 import os
@@ -123,6 +125,17 @@ def test_host_library_under_sanitizers(driver, tmp_path):
     s.geom("D3Q19", 24, 20, 16)
     s.round("sphere", (1.2, 19.5, 15.0), 4.3, True, V=(0.01, -0.02, 0.005), Om=(0.001, 0.002, -0.003))
     s.build((("UQ", 0.01, 1),))
+    # rows of several segments with a periodic x-wrap (the source-row table's row
+    # ends), and an outlet on a y face (source rows clamped onto it)
+    s.geom("D3Q19", 150, 12, 10)
+    s.round("sphere", (3.0, 4.0, 3.0), 2.6, True)
+    s.round("sphere", (148.5, 1.0, 6.0), 2.2, True)
+    s.round("sphere", (70.0, 5.0, 2.0), 2.5, True)
+    s.build()
+    s.geom("D2Q9", 130, 40, 1, periodic=(True, False, True), outlet=3)
+    s.round("sphere", (64.5, 20.0, 0.0), 6.0, True)
+    s.face(2, 0.5)
+    s.build()
     # degenerate lattices: one node, all solid, nodes exactly on the wall
     s.geom("D3Q19", 1, 1, 1)
     s.build()
@@ -139,7 +152,8 @@ def test_host_library_under_sanitizers(driver, tmp_path):
                        timeout=600)
     assert r.returncode == 0 and r.stdout.rstrip().endswith("ALL OK"), r.stdout[-3000:] + r.stderr[-3000:]
     assert "FAIL" not in r.stdout
-    assert r.stdout.count("plan ok") == 13
+    assert r.stdout.count("plan ok") == 15
+    assert r.stdout.count("source rows ok") == 15
     # the sanitized build agrees with the production library to the bit
     for prefix, case in s.cases:
         mask, links = _production(B, case)

@@ -248,11 +248,13 @@ def _oracle_case(kind, p):
     return sim
 
 
-def _time_oracle_steps(sim, k):
+def _time_oracle_steps(sim, k, log=None, every=0):
     sim.step()
     t0 = time.perf_counter()
-    for _ in range(k):
+    for j in range(k):
         sim.step()
+        if log and every and (j + 1) % every == 0:
+            log(f"cpu full: {j + 1} of {k} steps ({time.perf_counter() - t0:.0f} s)")
     return (time.perf_counter() - t0) / k
 
 
@@ -311,7 +313,7 @@ def cpu_baseline_full(log):
     # C2: 200 steps
     p = synth.cylinder_channel()
     sim = _oracle_case("channel", p)
-    s = _time_oracle_steps(sim, 200)
+    s = _time_oracle_steps(sim, 200, log, 20)
     nfl = int(sim.fluid.sum())
     out["C2_channel2048_200_steps"] = {"s_per_step": round(s, 3), "MLUPS": round(nfl / s / 1e6, 3), "cores": 1,
                                        "projected_20000_steps_h": round(20000 * s / 3600, 2)}
@@ -324,11 +326,16 @@ def cpu_baseline_full(log):
     sh = [G.Sphere(cc, rr, True) for cc, rr in zip(c, r)]
     t0 = time.perf_counter()
     fluid = G.classify(dom, sh)
+    log(f"cpu full: C3 classified ({time.perf_counter() - t0:.0f} s)")
+    links = G.cut_links(dom, fluid, sh)
+    log(f"cpu full: C3 {links['node'].size} cut links ({time.perf_counter() - t0:.0f} s)")
     sim = solver.Simulation(dom, 0.9, force=(1e-6, 0, 0))
-    sim.set_geometry(fluid, G.cut_links(dom, fluid, sh), "FQ")
+    sim.set_geometry(fluid, links, "FQ")
     sim.init_equilibrium()
+    del links
     setup = time.perf_counter() - t0
-    s = _time_oracle_steps(sim, 20)
+    log(f"cpu full: C3 set up ({setup:.0f} s)")
+    s = _time_oracle_steps(sim, 20, log, 2)
     nfl = int(fluid.sum())
     out["C3_packing256_20_steps"] = {"s_per_step": round(s, 3), "MLUPS": round(nfl / s / 1e6, 3), "cores": 1,
                                      "setup_s": round(setup, 1), "projected_10000_steps_h": round(10000 * s / 3600, 2)}
@@ -346,7 +353,10 @@ def cpu_baseline_full(log):
     sample = reqs[::16]
     with mp.get_context("fork").Pool(processes=cores, initializer=_worker_init) as pool:
         t0 = time.perf_counter()
-        sec = pool.map(_request_seconds, [(q, 10) for q in sample])
+        sec = []
+        for x in pool.imap_unordered(_request_seconds, [(q, 10) for q in sample]):
+            sec.append(x)
+            log(f"cpu full: C4 request {len(sec)} of {len(sample)} timed")
         wall = time.perf_counter() - t0
         per_req = float(np.mean(sec)) * 5000
         out["C4_served_all_cores"] = {"sample": f"{len(sample)} requests (every 16th of the 256), 10 steps each",
@@ -355,7 +365,10 @@ def cpu_baseline_full(log):
                                       "sample_wall_s": round(wall, 1)}
         log(f"cpu full: C4 {cores / per_req:.5f} solves/s on {cores} cores")
         bsample = boxes[::4]
-        sec = pool.map(_box_seconds, [(b, 3) for b in bsample])
+        sec = []
+        for x in pool.imap_unordered(_box_seconds, [(b, 3) for b in bsample]):
+            sec.append(x)
+            log(f"cpu full: C5 box {len(sec)} of {len(bsample)} timed")
         per_box = float(np.mean(sec)) * 4000
         out["C5_boxes_all_cores"] = {"sample": f"{len(bsample)} boxes (every 4th of the 32), 3 steps each",
                                      "mean_box_s_at_4000_steps": round(per_box, 1),

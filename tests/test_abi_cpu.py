@@ -27,7 +27,8 @@ def test_exports_every_declared_symbol(B):
 
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("lattice", 7), ("nz", 3),
-                                         ("storage", 9), ("outlet_face", 0), ("rho0", -1.0)])
+                                         ("storage", 9), ("outlet_face", 0), ("rho0", -1.0),
+                                         ("rounding", 2), ("rounding", 1)])   # stochastic needs 16-bit storage
 def test_init_rejects_invalid_descriptor(B, field, value):
     d = B.make_desc("D2Q9", 8, 8, 1, 0.8, periodic=(True, True, True))
     if field == "nz":

@@ -44,6 +44,13 @@ def test_init_rejects_invalid_descriptor(B, field, value):
     assert B.lib().lbm_last_error().decode()
 
 
+@pytest.mark.parametrize("name,storage,rounding", [("f16s", 2, 0), ("bf16s", 3, 0), ("f16s-sr", 2, 1),
+                                                  ("bf16s-sr", 3, 1), ("f32", 1, 0)])
+def test_storage_names_map_to_storage_and_rounding(B, name, storage, rounding):
+    d = B.make_desc("D2Q9", 8, 8, 1, 0.8, storage=name)
+    assert (d.storage, d.rounding) == (storage, rounding)
+
+
 def test_init_rejects_a_lattice_beyond_32_bit_indexing(B):
     """2048 x 1024 x 1024 stored nodes (dense layout) exceed the kernels' 32-bit
     population index; refused before any device call (the mask is never read)."""

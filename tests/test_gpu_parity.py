@@ -181,16 +181,19 @@ def test_sums_are_deterministic_and_consistent(gpu_lib):
     d.close()
 
 
-@pytest.mark.parametrize("storage,bound", [("f16s", 3e-2), ("bf16s", 2e-1)])
-def test_shifted_16bit_error_stated(gpu_lib, storage, bound):
-    """16-bit shifted storage on the annulus: error against the FP64 oracle after
-    5000 steps is printed and bounded."""
-    case = annulus_case()
+@pytest.mark.parametrize("storage,bound,magic", [("f16s", 3e-2, None), ("bf16s", 2e-1, None),
+                                                 ("f16s-sr", 3e-2, None), ("bf16s-sr", 2e-1, None),
+                                                 ("f16s-sr", 3e-2, 3.0 / 16.0), ("bf16s-sr", 2e-1, 3.0 / 16.0)])
+def test_shifted_16bit_error_stated(gpu_lib, storage, bound, magic):
+    """16-bit shifted storage on the annulus, nearest and stochastic rounding,
+    BGK and TRT: error against the FP64 oracle after 5000 steps is printed and
+    bounded."""
+    case = annulus_case(magic=magic)
     d, _, _ = case.gpu(gpu_lib, storage)
     sim = case.oracle()
     d.step(5000)
     sim.run(5000)
     err = fluid_velocity_error(d, sim)[0]
-    _say(storage, "rel L2 velocity vs FP64 oracle", err)
+    _say(storage, "TRT" if magic else "BGK", "rel L2 velocity vs FP64 oracle", err)
     assert err <= bound
     d.close()

@@ -184,7 +184,7 @@ def test_full_size_packing_256_f32_one_step(gpu_lib):
     assert np.isfinite(out).all() and err <= 1e-6 and rel <= 1e-6
 
 
-@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 1e-2)])
+@pytest.mark.parametrize("storage,bound", [("f16s", 1e-3), ("bf16s", 1e-2), ("f16s-sr", 1e-3), ("bf16s-sr", 1e-2)])
 def test_16bit_error_stated(gpu_lib, storage, bound):
     _say("case regularised annulus 48x48", storage)
     err = _compare(gpu_lib, annulus_case(), storage, 2000, tol=bound)

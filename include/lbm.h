@@ -179,6 +179,21 @@ int lbm_set_wall_neq(lbm_domain d, int32_t mode);
 int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
                           const double direction[3], const double omega[3], int32_t variant, double q_cutoff);
 
+/* The same rigid sphere (Sec. II.E moving boundaries) on a prescribed path of
+ * any form: sample k (k = 0 .. n_samples-1, host arrays [n_samples][3], (x, y,
+ * z), copied) gives the centre x_c(k) and the translational velocity V(k) at
+ * step k; omega is the constant angular velocity.  The geometry of time t is
+ * built from x_c(t), V(t) and V(t+1) exactly as for lbm_set_moving_sphere, so
+ * the domain can take n_samples - 2 steps in all; lbm_step and lbm_batch_step
+ * refuse (LBM_ESTATE) a call that would step past the path.  The sampled
+ * centres of lbm_set_moving_sphere's sinusoid reproduce it to the bit.  The
+ * sweep region is the samples' bounding box grown by the radius.  Requirements
+ * as for lbm_set_moving_sphere (LBM_ESTATE); LBM_EINVAL for n_samples < 2, a
+ * non-positive radius, non-finite samples, or a sweep that does not fit in half
+ * the box on some axis. */
+int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
+                               const double* centre, const double* velocity, int32_t variant, double q_cutoff);
+
 /* Advance n_steps >= 0 time steps; asynchronous on the domain's stream.  Each
  * step is the lattice Boltzmann equation of Sec. II.A (eq. LBE) split into the
  * local collision -- BGK (eq. LB-BGK) with the second-order equilibrium (eq.

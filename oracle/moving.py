@@ -3,7 +3,8 @@ Jeffery-orbit study of Sec. III.C uses moving objects with refilled fresh nodes)
 
 Kinematics (prescribed, not computed from forces): centre
 x_c(t) = x_0 + A sin(2 pi t / T) e, translational velocity
-V(t) = A (2 pi / T) cos(2 pi t / T) e, constant angular velocity Omega.
+V(t) = A (2 pi / T) cos(2 pi t / T) e, constant angular velocity Omega; or a
+path of any form given by samples of x_c and V per step (SampledKinematics).
 
 One step t -> t+1 (readings, listed in the design notes):
 1. geometry(t): fluid nodes and cut links of the sphere at x_c(t);
@@ -14,7 +15,9 @@ One step t -> t+1 (readings, listed in the design notes):
 3. the ordinary step with that geometry.
 
 Status: pinned -- V(t) against central differences of x_c(t) over a period and
-its closed values at t = 0 and T/4; the refill rule against hand-listed
+its closed values at t = 0 and T/4; a sampled path against the sinusoid it
+samples and against the co-moving invariant on a straight path; the refill
+rule against hand-listed
 neighbour sets (tests/test_oracle_refill.py); the co-moving invariant (a sphere
 moving at the velocity of a uniform flow leaves it unchanged, refills
 included).
@@ -38,6 +41,25 @@ class Kinematics:
 
     def velocity(self, t):
         return self.A * (2.0 * np.pi / self.T) * np.cos(2.0 * np.pi * t / self.T) * self.e
+
+
+class SampledKinematics:
+    """A prescribed path given by samples: x_c(t) = centre[t], V(t) =
+    velocity[t] at integer steps t (arrays [n][3]), constant angular velocity.
+    The step of MovingSphereSim asks for x_c(t), V(t) and V(t+1) only, so n
+    samples drive n - 2 steps."""
+
+    def __init__(self, centre, velocity, omega):
+        self.C = np.asarray(centre, dtype=np.float64).reshape(-1, 3)
+        self.V = np.asarray(velocity, dtype=np.float64).reshape(-1, 3)
+        assert self.C.shape == self.V.shape and self.C.shape[0] >= 2
+        self.Omega = np.asarray(omega, dtype=np.float64)
+
+    def centre(self, t):
+        return self.C[int(t)].copy()
+
+    def velocity(self, t):
+        return self.V[int(t)].copy()
 
 
 class MovingSphereSim:

@@ -139,6 +139,20 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
 // x0 + A sin(2 pi t / T) e and its velocity at t and t + 1.
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   MovingKin k{};
+  if (!d->path_c.empty()) {
+    // a sampled path: the geometry of time t needs x_c(t), V(t) and V(t+1); a
+    // time past the path (only in rows of a kinematics table that no step
+    // uses) takes its last pair of samples
+    const int64_t n = (int64_t)d->path_c.size() / 3;
+    const int64_t tt = std::min<int64_t>(std::max<int64_t>(t, 0), n - 2);
+    for (int a = 0; a < 3; ++a) {
+      k.c[a] = d->path_c[3 * tt + a];
+      k.V[a] = d->path_v[3 * tt + a];
+      k.V1[a] = d->path_v[3 * (tt + 1) + a];
+    }
+    if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
+    return k;
+  }
   const double two_pi = 2.0 * M_PI;
   const double s = std::sin(two_pi * t / d->mv_period);
   const double c0 = std::cos(two_pi * t / d->mv_period), c1 = std::cos(two_pi * (t + 1) / d->mv_period);
@@ -150,6 +164,13 @@ MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   }
   if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
   return k;
+}
+
+// Steps a domain whose sphere follows a sampled path can still take: the
+// geometry of time t uses the samples t and t+1.
+int64_t path_steps_left(const lbm_domain_s* d) {
+  if (d->path_c.empty()) return INT64_MAX;
+  return (int64_t)d->path_c.size() / 3 - 2 - d->steps;
 }
 
 // Static part of the moving-sphere rebuild; `cur` names the population buffer
@@ -504,12 +525,13 @@ int lbm_set_wall_neq(lbm_domain d, int32_t mode) {
   return LBM_OK;
 }
 
-int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
-                          const double direction[3], const double omega[3], int32_t variant, double q_cutoff) {
-  if (!d || !x0 || !direction || !omega) return fail(LBM_EINVAL, "null argument");
-  if (!(radius > 0.0) || !(period > 0.0) || !(amplitude >= 0.0)) return fail(LBM_EINVAL, "radius, period must be > 0, amplitude >= 0");
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(x0[a]) || !std::isfinite(direction[a]) || !std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite motion");
+namespace {
+// Common set-up of a moving sphere whose centre stays within [lo, hi] per axis:
+// checks, the sweep region's segments, the link arrays, the geometry of time 0
+// and the initial state.  The motion itself (sinusoid or sampled path) is set
+// on the domain by the caller beforehand.
+int install_moving(lbm_domain d, const double lo_c[3], const double hi_c[3], double radius, const double omega[3],
+                   int32_t variant, double q_cutoff) {
   if (variant < LBM_ELIBB_FQ || variant > LBM_HWBB) return fail(LBM_EINVAL, "invalid variant");
   if (!(q_cutoff >= 0.0) || !std::isfinite(q_cutoff)) return fail(LBM_EINVAL, "q_cutoff must be finite and >= 0");
   if (d->g.compact) return fail(LBM_ESTATE, "a moving sphere needs the dense layout (desc.layout = LBM_LAYOUT_DENSE)");
@@ -521,7 +543,7 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   {
     const int n3[3] = {g.nx, g.ny, d->D == 3 ? g.nz : 1 << 30};
     for (int a = 0; a < 3; ++a)
-      if (2.0 * (radius + std::fabs(amplitude * direction[a]) + 2.0) >= n3[a])
+      if (2.0 * (radius + 0.5 * (hi_c[a] - lo_c[a]) + 2.0) >= n3[a])
         return fail(LBM_EINVAL, "the sphere and its sweep must fit in half the box on every axis");
   }
   // the region: segments of the box swept by the sphere (plus two nodes)
@@ -529,9 +551,8 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   int lo[3], hi[3];
   const int n[3] = {g.nx, g.ny, g.nz}, per[3] = {g.perx, g.pery, g.perz};
   for (int a = 0; a < 3; ++a) {
-    const double ext = std::fabs(amplitude * direction[a]) + radius;
-    lo[a] = (int)std::floor(x0[a] - ext) - 2;
-    hi[a] = (int)std::ceil(x0[a] + ext) + 2;
+    lo[a] = (int)std::floor(lo_c[a] - radius) - 2;
+    hi[a] = (int)std::ceil(hi_c[a] + radius) + 2;
     if (d->D == 2 && a == 2) lo[a] = hi[a] = 0;
     if (hi[a] - lo[a] + 1 >= n[a]) {
       lo[a] = 0;
@@ -566,14 +587,8 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));
-  for (int a = 0; a < 3; ++a) {
-    d->mv_x0[a] = x0[a];
-    d->mv_dir[a] = direction[a];
-    d->mv_om[a] = omega[a];
-  }
+  for (int a = 0; a < 3; ++a) d->mv_om[a] = omega[a];
   d->mv_r = radius;
-  d->mv_amp = amplitude;
-  d->mv_period = period;
   d->variant = variant;
   d->q_cut = q_cutoff;
   d->moving = true;
@@ -585,11 +600,65 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   clear_error();
   return LBM_OK;
 }
+}  // namespace
+
+int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, double amplitude, double period,
+                          const double direction[3], const double omega[3], int32_t variant, double q_cutoff) {
+  if (!d || !x0 || !direction || !omega) return fail(LBM_EINVAL, "null argument");
+  if (!(radius > 0.0) || !(period > 0.0) || !(amplitude >= 0.0)) return fail(LBM_EINVAL, "radius, period must be > 0, amplitude >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(x0[a]) || !std::isfinite(direction[a]) || !std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite motion");
+  if (d->moving) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
+  double lo_c[3], hi_c[3];
+  for (int a = 0; a < 3; ++a) {
+    const double ext = std::fabs(amplitude * direction[a]);
+    lo_c[a] = x0[a] - ext;
+    hi_c[a] = x0[a] + ext;
+    d->mv_x0[a] = x0[a];
+    d->mv_dir[a] = direction[a];
+  }
+  d->mv_amp = amplitude;
+  d->mv_period = period;
+  d->path_c.clear();
+  d->path_v.clear();
+  return install_moving(d, lo_c, hi_c, radius, omega, variant, q_cutoff);
+}
+
+int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
+                               const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
+  if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
+  if (!(radius > 0.0) || !std::isfinite(radius)) return fail(LBM_EINVAL, "radius must be finite and > 0");
+  if (n_samples < 2) return fail(LBM_EINVAL, "a path needs at least 2 samples");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite omega");
+  for (int64_t k = 0; k < 3 * n_samples; ++k)
+    if (!std::isfinite(centre[k]) || !std::isfinite(velocity[k]))
+      return fail(LBM_EINVAL, "non-finite path sample " + std::to_string(k / 3));
+  if (d->moving) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
+  double lo_c[3], hi_c[3];
+  for (int a = 0; a < 3; ++a) {
+    lo_c[a] = hi_c[a] = centre[a];
+    for (int64_t k = 1; k < n_samples; ++k) {
+      lo_c[a] = std::min(lo_c[a], centre[3 * k + a]);
+      hi_c[a] = std::max(hi_c[a], centre[3 * k + a]);
+    }
+  }
+  d->path_c.assign(centre, centre + 3 * n_samples);
+  d->path_v.assign(velocity, velocity + 3 * n_samples);
+  const int e = install_moving(d, lo_c, hi_c, radius, omega, variant, q_cutoff);
+  if (e != LBM_OK && !d->moving) {
+    d->path_c.clear();
+    d->path_v.clear();
+  }
+  return e;
+}
 
 int lbm_step(lbm_domain d, int32_t n_steps) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   if (n_steps < 0) return fail(LBM_EINVAL, "n_steps < 0");
   if (!d->links_ok) return fail(LBM_ESTATE, "boundary links not set: some populations would be missing");
+  if (n_steps > path_steps_left(d))
+    return fail(LBM_ESTATE, "the sphere's path ends after " + std::to_string(path_steps_left(d)) + " more steps");
   for (int32_t s = 0; s < n_steps; ++s) {
     StepParams p = step_params(d, d->cur);
     hipError_t e = launch_step(d->desc.lattice, d->skind, p, d->stream);

@@ -600,6 +600,10 @@ int lbm_batch_step(lbm_batch b, const lbm_domain* ds, int32_t n, int32_t n_steps
   if (int e = check_members(b, ds, n)) return e;
   if (n_steps < 0) return bfail(LBM_EINVAL, "n_steps < 0");
   if (n == 0 || n_steps == 0) return LBM_OK;
+  for (int32_t k = 0; k < n; ++k)
+    if (n_steps > path_steps_left(ds[k]))
+      return bfail(LBM_ESTATE, "domain " + std::to_string(k) + ": the sphere's path ends after " +
+                                   std::to_string(path_steps_left(ds[k])) + " more steps");
   if (int e = prepare(b, ds, n)) return e;
   if (b->autotune) {
     bool known = true;

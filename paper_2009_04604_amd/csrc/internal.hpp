@@ -327,6 +327,7 @@ struct lbm_domain_s {
   // moving sphere (lbm_set_moving_sphere)
   bool moving;
   double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
+  std::vector<double> path_c, path_v;  // [n][3] prescribed centre and velocity per step (empty: the sinusoid)
   int32_t* reg_seg;
   int64_t nreg;
   uint64_t* seg_prev;
@@ -352,6 +353,8 @@ namespace lbm {
 StepParams step_params(const lbm_domain_s* d, int cur);
 MovingParams moving_params(const lbm_domain_s* d, int cur);
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t);
+// Steps left on a sphere's sampled path (INT64_MAX without one).
+int64_t path_steps_left(const lbm_domain_s* d);
 // Identity for caches of kernel parameters (a freed domain's address can be
 // reused by a new one; links or a stream set anew also change the uid).
 uint64_t next_uid();

@@ -107,3 +107,110 @@ def test_moving_sphere_force_and_torque_match_oracle(gpu_lib, storage, tol):
         static.set_force_tracking(True)                   # static links: lbm_force_torque
     assert e.value.code == B.LBM_ESTATE
     static.close()
+
+
+def _circle_path(n_samples, c0=(20.2, 19.6, 20.4), R=3.5, period=50.0):
+    """A sphere carried round a circle in a tilted plane: samples of the centre
+    and of its velocity (the exact derivative) per step."""
+    t = np.arange(n_samples, dtype=np.float64)
+    w = 2.0 * np.pi / period
+    e1 = np.array([1.0, 0.0, 0.0])
+    e2 = np.array([0.0, 0.8, 0.6])
+    C = np.asarray(c0)[None, :] + R * (np.cos(w * t)[:, None] * e1 + np.sin(w * t)[:, None] * e2)
+    V = R * w * (-np.sin(w * t)[:, None] * e1 + np.cos(w * t)[:, None] * e2)
+    return C, V
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_sampled_path_matches_oracle(gpu_lib, storage, tol):
+    """lbm_set_moving_sphere_path: a circular path (not the sinusoid) against the
+    oracle driven by the same samples; identical fluid and link sets."""
+    B = gpu_lib
+    n, steps = 40, 30
+    C, V = _circle_path(steps + 2)
+    om = (0.001, 0.002, -0.0015)
+    _say("case sampled circular path 40^3", storage)
+    d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    d.set_moving_sphere_path(5.7, om, C, V)
+    m = moving.MovingSphereSim(G.Domain(OL.D3Q19, n, n, n), 5.7, moving.SampledKinematics(C, V, om), 0.8)
+    fresh_seen = 0
+    for block in range(6):
+        d.step(5)
+        for _ in range(5):
+            prev = m.sim.fluid.copy()
+            m.step()
+            fresh_seen += int((m.sim.fluid & ~prev).sum())
+        info = d.info()
+        assert info["n_fluid"] == int(m.sim.fluid.sum())
+        assert info["n_links"] == m.sim.links["node"].size
+        _, u_g, _, unstable = d.macros()
+        assert not unstable
+        _, u_o = m.sim.macros()
+        fl = m.sim.fluid
+        err = np.linalg.norm(u_g[fl] - u_o[:, fl].T) / np.linalg.norm(u_o[:, fl])
+        _say("t", m.t, "rel L2 velocity", err)
+        assert err <= tol
+    assert fresh_seen > 0
+    # the path is used up: a further step is refused, the state stays
+    with pytest.raises(B.LBMError) as e:
+        d.step(1)
+    assert e.value.code == B.LBM_ESTATE
+    assert d.info()["steps_done"] == steps
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s-sr"])
+def test_sampled_sinusoid_equals_parametric_motion(gpu_lib, storage):
+    """The sinusoid's own samples through lbm_set_moving_sphere_path give, to the
+    bit, what lbm_set_moving_sphere gives, alone and in a batch; a batch call
+    longer than a member's path is refused."""
+    B = gpu_lib
+    c = _case()
+    n, steps = c["n"], 40
+    kin = moving.Kinematics(c["x0"], c["amplitude"], c["period"], c["direction"], c["omega"])
+    C = np.array([kin.centre(t) for t in range(steps + 2)])
+    V = np.array([kin.velocity(t) for t in range(steps + 2)])
+
+    def path_domain():
+        d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), c["tau"], storage=storage, layout="dense")
+        d.set_moving_sphere_path(c["radius"], c["omega"], C, V)
+        return d
+    a = _gpu(B, c, storage)
+    p = path_domain()
+    q = path_domain()
+    a.step(steps)
+    p.step(steps)
+    b = B.Batch()
+    b.step([q], 25)
+    with pytest.raises(B.LBMError) as e:
+        b.step([q], steps - 25 + 1)
+    assert e.value.code == B.LBM_ESTATE
+    b.step([q], steps - 25)
+    b.close()
+    fa, fp, fq = a.get_state(), p.get_state(), q.get_state()
+    assert np.array_equal(fa, fp) and np.array_equal(fa, fq)
+    for d in (a, p, q):
+        d.close()
+
+
+def test_sampled_path_validation(gpu_lib):
+    B = gpu_lib
+    n = 24
+    C, V = _circle_path(10, c0=(12.0, 12.0, 12.0), R=2.0)
+
+    def fresh(layout="dense"):
+        return B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage="f32", layout=layout)
+    for args, code in [((3.0, (0, 0, 0), C[:1], V[:1]), B.LBM_EINVAL),          # one sample
+                       ((0.0, (0, 0, 0), C, V), B.LBM_EINVAL),                  # radius
+                       ((3.0, (0, 0, 0), C + np.array([0, 0, 1e300 * 1e10]), V), B.LBM_EINVAL),   # non-finite
+                       ((10.5, (0, 0, 0), C, V), B.LBM_EINVAL)]:                # sweep too large for the box
+        d = fresh()
+        with pytest.raises(B.LBMError) as e:
+            d.set_moving_sphere_path(*args)
+        assert e.value.code == code
+        d.close()
+    d = fresh("compact")
+    with pytest.raises(B.LBMError) as e:
+        d.set_moving_sphere_path(3.0, (0, 0, 0), C, V)
+    assert e.value.code == B.LBM_ESTATE
+    d.close()

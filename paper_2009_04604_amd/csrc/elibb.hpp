@@ -87,15 +87,15 @@ __device__ __forceinline__ Coef<T> elibb_coefficients_fast(int variant, T q, T q
   const T one = T(1), two = T(2), half = T(0.5);
   const T tq1 = two * q - one;                 // 2q - 1
   const T omq = one - q;                       // 1 - q
-  const T rq = fast_recip(q);
-  const T rom = fast_recip(omq > T(0) ? omq : one);
   const bool lo = q < half;
+  // one reciprocal: 1 / (1 - q) below 1/2, 1 / q from 1/2 on (both >= 1/2)
+  const T r = fast_recip(lo ? omq : q);
   // linear (ELIBB-F) weights
-  const T fa4 = lo ? -tq1 * rom : T(0);
-  const T fa2 = lo ? q * rom : omq * rq;
-  const T fa5 = lo ? T(0) : tq1 * rq;
-  // quadratic weights: UQ everywhere, FQ below 1/2
-  const T r2 = rq * rq;
+  const T fa4 = lo ? -tq1 * r : T(0);
+  const T fa2 = lo ? q * r : omq * r;
+  const T fa5 = lo ? T(0) : tq1 * r;
+  // quadratic weights: UQ everywhere, FQ below 1/2 (r2 = 1 / q^2 where used)
+  const T r2 = r * r;
   const bool fq_hi = (variant == FQ) && !lo;
   const T qa4 = fq_hi ? T(0) : -tq1;
   const T qa2 = fq_hi ? omq * half * r2 : one;

@@ -631,8 +631,12 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   // byte distance between direction arrays; the direction bases below are
   // advanced by it in scalar registers (a running sum, no multiplies)
   const uint64_t npb = (uint64_t)np * sizeof(T);
+  // In the compact layout every lane pulls: the slots formed for a lane that is
+  // not fluid (or lies past the row's end) stay inside the population array
+  // (between the guard's last slot and the last fluid slot + 1, which the
+  // array holds), so no branch and no zero fill; such a lane stores nothing.
   R h[L::Q];
-  if (fluid) {
+  if (COMPACT || fluid) {
     uint64_t qb = uniform_u64(reinterpret_cast<uint64_t>(src));
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -644,7 +648,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   if (has_links && list_mode) patch_links<L, R, 2>(h, stage, bnd, tid, wbase, lb0, lb1, si.lane, lk.lld, lvi, ldp, vp);
 
   Moments<R> m;
-  if (!fluid) {
+  if (!COMPACT && !fluid) {
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) h[i] = R(0);
   }

@@ -357,7 +357,38 @@ void check_source_rows(const Built& b) {
           ++checked;
         }
       }
-  std::printf("source rows ok %lld\n", (long long)checked);
+  // every lane of every segment (also lanes that are not fluid and lanes past
+  // the row's end, which the compact step lets pull too) and every direction
+  // (also cut links) reads inside the population array
+  const int64_t npad = (lbm::GUARD + nf + 1 + 63) / 64 * 64;
+  int64_t ranged = 0;
+  for (int z = 0; z < g.n[2]; ++z)
+    for (int y = 0; y < g.n[1]; ++y)
+      for (int64_t sx = 0; sx < nsx; ++sx)
+        for (int lane = 0; lane < lbm::SEG; ++lane) {
+          const int64_t r = y + (int64_t)g.n[1] * z, x = sx * lbm::SEG + lane;
+          const bool edge = sx == 0 || sx == nsx - 1, wrap = edge && g.per[0];
+          const bool xlo = edge && x == 0, xhi = edge && x == g.n[0] - 1;
+          for (int i = 0; i < Q; ++i) {
+            int c[3];
+            direction(b.lattice, i, c);
+            const int k = b.lattice == LBM_D2Q9 ? 1 + c[1] : 3 * (1 + c[1]) + (1 + c[2]);
+            const int64_t seg = rows[r * nr + k] + sx;
+            CHECK(seg >= 0 && seg < g.nseg, "source segment out of range");
+            const uint64_t fm = fluid[seg];
+            const int64_t f0 = fbase[seg] + lbm::GUARD, s0 = seg - sx;
+            const int64_t ed = sx == 0 ? fbase[s0 + nsx] + lbm::GUARD - 1 : fbase[s0] + lbm::GUARD;
+            const uint64_t below = lane ? (fm & ((1ull << lane) - 1)) : 0;
+            const int64_t P = f0 + __builtin_popcountll(below);
+            const int64_t B = (int64_t)((fm >> lane) & 1ull);
+            const int64_t lo = wrap ? ed : P, hi = wrap ? (nsx == 1 ? f0 : ed) : P;
+            const int64_t got = c[0] == 0 ? P : (c[0] == 1 ? (xlo ? lo : P - 1) : (xhi ? hi : P + B));
+            CHECK(got >= 0 && got < npad, "pull of lane %d segment %lld dir %d at slot %lld outside [0, %lld)", lane,
+                  (long long)seg, i, (long long)got, (long long)npad);
+            ++ranged;
+          }
+        }
+  std::printf("source rows ok %lld in range %lld\n", (long long)checked, (long long)ranged);
 }
 
 }  // namespace

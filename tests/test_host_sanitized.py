@@ -11,6 +11,7 @@ also compared, to the bit, with the production library's (hipcc build) on the
 same shapes."""
 import os
 import shutil
+import re
 import subprocess
 
 import numpy as np
@@ -154,6 +155,9 @@ def test_host_library_under_sanitizers(driver, tmp_path):
     assert "FAIL" not in r.stdout
     assert r.stdout.count("plan ok") == 15
     assert r.stdout.count("source rows ok") == 15
+    # every lane of every segment pulls inside the population array (the
+    # compact step lets lanes that are not fluid pull as well)
+    assert len(re.findall(r"source rows ok \d+ in range [1-9]\d*", r.stdout)) == 15
     # the sanitized build agrees with the production library to the bit
     for prefix, case in s.cases:
         mask, links = _production(B, case)

@@ -132,6 +132,12 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   p.rng_ctr = d->rng_ctr;
   p.parity = cur;
   p.wall_neq = d->wall_neq;
+  p.omega_f = (float)p.omega;
+  p.omega_minus_f = (float)p.omega_minus;
+  for (int a = 0; a < 3; ++a) p.force_f[a] = (float)p.force[a];
+  p.src_eq_f = (float)p.src_eq;
+  p.src_eq_minus_f = (float)p.src_eq_minus;
+  p.q_cut_f = (float)p.q_cut;
   return p;
 }
 

@@ -136,6 +136,10 @@ struct StepParams {
   uint32_t* rng_ctr;             // stochastic rounding: the domain's step count, by buffer parity
                                  // ([parity] is read, block 0 writes [1 - parity] = [parity] + 1)
   int32_t parity;                // buffer holding the current state (the domain's cur)
+  // omega, omega-, force, src_eq, src_eq_minus and q_cut rounded to FP32 on the
+  // host (the FP32 and 16-bit kernels read these instead of converting the
+  // doubles in every wave; the values are the same)
+  float omega_f, omega_minus_f, force_f[3], src_eq_f, src_eq_minus_f, q_cut_f;
 };
 
 struct InitParams {

@@ -588,15 +588,20 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   const int wbase = tid & ~(SEG - 1);
   const bool list_mode = lk.lv_out != nullptr;
 
+  // parameters: the doubles (FP64 kernels) or their FP32 roundings
+  auto prm = [](double d, float f) -> R {
+    if constexpr (sizeof(R) == 4) return f;
+    else return R(d);
+  };
   Collider<R, TRT> col;
-  col.omega = R(p.omega);
+  col.omega = prm(p.omega, p.omega_f);
   col.kf = R(1) - R(0.5) * col.omega;
-  col.omega_m = R(p.omega_minus);
-  col.Fx = R(p.force[0]);
-  col.Fy = R(p.force[1]);
-  col.Fz = R(p.force[2]);
-  col.src_eq = R(p.src_eq);
-  col.src_eq_m = R(p.src_eq_minus);
+  col.omega_m = prm(p.omega_minus, p.omega_minus_f);
+  col.Fx = prm(p.force[0], p.force_f[0]);
+  col.Fy = prm(p.force[1], p.force_f[1]);
+  col.Fz = prm(p.force[2], p.force_f[2]);
+  col.src_eq = prm(p.src_eq, p.src_eq_f);
+  col.src_eq_m = prm(p.src_eq_minus, p.src_eq_minus_f);
   col.force = p.has_force != 0;
 
   // segments without boundary nodes have no links (and need not read seg_lbase)
@@ -698,7 +703,7 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   if (has_links) {
     wave_lds_sync();
     const int xseg = c.x - si.lane;
-    const R qc = R(p.q_cut);
+    const R qc = prm(p.q_cut, p.q_cut_f);
     auto rebuild = [&](int k, int ld, R q, R gw) {
       const int nl = ld & (SEG - 1);
       const int i = ld >> 8;

@@ -362,13 +362,16 @@ struct DenseIndex {
   }
 };
 
+// A lane past the row's end (x >= nx) takes the indices of the row's last node,
+// so that every lane of a wave may pull (such a lane stores nothing).
 __device__ __forceinline__ DenseIndex dense_index(const GridGeom& g, Coords c) {
   const uint32_t NX = (uint32_t)g.NX, NXY = (uint32_t)g.NX * (uint32_t)g.NY;
   const int o = g.outlet;
+  const int x = c.x < g.nx ? c.x : g.nx - 1;
   DenseIndex p;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {   // k = 1 + c, the source of direction c is x - c
-    p.xs[k] = (uint32_t)(axis_src(c.x, k - 1, g.nx, g.perx, o == 0, o == 1) + g.px);
+    p.xs[k] = (uint32_t)(axis_src(x, k - 1, g.nx, g.perx, o == 0, o == 1) + g.px);
     p.ys[k] = (uint32_t)(axis_src(c.y, k - 1, g.ny, g.pery, o == 2, o == 3) + g.py) * NX;
     p.zs[k] = (uint32_t)(axis_src(c.z, k - 1, g.nz, g.perz, o == 4, o == 5) + g.pz) * NXY;
   }
@@ -636,12 +639,15 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   // byte distance between direction arrays; the direction bases below are
   // advanced by it in scalar registers (a running sum, no multiplies)
   const uint64_t npb = (uint64_t)np * sizeof(T);
-  // In the compact layout every lane pulls: the slots formed for a lane that is
-  // not fluid (or lies past the row's end) stay inside the population array
-  // (between the guard's last slot and the last fluid slot + 1, which the
-  // array holds), so no branch and no zero fill; such a lane stores nothing.
+  // Every lane pulls, so that no branch and no zero fill are needed: in the
+  // compact layout the slots formed for a lane that is not fluid (or lies past
+  // the row's end) stay inside the population array (between the guard's last
+  // slot and the last fluid slot + 1, which the array holds); in the dense
+  // layout a solid lane reads its neighbours and a lane past the row's end
+  // those of the row's last node.  Such lanes store nothing that is read (the
+  // dense layout's list mode stores zeros from them).
   R h[L::Q];
-  if (COMPACT || fluid) {
+  {
     uint64_t qb = uniform_u64(reinterpret_cast<uint64_t>(src));
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -653,10 +659,6 @@ __device__ __forceinline__ void step_body(const StepParams& p, uint32_t block) {
   if (has_links && list_mode) patch_links<L, R, 2>(h, stage, bnd, tid, wbase, lb0, lb1, si.lane, lk.lld, lvi, ldp, vp);
 
   Moments<R> m;
-  if (!COMPACT && !fluid) {
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) h[i] = R(0);
-  }
   m = moments<L, R>(h, col.Fx, col.Fy, col.Fz);
   // boundary nodes leave their moments (and, in slot mode, their pre-collision
   // populations) for the link phase

@@ -73,7 +73,9 @@ struct Storage<ST_F16SR> : Storage<ST_F16S> {
   static constexpr bool stochastic = true;
   template <class L>
   __device__ __forceinline__ static void store(T* p, R v, int, uint32_t rnd) {
-    const sr_f16x2 r = __builtin_amdgcn_cvt_sr_f16_f32(sr_f16x2{}, v, rnd, false);
+    // only the low half is stored, so the other half may hold anything: it is
+    // v's own bits, which lets the conversion overwrite v's register in place
+    const sr_f16x2 r = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(sr_f16x2, v), v, rnd, false);
     *reinterpret_cast<uint16_t*>(p) = __builtin_bit_cast(uint16_t, r[0]);
   }
 };
@@ -83,7 +85,7 @@ struct Storage<ST_BF16SR> : Storage<ST_BF16S> {
   static constexpr bool stochastic = true;
   template <class L>
   __device__ __forceinline__ static void store(T* p, R v, int, uint32_t rnd) {
-    const sr_bf16x2 r = __builtin_amdgcn_cvt_sr_bf16_f32(sr_bf16x2{}, v, rnd, false);
+    const sr_bf16x2 r = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(sr_bf16x2, v), v, rnd, false);
     *reinterpret_cast<uint16_t*>(p) = __builtin_bit_cast(uint16_t, r[0]);
   }
 };

@@ -194,6 +194,16 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
 int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
                                const double* centre, const double* velocity, int32_t variant, double q_cutoff);
 
+/* The same, with the angular velocity sampled too (omega: host array
+ * [n_samples][3], copied): the geometry of time t takes the wall velocities
+ * u_w(t) = V(t) + Omega(t) x r and u_w(t+1) = V(t+1) + Omega(t+1) x r at each
+ * link's wall point (r from the centre at t), the refill and the force the
+ * rigid-body velocity V(t) + Omega(t) x r.  Constant samples reproduce
+ * lbm_set_moving_sphere_path to the bit.  Errors as lbm_set_moving_sphere_path
+ * (LBM_EINVAL also for a non-finite Omega sample). */
+int lbm_set_moving_sphere_motion(lbm_domain d, double radius, int64_t n_samples, const double* centre,
+                                 const double* velocity, const double* omega, int32_t variant, double q_cutoff);
+
 /* Advance n_steps >= 0 time steps; asynchronous on the domain's stream.  Each
  * step is the lattice Boltzmann equation of Sec. II.A (eq. LBE) split into the
  * local collision -- BGK (eq. LB-BGK) with the second-order equilibrium (eq.

@@ -4,19 +4,22 @@ Jeffery-orbit study of Sec. III.C uses moving objects with refilled fresh nodes)
 Kinematics (prescribed, not computed from forces): centre
 x_c(t) = x_0 + A sin(2 pi t / T) e, translational velocity
 V(t) = A (2 pi / T) cos(2 pi t / T) e, constant angular velocity Omega; or a
-path of any form given by samples of x_c and V per step (SampledKinematics).
+path of any form given by samples of x_c, V and optionally Omega per step
+(SampledKinematics).
 
 One step t -> t+1 (readings, listed in the design notes):
 1. geometry(t): fluid nodes and cut links of the sphere at x_c(t);
-   u_w(t) = V(t) + Omega x (x_W - x_c(t)) and
-   u_w(t+1) = V(t+1) + Omega x (x_W - x_c(t)) at each link's wall point;
+   u_w(t) = V(t) + Omega(t) x (x_W - x_c(t)) and
+   u_w(t+1) = V(t+1) + Omega(t+1) x (x_W - x_c(t)) at each link's wall point;
 2. nodes fluid at t but solid at t-1 are refilled with
-   f^eq(rho_bar, V(t) + Omega x (x - x_c(t))) before the step;
+   f^eq(rho_bar, V(t) + Omega(t) x (x - x_c(t))) before the step;
 3. the ordinary step with that geometry.
 
 Status: pinned -- V(t) against central differences of x_c(t) over a period and
 its closed values at t = 0 and T/4; a sampled path against the sinusoid it
-samples and against the co-moving invariant on a straight path; the refill
+samples and against the co-moving invariant on a straight path; a sampled spin
+against the constant spin it repeats, its time index (an impulsive spin-up
+moves the walls at t+1 only) and the mirror symmetry of a reversed spin; the refill
 rule against hand-listed
 neighbour sets (tests/test_oracle_refill.py); the co-moving invariant (a sphere
 moving at the velocity of a uniform flow leaves it unchanged, refills
@@ -42,24 +45,38 @@ class Kinematics:
     def velocity(self, t):
         return self.A * (2.0 * np.pi / self.T) * np.cos(2.0 * np.pi * t / self.T) * self.e
 
+    def omega(self, t):
+        return self.Omega.copy()
+
 
 class SampledKinematics:
     """A prescribed path given by samples: x_c(t) = centre[t], V(t) =
-    velocity[t] at integer steps t (arrays [n][3]), constant angular velocity.
-    The step of MovingSphereSim asks for x_c(t), V(t) and V(t+1) only, so n
-    samples drive n - 2 steps."""
+    velocity[t] at integer steps t (arrays [n][3]); the angular velocity is
+    constant (omega of 3 values) or sampled too (omega [n][3]).  The step of
+    MovingSphereSim asks for x_c(t), V(t), V(t+1), Omega(t) and Omega(t+1)
+    only, so n samples drive n - 2 steps."""
 
     def __init__(self, centre, velocity, omega):
         self.C = np.asarray(centre, dtype=np.float64).reshape(-1, 3)
         self.V = np.asarray(velocity, dtype=np.float64).reshape(-1, 3)
         assert self.C.shape == self.V.shape and self.C.shape[0] >= 2
-        self.Omega = np.asarray(omega, dtype=np.float64)
+        om = np.asarray(omega, dtype=np.float64)
+        if om.size == 3:
+            self.W = None
+            self.Omega = om.reshape(3)
+        else:
+            self.W = om.reshape(-1, 3)
+            assert self.W.shape == self.C.shape
+            self.Omega = None
 
     def centre(self, t):
         return self.C[int(t)].copy()
 
     def velocity(self, t):
         return self.V[int(t)].copy()
+
+    def omega(self, t):
+        return self.Omega.copy() if self.W is None else self.W[int(t)].copy()
 
 
 class MovingSphereSim:
@@ -75,13 +92,13 @@ class MovingSphereSim:
     def geometry(self, t):
         k = self.kin
         c_t = k.centre(t)
-        sph = G.Sphere(c_t, self.radius, True, V=k.velocity(t), Omega=k.Omega)
+        sph = G.Sphere(c_t, self.radius, True, V=k.velocity(t), Omega=k.omega(t))
         fluid = G.classify(self.dom, [sph])
-        V1 = k.velocity(t + 1)
+        V1, Om1 = k.velocity(t + 1), k.omega(t + 1)
 
         def uw1(shape, xw):
             r = self.dom.min_image(xw - c_t[:, None])
-            return V1[:, None] + np.cross(k.Omega, r.T).T
+            return V1[:, None] + np.cross(Om1, r.T).T
         links = G.cut_links(self.dom, fluid, [sph], uw_t1_fn=uw1)
         return fluid, links, sph
 

@@ -142,19 +142,25 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
 }
 
 // Kinematics of the moving sphere for the geometry of time t: centre
-// x0 + A sin(2 pi t / T) e and its velocity at t and t + 1.
+// x0 + A sin(2 pi t / T) e and its velocity at t and t + 1, or the samples of a
+// prescribed path; angular velocity at t and t + 1 (constant unless sampled).
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   MovingKin k{};
+  for (int a = 0; a < 3; ++a) k.Om[a] = k.Om1[a] = d->mv_om[a];
   if (!d->path_c.empty()) {
-    // a sampled path: the geometry of time t needs x_c(t), V(t) and V(t+1); a
-    // time past the path (only in rows of a kinematics table that no step
-    // uses) takes its last pair of samples
+    // a sampled path: the geometry of time t needs x_c(t), V(t), V(t+1) and,
+    // when sampled, Omega(t), Omega(t+1); a time past the path (only in rows of
+    // a kinematics table that no step uses) takes its last pair of samples
     const int64_t n = (int64_t)d->path_c.size() / 3;
     const int64_t tt = std::min<int64_t>(std::max<int64_t>(t, 0), n - 2);
     for (int a = 0; a < 3; ++a) {
       k.c[a] = d->path_c[3 * tt + a];
       k.V[a] = d->path_v[3 * tt + a];
       k.V1[a] = d->path_v[3 * (tt + 1) + a];
+      if (!d->path_om.empty()) {
+        k.Om[a] = d->path_om[3 * tt + a];
+        k.Om1[a] = d->path_om[3 * (tt + 1) + a];
+      }
     }
     if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
     return k;
@@ -184,7 +190,6 @@ int64_t path_steps_left(const lbm_domain_s* d) {
 MovingParams moving_params(const lbm_domain_s* d, int cur) {
   MovingParams mp{};
   mp.g = d->g;
-  for (int a = 0; a < 3; ++a) mp.Om[a] = d->mv_om[a];
   mp.r = d->mv_r;
   mp.variant = d->variant;
   mp.q_cut = d->q_cut;
@@ -627,18 +632,22 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   d->mv_period = period;
   d->path_c.clear();
   d->path_v.clear();
+  d->path_om.clear();
   return install_moving(d, lo_c, hi_c, radius, omega, variant, q_cutoff);
 }
 
-int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
-                               const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
-  if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
+namespace {
+// A sphere on a sampled path: centre and velocity per step, angular velocity
+// constant (omega) or per step (omega_path, [n][3]).
+int set_moving_path(lbm_domain d, double radius, const double* omega, const double* omega_path, int64_t n_samples,
+                    const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
   if (!(radius > 0.0) || !std::isfinite(radius)) return fail(LBM_EINVAL, "radius must be finite and > 0");
   if (n_samples < 2) return fail(LBM_EINVAL, "a path needs at least 2 samples");
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite omega");
+  if (omega)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite omega");
   for (int64_t k = 0; k < 3 * n_samples; ++k)
-    if (!std::isfinite(centre[k]) || !std::isfinite(velocity[k]))
+    if (!std::isfinite(centre[k]) || !std::isfinite(velocity[k]) || (omega_path && !std::isfinite(omega_path[k])))
       return fail(LBM_EINVAL, "non-finite path sample " + std::to_string(k / 3));
   if (d->moving) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
   double lo_c[3], hi_c[3];
@@ -651,12 +660,29 @@ int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3
   }
   d->path_c.assign(centre, centre + 3 * n_samples);
   d->path_v.assign(velocity, velocity + 3 * n_samples);
-  const int e = install_moving(d, lo_c, hi_c, radius, omega, variant, q_cutoff);
+  if (omega_path) d->path_om.assign(omega_path, omega_path + 3 * n_samples);
+  else d->path_om.clear();
+  const double zero[3] = {0.0, 0.0, 0.0};
+  const int e = install_moving(d, lo_c, hi_c, radius, omega ? omega : zero, variant, q_cutoff);
   if (e != LBM_OK && !d->moving) {
     d->path_c.clear();
     d->path_v.clear();
+    d->path_om.clear();
   }
   return e;
+}
+}  // namespace
+
+int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
+                               const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
+  if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
+  return set_moving_path(d, radius, omega, nullptr, n_samples, centre, velocity, variant, q_cutoff);
+}
+
+int lbm_set_moving_sphere_motion(lbm_domain d, double radius, int64_t n_samples, const double* centre,
+                                 const double* velocity, const double* omega, int32_t variant, double q_cutoff) {
+  if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
+  return set_moving_path(d, radius, nullptr, omega, n_samples, centre, velocity, variant, q_cutoff);
 }
 
 int lbm_step(lbm_domain d, int32_t n_steps) {

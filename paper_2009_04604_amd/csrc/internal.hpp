@@ -186,6 +186,7 @@ struct ForceParams {
 struct MovingKin {
   double c[3];                   // centre at t
   double V[3], V1[3];            // translational velocity at t and t+1
+  double Om[3], Om1[3];          // angular velocity at t and t+1
 };
 
 // One moving sphere (dense layout, slot mode): the geometry of time t is rebuilt
@@ -193,7 +194,7 @@ struct MovingKin {
 struct MovingParams {
   GridGeom g;
   MovingKin k;                   // single-domain launches; batched launches read a table
-  double r, Om[3];               // radius, angular velocity
+  double r;                      // radius
   int32_t kin_slot;              // batched launches: column of this sphere in the table
   int32_t variant;
   double q_cut;
@@ -332,6 +333,7 @@ struct lbm_domain_s {
   bool moving;
   double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
   std::vector<double> path_c, path_v;  // [n][3] prescribed centre and velocity per step (empty: the sinusoid)
+  std::vector<double> path_om;         // [n][3] angular velocity per step (empty: constant mv_om)
   int32_t* reg_seg;
   int64_t nreg;
   uint64_t* seg_prev;

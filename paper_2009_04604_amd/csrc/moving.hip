@@ -82,11 +82,11 @@ __device__ __forceinline__ double crossing(const MovingParams& p, int x, int y, 
 }
 
 // rigid-body velocity V + Omega x r, r the minimum image of x - centre(t)
-__device__ __forceinline__ void body_velocity(const MovingParams& p, const double (&V)[3], const double (&r)[3],
+__device__ __forceinline__ void body_velocity(const double (&Om)[3], const double (&V)[3], const double (&r)[3],
                                               double (&u)[3]) {
-  u[0] = __dadd_rn(V[0], __dsub_rn(__dmul_rn(p.Om[1], r[2]), __dmul_rn(p.Om[2], r[1])));
-  u[1] = __dadd_rn(V[1], __dsub_rn(__dmul_rn(p.Om[2], r[0]), __dmul_rn(p.Om[0], r[2])));
-  u[2] = __dadd_rn(V[2], __dsub_rn(__dmul_rn(p.Om[0], r[1]), __dmul_rn(p.Om[1], r[0])));
+  u[0] = __dadd_rn(V[0], __dsub_rn(__dmul_rn(Om[1], r[2]), __dmul_rn(Om[2], r[1])));
+  u[1] = __dadd_rn(V[1], __dsub_rn(__dmul_rn(Om[2], r[0]), __dmul_rn(Om[0], r[2])));
+  u[2] = __dadd_rn(V[2], __dsub_rn(__dmul_rn(Om[0], r[1]), __dmul_rn(Om[1], r[0])));
 }
 
 // cut directions of the fluid node (x, y, z): source x - c_i inside the sphere
@@ -203,8 +203,8 @@ __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
     rel(p, xw[0], xw[1], xw[2], r);
     double u0[3], u1[3];
     const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]}, V1[3] = {p.k.V1[0], p.k.V1[1], p.k.V1[2]};
-    body_velocity(p, V, r, u0);
-    body_velocity(p, V1, r, u1);
+    body_velocity(p.k.Om, V, r, u0);
+    body_velocity(p.k.Om1, V1, r, u1);
     if (L::D == 2) u0[2] = u1[2] = 0.0;
     const double cu0 = cx * u0[0] + cy * u0[1] + cz * u0[2];
     const double cu1 = cx * u1[0] + cy * u1[1] + cz * u1[2];
@@ -269,7 +269,7 @@ __device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave)
   double r[3], u[3];
   rel(p, (double)s.x, (double)s.y, (double)s.z, r);
   const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
-  body_velocity(p, V, r, u);
+  body_velocity(p.k.Om, V, r, u);
   if (L::D == 2) u[2] = 0.0;
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -333,7 +333,7 @@ __device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, 
     double r[3], u[3];
     rel(p, x - q * cx, s.y - q * cy, s.z - q * cz, r);
     const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
-    body_velocity(p, V, r, u);
+    body_velocity(p.k.Om, V, r, u);
     if (L::D == 2) u[2] = r[2] = 0.0;
     const double c[3] = {(double)cx, (double)cy, (double)cz};
     double F[3];

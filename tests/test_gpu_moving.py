@@ -193,6 +193,101 @@ def test_sampled_sinusoid_equals_parametric_motion(gpu_lib, storage):
         d.close()
 
 
+def _spin_up(n_samples, W=0.004, ramp=8):
+    """Angular velocity per step: a tilted axis whose spin ramps up over `ramp`
+    steps from rest."""
+    t = np.arange(n_samples, dtype=np.float64)
+    Om = np.zeros((n_samples, 3))
+    Om[:, 0] = 0.25 * W * np.minimum(t, ramp) / ramp
+    Om[:, 2] = W * np.minimum(t, ramp) / ramp
+    return Om
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_sampled_spin_matches_oracle(gpu_lib, storage, tol):
+    """lbm_set_moving_sphere_motion: the circular path with an angular velocity
+    that spins up from rest, against the oracle driven by the same samples."""
+    B = gpu_lib
+    n, steps = 40, 30
+    C, V = _circle_path(steps + 2)
+    Om = _spin_up(steps + 2)
+    _say("case sampled spin-up on a circular path 40^3", storage)
+    d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    d.set_moving_sphere_motion(5.7, C, V, Om)
+    m = moving.MovingSphereSim(G.Domain(OL.D3Q19, n, n, n), 5.7, moving.SampledKinematics(C, V, Om), 0.8)
+    for block in range(6):
+        d.step(5)
+        m.run(5)
+        info = d.info()
+        assert info["n_fluid"] == int(m.sim.fluid.sum())
+        assert info["n_links"] == m.sim.links["node"].size
+        _, u_g, _, unstable = d.macros()
+        assert not unstable
+        _, u_o = m.sim.macros()
+        fl = m.sim.fluid
+        err = np.linalg.norm(u_g[fl] - u_o[:, fl].T) / np.linalg.norm(u_o[:, fl])
+        _say("t", m.t, "rel L2 velocity", err)
+        assert err <= tol
+    with pytest.raises(B.LBMError) as e:
+        d.step(1)
+    assert e.value.code == B.LBM_ESTATE
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s-sr"])
+def test_constant_spin_samples_equal_the_path_form(gpu_lib, storage):
+    """A sampled spin whose samples all equal the constant gives, to the bit,
+    what lbm_set_moving_sphere_path gives; a sampled spin-up gives the same
+    alone and in a batch."""
+    B = gpu_lib
+    n, steps = 40, 24
+    C, V = _circle_path(steps + 2)
+    om = np.array([0.001, 0.002, -0.0015])
+
+    def dom():
+        return B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    p = dom()
+    p.set_moving_sphere_path(5.7, om, C, V)
+    q = dom()
+    q.set_moving_sphere_motion(5.7, C, V, np.repeat(om[None, :], steps + 2, 0))
+    a = dom()
+    a.set_moving_sphere_motion(5.7, C, V, _spin_up(steps + 2))
+    b = dom()
+    b.set_moving_sphere_motion(5.7, C, V, _spin_up(steps + 2))
+    p.step(steps)
+    q.step(steps)
+    a.step(steps)
+    bt = B.Batch()
+    bt.step([b], 10)
+    bt.step([b], steps - 10)
+    bt.close()
+    assert np.array_equal(p.get_state(), q.get_state())
+    fa, fb = a.get_state(), b.get_state()
+    assert np.array_equal(fa, fb)
+    assert not np.array_equal(fa, p.get_state())
+    for d in (p, q, a, b):
+        d.close()
+
+
+def test_sampled_spin_validation(gpu_lib):
+    B = gpu_lib
+    n = 24
+    C, V = _circle_path(10, c0=(12.0, 12.0, 12.0), R=2.0)
+    Om = _spin_up(10)
+    Om[4, 1] = np.inf
+    d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage="f32", layout="dense")
+    with pytest.raises(B.LBMError) as e:
+        d.set_moving_sphere_motion(3.0, C, V, Om)
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(ValueError):
+        d.set_moving_sphere_motion(3.0, C, V, Om[:5])
+    d.set_moving_sphere_motion(3.0, C, V, _spin_up(10))
+    with pytest.raises(B.LBMError) as e:      # once per domain
+        d.set_moving_sphere_motion(3.0, C, V, _spin_up(10))
+    assert e.value.code == B.LBM_ESTATE
+    d.close()
+
+
 def test_sampled_path_validation(gpu_lib):
     B = gpu_lib
     n = 24

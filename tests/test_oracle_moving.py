@@ -70,6 +70,82 @@ def test_comoving_uniform_flow_on_a_sampled_straight_path():
     assert fresh_total > 0
 
 
+def test_constant_spin_samples_reproduce_the_constant_spin():
+    """Angular velocity given per step with every sample equal to a constant
+    drives the same steps as the constant: fields identical after 10 steps."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 22, 20, 18)
+    kin = moving.Kinematics((10.4, 9.7, 8.6), amplitude=3.0, period=40.0, direction=(0.6, 0.8, 0.0),
+                            omega=(0.002, -0.001, 0.003))
+    C = np.array([kin.centre(t) for t in range(12)])
+    V = np.array([kin.velocity(t) for t in range(12)])
+    a = moving.MovingSphereSim(dom, 4.1, moving.SampledKinematics(C, V, kin.Omega), tau=0.8)
+    b = moving.MovingSphereSim(dom, 4.1, moving.SampledKinematics(C, V, np.repeat(kin.Omega[None, :], 12, 0)),
+                               tau=0.8)
+    a.run(10)
+    b.run(10)
+    assert np.array_equal(a.sim.f, b.sim.f, equal_nan=True)
+
+
+def test_sampled_spin_enters_the_wall_velocity_at_its_own_time():
+    """An impulsive spin-up about z (Omega(0) = 0, Omega(t >= 1) = W e_z) of a
+    resting sphere: the links of the geometry of time 0 carry u_w(0) = 0 and
+    u_w(1) = W e_z x r at their wall points, i.e. tangential, of size W times
+    the wall point's distance from the axis, and in the sense of the rotation."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 20, 20, 16)
+    n, W = 6, 0.004
+    C = np.repeat(np.array([[9.6, 10.3, 7.8]]), n, 0)
+    V = np.zeros((n, 3))
+    Om = np.zeros((n, 3))
+    Om[1:, 2] = W
+    m = moving.MovingSphereSim(dom, 4.3, moving.SampledKinematics(C, V, Om), tau=0.8)
+    fluid, links, _ = m.geometry(0)
+    assert links["node"].size > 0
+    assert np.abs(links["uw_t"]).max() == 0.0
+    X = dom.coords(links["node"]).astype(np.float64)
+    cvec = lat.c[links["dir"]].T.astype(np.float64)
+    xw = X - links["q"][None, :] * cvec
+    r = xw - C[0][:, None]
+    u1 = links["uw_t1"]
+    rperp = np.hypot(r[0], r[1])
+    np.testing.assert_allclose(np.hypot(u1[0], u1[1]), W * rperp, rtol=1e-12, atol=1e-15)
+    assert np.abs(u1[2]).max() == 0.0
+    assert np.all(r[0] * u1[0] + r[1] * u1[1] <= 1e-15)        # tangential
+    assert np.all(r[0] * u1[1] - r[1] * u1[0] >= -1e-15)       # counter-clockwise about +z
+    # one step later both velocities are the spin's
+    _, links1, _ = m.geometry(1)
+    assert np.abs(links1["uw_t"]).max() > 0.0
+
+
+def test_reversed_spin_mirrors_the_flow():
+    """A sphere spinning up about z with Omega(t) and one spinning with
+    -Omega(t), both at rest in a box symmetric under y -> -y about the sphere's
+    centre: after 12 steps the second flow is the mirror image of the first
+    (u_x even, u_y odd in y)."""
+    lat = lattice.D3Q19
+    ny = 20
+    dom = G.Domain(lat, 18, ny, 14)
+    n = 14
+    C = np.repeat(np.array([[8.7, (ny - 1) / 2.0, 6.9]]), n, 0)
+    V = np.zeros((n, 3))
+    Om = np.zeros((n, 3))
+    Om[:, 2] = 0.003 * np.minimum(np.arange(n), 5) / 5.0
+    a = moving.MovingSphereSim(dom, 3.8, moving.SampledKinematics(C, V, Om), tau=0.8)
+    b = moving.MovingSphereSim(dom, 3.8, moving.SampledKinematics(C, V, -Om), tau=0.8)
+    a.run(12)
+    b.run(12)
+    _, ua = a.sim.macros()
+    _, ub = b.sim.macros()
+    ua = ua.reshape(3, 14, ny, 18)
+    ub = ub.reshape(3, 14, ny, 18)
+    fl = a.sim.fluid.reshape(14, ny, 18)
+    assert np.array_equal(fl, fl[:, ::-1, :])
+    assert np.abs(ua[:, fl]).max() > 1e-4
+    np.testing.assert_allclose(ub[0][fl], ua[0][:, ::-1, :][fl], atol=1e-15)
+    np.testing.assert_allclose(ub[1][fl], -ua[1][:, ::-1, :][fl], atol=1e-15)
+
+
 def test_moving_box_runs_and_conserves_mass_roughly():
     box = synth.moving_boxes(1, side_min=40, side_max=40, r_min=6, r_max=6, period=200)[0]
     lat = lattice.D3Q19

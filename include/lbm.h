@@ -204,6 +204,22 @@ int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3
 int lbm_set_moving_sphere_motion(lbm_domain d, double radius, int64_t n_samples, const double* centre,
                                  const double* velocity, const double* omega, int32_t variant, double q_cutoff);
 
+/* Several rigid spheres (1 .. 4) in prescribed motion in one domain (Sec. II.E
+ * moving boundaries), each as in lbm_set_moving_sphere_motion: radius[s], and
+ * per sample k and sphere s the centre, translational velocity and angular
+ * velocity at [k][s][0..2] of centre, velocity, omega (host arrays
+ * [n_samples][n_spheres][3], copied).  A node is solid when it lies in or on any
+ * sphere; a cut link takes the first crossing over the spheres (the first
+ * sphere in the list wins a tie) and that sphere's wall velocities; a fresh
+ * node takes the rigid-body velocity of the sphere whose surface is nearest.
+ * The sweep region is the union of the spheres' sweep boxes.  The surfaces must
+ * stay more than two nodes apart at every sample (LBM_EINVAL otherwise, naming
+ * the pair and the sample); force tracking (lbm_set_force_tracking) is for one
+ * sphere (LBM_ESTATE).  Other errors as lbm_set_moving_sphere_motion. */
+int lbm_set_moving_spheres(lbm_domain d, int32_t n_spheres, const double* radius, int64_t n_samples,
+                           const double* centre, const double* velocity, const double* omega, int32_t variant,
+                           double q_cutoff);
+
 /* Advance n_steps >= 0 time steps; asynchronous on the domain's stream.  Each
  * step is the lattice Boltzmann equation of Sec. II.A (eq. LBE) split into the
  * local collision -- BGK (eq. LB-BGK) with the second-order equilibrium (eq.

@@ -19,7 +19,9 @@ Status: pinned -- V(t) against central differences of x_c(t) over a period and
 its closed values at t = 0 and T/4; a sampled path against the sinusoid it
 samples and against the co-moving invariant on a straight path; a sampled spin
 against the constant spin it repeats, its time index (an impulsive spin-up
-moves the walls at t+1 only) and the mirror symmetry of a reversed spin; the refill
+moves the walls at t+1 only) and the mirror symmetry of a reversed spin;
+several spheres by the co-moving invariant with two spheres, the independence
+of their order and hand-placed refill points; the refill
 rule against hand-listed
 neighbour sets (tests/test_oracle_refill.py); the co-moving invariant (a sphere
 moving at the velocity of a uniform flow leaves it unchanged, refills
@@ -79,10 +81,22 @@ class SampledKinematics:
         return self.Omega.copy() if self.W is None else self.W[int(t)].copy()
 
 
-class MovingSphereSim:
-    def __init__(self, dom, radius, kin, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None,
+class MovingSpheresSim:
+    """Several rigid spheres in prescribed motion (kins[s] with radii[s]).
+
+    Readings for more than one sphere: a node is solid when it lies in or on
+    any sphere; a cut link takes the first crossing over the spheres (the first
+    in the list wins a tie, the host builder's rule) and that sphere's wall
+    velocities; a fresh node takes the rigid-body velocity of the sphere whose
+    surface is nearest (|x - x_c| - R smallest, the first on a tie).  Forces and
+    torques are kept for one sphere (about its centre)."""
+
+    def __init__(self, dom, radii, kins, tau, variant="FQ", q_cut=0.01, rho0=1.0, u0=(0.0, 0.0, 0.0), magic=None,
                  wall_neq="bounceback"):
-        self.dom, self.radius, self.kin = dom, float(radius), kin
+        self.dom = dom
+        self.radii = [float(r) for r in radii]
+        self.kins = list(kins)
+        assert len(self.radii) == len(self.kins) >= 1
         self.variant, self.q_cut, self.wall_neq = variant, q_cut, wall_neq
         self.sim = Simulation(dom, tau, rho0=rho0, u0=u0, magic=magic)
         self.t = 0
@@ -90,28 +104,43 @@ class MovingSphereSim:
         self.sim.init_equilibrium()
 
     def geometry(self, t):
-        k = self.kin
-        c_t = k.centre(t)
-        sph = G.Sphere(c_t, self.radius, True, V=k.velocity(t), Omega=k.omega(t))
-        fluid = G.classify(self.dom, [sph])
-        V1, Om1 = k.velocity(t + 1), k.omega(t + 1)
+        return self._geometry(t)
+
+    def _geometry(self, t):
+        sphs = [G.Sphere(k.centre(t), r, True, V=k.velocity(t), Omega=k.omega(t))
+                for r, k in zip(self.radii, self.kins)]
+        fluid = G.classify(self.dom, sphs)
+        at1 = {id(s): (k.centre(t), k.velocity(t + 1), k.omega(t + 1)) for s, k in zip(sphs, self.kins)}
 
         def uw1(shape, xw):
+            c_t, V1, Om1 = at1[id(shape)]
             r = self.dom.min_image(xw - c_t[:, None])
             return V1[:, None] + np.cross(Om1, r.T).T
-        links = G.cut_links(self.dom, fluid, [sph], uw_t1_fn=uw1)
-        return fluid, links, sph
+        links = G.cut_links(self.dom, fluid, sphs, uw_t1_fn=uw1)
+        return fluid, links, sphs
+
+    def body_velocity(self, sphs, X):
+        """Rigid-body velocity at the points X (3, N) of the sphere whose surface is nearest."""
+        u = sphs[0].velocity(self.dom, X)
+        if len(sphs) > 1:
+            gap = np.stack([np.sqrt((s._rel(self.dom, X) ** 2).sum(axis=0)) - s.radius for s in sphs])
+            near = np.argmin(gap, axis=0)
+            for j, s in enumerate(sphs[1:], start=1):
+                sel = near == j
+                if sel.any():
+                    u[:, sel] = s.velocity(self.dom, X[:, sel])
+        return u
 
     def _install(self, first=False):
-        fluid, links, sph = self.geometry(self.t)
+        fluid, links, sphs = self._geometry(self.t)
         if not first:
             X = self.dom.coords().astype(np.float64)
-            self.sim.refill(fluid, sph.velocity(self.dom, X))
+            self.sim.refill(fluid, self.body_velocity(sphs, X))
         self.sim.set_geometry(fluid, links, self.variant, self.q_cut, wall_neq=self.wall_neq)
 
     def step(self):
-        # torques about the sphere's centre at the geometry's time t
-        self.sim.centres = self.kin.centre(self.t)[None, :].copy()
+        # torques about the (first) sphere's centre at the geometry's time t
+        self.sim.centres = self.kins[0].centre(self.t)[None, :].copy()
         self.sim.step()
         self.t += 1
         self._install()
@@ -119,3 +148,22 @@ class MovingSphereSim:
     def run(self, n):
         for _ in range(int(n)):
             self.step()
+
+
+class MovingSphereSim(MovingSpheresSim):
+    """One rigid sphere of radius `radius` moving with `kin`."""
+
+    def __init__(self, dom, radius, kin, tau, **kw):
+        super().__init__(dom, [radius], [kin], tau, **kw)
+
+    @property
+    def radius(self):
+        return self.radii[0]
+
+    @property
+    def kin(self):
+        return self.kins[0]
+
+    def geometry(self, t):
+        fluid, links, sphs = self._geometry(t)
+        return fluid, links, sphs[0]

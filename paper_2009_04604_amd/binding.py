@@ -39,7 +39,7 @@ EXPORTED = [
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
     "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque", "lbm_set_force_tracking",
     "lbm_moving_force", "lbm_macros_noalloc", "lbm_stream_probe", "lbm_set_moving_sphere_path",
-    "lbm_set_moving_sphere_motion",
+    "lbm_set_moving_sphere_motion", "lbm_set_moving_spheres",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
 
@@ -98,6 +98,7 @@ def lib():
         "lbm_set_moving_sphere": (I32, [P, P, DBL, DBL, DBL, P, P, I32, DBL]),
         "lbm_set_moving_sphere_path": (I32, [P, DBL, P, I64, P, P, I32, DBL]),
         "lbm_set_moving_sphere_motion": (I32, [P, DBL, I64, P, P, P, I32, DBL]),
+        "lbm_set_moving_spheres": (I32, [P, I32, P, I64, P, P, P, I32, DBL]),
         "lbm_macros": (I32, [P, P, P, P]),
         "lbm_get_state": (I32, [P, P]),
         "lbm_set_state": (I32, [P, P]),
@@ -248,6 +249,19 @@ def lbm_set_moving_sphere_motion(h, radius, centre, velocity, omega, variant="FQ
                                               float(q_cutoff)))
 
 
+def lbm_set_moving_spheres(h, radius, centre, velocity, omega, variant="FQ", q_cutoff=0.01):
+    r = np.ascontiguousarray(radius, dtype=np.float64).reshape(-1)
+    ns = r.size
+    c = np.ascontiguousarray(centre, dtype=np.float64).reshape(-1, ns, 3)
+    v = np.ascontiguousarray(velocity, dtype=np.float64).reshape(-1, ns, 3)
+    om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1, ns, 3)
+    if c.shape != v.shape or c.shape != om.shape:
+        raise ValueError("centre, velocity and omega need the same [n_samples, n_spheres, 3] shape")
+    var = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    _check(lib().lbm_set_moving_spheres(h, ns, _ptr(r), c.shape[0], _ptr(c), _ptr(v), _ptr(om), var,
+                                        float(q_cutoff)))
+
+
 def lbm_step(h, n_steps):
     _check(lib().lbm_step(h, int(n_steps)))
 
@@ -337,6 +351,10 @@ class Domain:
     def set_moving_sphere_path(self, radius, omega, centre, velocity, variant="FQ", q_cutoff=0.01):
         """centre, velocity: [n_samples, 3] per step (see lbm_set_moving_sphere_path)."""
         lbm_set_moving_sphere_path(self.h, radius, omega, centre, velocity, variant, q_cutoff)
+
+    def set_moving_spheres(self, radius, centre, velocity, omega, variant="FQ", q_cutoff=0.01):
+        """radius [n_spheres]; centre, velocity, omega: [n_samples, n_spheres, 3] (see lbm_set_moving_spheres)."""
+        lbm_set_moving_spheres(self.h, radius, centre, velocity, omega, variant, q_cutoff)
 
     def set_moving_sphere_motion(self, radius, centre, velocity, omega, variant="FQ", q_cutoff=0.01):
         """centre, velocity, omega: [n_samples, 3] per step (see lbm_set_moving_sphere_motion)."""

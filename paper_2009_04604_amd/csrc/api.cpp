@@ -141,28 +141,34 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
   return p;
 }
 
-// Kinematics of the moving sphere for the geometry of time t: centre
-// x0 + A sin(2 pi t / T) e and its velocity at t and t + 1, or the samples of a
-// prescribed path; angular velocity at t and t + 1 (constant unless sampled).
+// Kinematics of the moving spheres for the geometry of time t: the sinusoid's
+// centre x0 + A sin(2 pi t / T) e and velocity at t and t + 1 (one sphere), or
+// the samples of prescribed paths; angular velocities at t and t + 1
+// (constant unless sampled).
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   MovingKin k{};
-  for (int a = 0; a < 3; ++a) k.Om[a] = k.Om1[a] = d->mv_om[a];
+  const int ns = d->mv_ns;
+  for (int a = 0; a < 3; ++a) k.Om[0][a] = k.Om1[0][a] = d->mv_om[a];
   if (!d->path_c.empty()) {
-    // a sampled path: the geometry of time t needs x_c(t), V(t), V(t+1) and,
-    // when sampled, Omega(t), Omega(t+1); a time past the path (only in rows of
-    // a kinematics table that no step uses) takes its last pair of samples
-    const int64_t n = (int64_t)d->path_c.size() / 3;
+    // sampled paths ([n][ns][3]): the geometry of time t needs x_c(t), V(t),
+    // V(t+1) and, when sampled, Omega(t), Omega(t+1); a time past the path
+    // (only in rows of a kinematics table that no step uses) takes its last
+    // pair of samples
+    const int64_t n = (int64_t)d->path_c.size() / (3 * ns);
     const int64_t tt = std::min<int64_t>(std::max<int64_t>(t, 0), n - 2);
-    for (int a = 0; a < 3; ++a) {
-      k.c[a] = d->path_c[3 * tt + a];
-      k.V[a] = d->path_v[3 * tt + a];
-      k.V1[a] = d->path_v[3 * (tt + 1) + a];
-      if (!d->path_om.empty()) {
-        k.Om[a] = d->path_om[3 * tt + a];
-        k.Om1[a] = d->path_om[3 * (tt + 1) + a];
+    for (int sp = 0; sp < ns; ++sp) {
+      const size_t o0 = 3 * ((size_t)tt * ns + sp), o1 = 3 * ((size_t)(tt + 1) * ns + sp);
+      for (int a = 0; a < 3; ++a) {
+        k.c[sp][a] = d->path_c[o0 + a];
+        k.V[sp][a] = d->path_v[o0 + a];
+        k.V1[sp][a] = d->path_v[o1 + a];
+        if (!d->path_om.empty()) {
+          k.Om[sp][a] = d->path_om[o0 + a];
+          k.Om1[sp][a] = d->path_om[o1 + a];
+        }
       }
+      if (d->D == 2) k.c[sp][2] = k.V[sp][2] = k.V1[sp][2] = 0.0;
     }
-    if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
     return k;
   }
   const double two_pi = 2.0 * M_PI;
@@ -170,19 +176,19 @@ MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   const double c0 = std::cos(two_pi * t / d->mv_period), c1 = std::cos(two_pi * (t + 1) / d->mv_period);
   const double vamp = d->mv_amp * (two_pi / d->mv_period);
   for (int a = 0; a < 3; ++a) {
-    k.c[a] = d->mv_x0[a] + d->mv_amp * s * d->mv_dir[a];
-    k.V[a] = vamp * c0 * d->mv_dir[a];
-    k.V1[a] = vamp * c1 * d->mv_dir[a];
+    k.c[0][a] = d->mv_x0[a] + d->mv_amp * s * d->mv_dir[a];
+    k.V[0][a] = vamp * c0 * d->mv_dir[a];
+    k.V1[0][a] = vamp * c1 * d->mv_dir[a];
   }
-  if (d->D == 2) k.c[2] = k.V[2] = k.V1[2] = 0.0;
+  if (d->D == 2) k.c[0][2] = k.V[0][2] = k.V1[0][2] = 0.0;
   return k;
 }
 
-// Steps a domain whose sphere follows a sampled path can still take: the
+// Steps a domain whose spheres follow sampled paths can still take: the
 // geometry of time t uses the samples t and t+1.
 int64_t path_steps_left(const lbm_domain_s* d) {
   if (d->path_c.empty()) return INT64_MAX;
-  return (int64_t)d->path_c.size() / 3 - 2 - d->steps;
+  return (int64_t)d->path_c.size() / (3 * d->mv_ns) - 2 - d->steps;
 }
 
 // Static part of the moving-sphere rebuild; `cur` names the population buffer
@@ -190,7 +196,8 @@ int64_t path_steps_left(const lbm_domain_s* d) {
 MovingParams moving_params(const lbm_domain_s* d, int cur) {
   MovingParams mp{};
   mp.g = d->g;
-  mp.r = d->mv_r;
+  mp.ns = d->mv_ns;
+  for (int sp = 0; sp < d->mv_ns; ++sp) mp.r[sp] = d->mv_r[sp];
   mp.variant = d->variant;
   mp.q_cut = d->q_cut;
   mp.reg_seg = d->reg_seg;
@@ -541,8 +548,8 @@ namespace {
 // checks, the sweep region's segments, the link arrays, the geometry of time 0
 // and the initial state.  The motion itself (sinusoid or sampled path) is set
 // on the domain by the caller beforehand.
-int install_moving(lbm_domain d, const double lo_c[3], const double hi_c[3], double radius, const double omega[3],
-                   int32_t variant, double q_cutoff) {
+int install_moving(lbm_domain d, int ns, const double (*lo_c)[3], const double (*hi_c)[3], const double* radius,
+                   const double omega[3], int32_t variant, double q_cutoff) {
   if (variant < LBM_ELIBB_FQ || variant > LBM_HWBB) return fail(LBM_EINVAL, "invalid variant");
   if (!(q_cutoff >= 0.0) || !std::isfinite(q_cutoff)) return fail(LBM_EINVAL, "q_cutoff must be finite and >= 0");
   if (d->g.compact) return fail(LBM_ESTATE, "a moving sphere needs the dense layout (desc.layout = LBM_LAYOUT_DENSE)");
@@ -551,34 +558,35 @@ int install_moving(lbm_domain d, const double lo_c[3], const double hi_c[3], dou
   if (d->n_fluid != d->N) return fail(LBM_ESTATE, "the domain's initial mask must be all fluid");
   const GridGeom& g = d->g;
   if (!(g.perx && g.pery && g.perz)) return fail(LBM_ESTATE, "a moving sphere needs a fully periodic box");
-  {
-    const int n3[3] = {g.nx, g.ny, d->D == 3 ? g.nz : 1 << 30};
+  const int n3[3] = {g.nx, g.ny, d->D == 3 ? g.nz : 1 << 30};
+  for (int sp = 0; sp < ns; ++sp)
     for (int a = 0; a < 3; ++a)
-      if (2.0 * (radius + 0.5 * (hi_c[a] - lo_c[a]) + 2.0) >= n3[a])
-        return fail(LBM_EINVAL, "the sphere and its sweep must fit in half the box on every axis");
-  }
-  // the region: segments of the box swept by the sphere (plus two nodes)
+      if (2.0 * (radius[sp] + 0.5 * (hi_c[sp][a] - lo_c[sp][a]) + 2.0) >= n3[a])
+        return fail(LBM_EINVAL, "each sphere and its sweep must fit in half the box on every axis");
+  // the region: segments of the boxes swept by the spheres (plus two nodes)
   std::vector<char> in_seg(g.nseg, 0);
-  int lo[3], hi[3];
   const int n[3] = {g.nx, g.ny, g.nz}, per[3] = {g.perx, g.pery, g.perz};
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = (int)std::floor(lo_c[a] - radius) - 2;
-    hi[a] = (int)std::ceil(hi_c[a] + radius) + 2;
-    if (d->D == 2 && a == 2) lo[a] = hi[a] = 0;
-    if (hi[a] - lo[a] + 1 >= n[a]) {
-      lo[a] = 0;
-      hi[a] = n[a] - 1;
-    } else if (!per[a]) {
-      lo[a] = std::max(lo[a], 0);
-      hi[a] = std::min(hi[a], n[a] - 1);
-    }
-  }
-  for (int zz = lo[2]; zz <= hi[2]; ++zz)
-    for (int yy = lo[1]; yy <= hi[1]; ++yy)
-      for (int xx = lo[0]; xx <= hi[0]; xx += 1) {
-        const int x = ((xx % n[0]) + n[0]) % n[0], y = ((yy % n[1]) + n[1]) % n[1], z = ((zz % n[2]) + n[2]) % n[2];
-        in_seg[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] = 1;
+  for (int sp = 0; sp < ns; ++sp) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = (int)std::floor(lo_c[sp][a] - radius[sp]) - 2;
+      hi[a] = (int)std::ceil(hi_c[sp][a] + radius[sp]) + 2;
+      if (d->D == 2 && a == 2) lo[a] = hi[a] = 0;
+      if (hi[a] - lo[a] + 1 >= n[a]) {
+        lo[a] = 0;
+        hi[a] = n[a] - 1;
+      } else if (!per[a]) {
+        lo[a] = std::max(lo[a], 0);
+        hi[a] = std::min(hi[a], n[a] - 1);
       }
+    }
+    for (int zz = lo[2]; zz <= hi[2]; ++zz)
+      for (int yy = lo[1]; yy <= hi[1]; ++yy)
+        for (int xx = lo[0]; xx <= hi[0]; xx += 1) {
+          const int x = ((xx % n[0]) + n[0]) % n[0], y = ((yy % n[1]) + n[1]) % n[1], z = ((zz % n[2]) + n[2]) % n[2];
+          in_seg[(x / SEG) + (int64_t)g.nseg_x * (y + (int64_t)g.ny * z)] = 1;
+        }
+  }
   std::vector<int32_t> reg;
   for (int64_t s2 = 0; s2 < g.nseg; ++s2)
     if (in_seg[s2]) reg.push_back((int32_t)s2);
@@ -599,7 +607,8 @@ int install_moving(lbm_domain d, const double lo_c[3], const double hi_c[3], dou
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));
   for (int a = 0; a < 3; ++a) d->mv_om[a] = omega[a];
-  d->mv_r = radius;
+  d->mv_ns = ns;
+  for (int sp = 0; sp < ns; ++sp) d->mv_r[sp] = radius[sp];
   d->variant = variant;
   d->q_cut = q_cutoff;
   d->moving = true;
@@ -620,11 +629,11 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(x0[a]) || !std::isfinite(direction[a]) || !std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite motion");
   if (d->moving) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
-  double lo_c[3], hi_c[3];
+  double lo_c[1][3], hi_c[1][3];
   for (int a = 0; a < 3; ++a) {
     const double ext = std::fabs(amplitude * direction[a]);
-    lo_c[a] = x0[a] - ext;
-    hi_c[a] = x0[a] + ext;
+    lo_c[0][a] = x0[a] - ext;
+    hi_c[0][a] = x0[a] + ext;
     d->mv_x0[a] = x0[a];
     d->mv_dir[a] = direction[a];
   }
@@ -633,41 +642,67 @@ int lbm_set_moving_sphere(lbm_domain d, const double x0[3], double radius, doubl
   d->path_c.clear();
   d->path_v.clear();
   d->path_om.clear();
-  return install_moving(d, lo_c, hi_c, radius, omega, variant, q_cutoff);
+  return install_moving(d, 1, lo_c, hi_c, &radius, omega, variant, q_cutoff);
 }
 
 namespace {
-// A sphere on a sampled path: centre and velocity per step, angular velocity
-// constant (omega) or per step (omega_path, [n][3]).
-int set_moving_path(lbm_domain d, double radius, const double* omega, const double* omega_path, int64_t n_samples,
-                    const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
-  if (!(radius > 0.0) || !std::isfinite(radius)) return fail(LBM_EINVAL, "radius must be finite and > 0");
+// Spheres on sampled paths: centres and velocities per step ([n][ns][3]),
+// angular velocity constant (omega, one sphere) or per step (omega_path,
+// [n][ns][3]).
+int set_moving_paths(lbm_domain d, int ns, const double* radius, const double* omega, const double* omega_path,
+                     int64_t n_samples, const double* centre, const double* velocity, int32_t variant,
+                     double q_cutoff) {
+  if (ns < 1 || ns > MAX_SPHERES)
+    return fail(LBM_EINVAL, "between 1 and " + std::to_string(MAX_SPHERES) + " spheres per domain");
+  for (int sp = 0; sp < ns; ++sp)
+    if (!(radius[sp] > 0.0) || !std::isfinite(radius[sp])) return fail(LBM_EINVAL, "radius must be finite and > 0");
   if (n_samples < 2) return fail(LBM_EINVAL, "a path needs at least 2 samples");
   if (omega)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(omega[a])) return fail(LBM_EINVAL, "non-finite omega");
-  for (int64_t k = 0; k < 3 * n_samples; ++k)
+  const int64_t nv = 3 * n_samples * ns;
+  for (int64_t k = 0; k < nv; ++k)
     if (!std::isfinite(centre[k]) || !std::isfinite(velocity[k]) || (omega_path && !std::isfinite(omega_path[k])))
-      return fail(LBM_EINVAL, "non-finite path sample " + std::to_string(k / 3));
+      return fail(LBM_EINVAL, "non-finite path sample " + std::to_string(k / (3 * ns)));
   if (d->moving) return fail(LBM_ESTATE, "set the moving sphere once, on a fresh domain without links");
-  double lo_c[3], hi_c[3];
-  for (int a = 0; a < 3; ++a) {
-    lo_c[a] = hi_c[a] = centre[a];
-    for (int64_t k = 1; k < n_samples; ++k) {
-      lo_c[a] = std::min(lo_c[a], centre[3 * k + a]);
-      hi_c[a] = std::max(hi_c[a], centre[3 * k + a]);
+  // spheres keep apart: at every sample the surfaces are more than two nodes apart
+  // (minimum image on the periodic axes)
+  const int n3[3] = {d->g.nx, d->g.ny, d->g.nz};
+  for (int64_t k = 0; k < n_samples; ++k)
+    for (int a = 0; a < ns; ++a)
+      for (int b = a + 1; b < ns; ++b) {
+        double dd = 0.0;
+        for (int x = 0; x < 3; ++x) {
+          double v = centre[3 * (k * ns + a) + x] - centre[3 * (k * ns + b) + x];
+          if (d->D == 2 && x == 2) v = 0.0;
+          v -= n3[x] * std::nearbyint(v / n3[x]);
+          dd += v * v;
+        }
+        if (!(std::sqrt(dd) > radius[a] + radius[b] + 2.0))
+          return fail(LBM_EINVAL, "spheres " + std::to_string(a) + " and " + std::to_string(b) +
+                                      " come within two nodes of each other at sample " + std::to_string(k));
+      }
+  double lo_c[MAX_SPHERES][3], hi_c[MAX_SPHERES][3];
+  for (int sp = 0; sp < ns; ++sp)
+    for (int a = 0; a < 3; ++a) {
+      lo_c[sp][a] = hi_c[sp][a] = centre[3 * sp + a];
+      for (int64_t k = 1; k < n_samples; ++k) {
+        lo_c[sp][a] = std::min(lo_c[sp][a], centre[3 * (k * ns + sp) + a]);
+        hi_c[sp][a] = std::max(hi_c[sp][a], centre[3 * (k * ns + sp) + a]);
+      }
     }
-  }
-  d->path_c.assign(centre, centre + 3 * n_samples);
-  d->path_v.assign(velocity, velocity + 3 * n_samples);
-  if (omega_path) d->path_om.assign(omega_path, omega_path + 3 * n_samples);
+  d->path_c.assign(centre, centre + nv);
+  d->path_v.assign(velocity, velocity + nv);
+  if (omega_path) d->path_om.assign(omega_path, omega_path + nv);
   else d->path_om.clear();
+  d->mv_ns = ns;
   const double zero[3] = {0.0, 0.0, 0.0};
-  const int e = install_moving(d, lo_c, hi_c, radius, omega ? omega : zero, variant, q_cutoff);
+  const int e = install_moving(d, ns, lo_c, hi_c, radius, omega ? omega : zero, variant, q_cutoff);
   if (e != LBM_OK && !d->moving) {
     d->path_c.clear();
     d->path_v.clear();
     d->path_om.clear();
+    d->mv_ns = 1;
   }
   return e;
 }
@@ -676,13 +711,20 @@ int set_moving_path(lbm_domain d, double radius, const double* omega, const doub
 int lbm_set_moving_sphere_path(lbm_domain d, double radius, const double omega[3], int64_t n_samples,
                                const double* centre, const double* velocity, int32_t variant, double q_cutoff) {
   if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
-  return set_moving_path(d, radius, omega, nullptr, n_samples, centre, velocity, variant, q_cutoff);
+  return set_moving_paths(d, 1, &radius, omega, nullptr, n_samples, centre, velocity, variant, q_cutoff);
 }
 
 int lbm_set_moving_sphere_motion(lbm_domain d, double radius, int64_t n_samples, const double* centre,
                                  const double* velocity, const double* omega, int32_t variant, double q_cutoff) {
   if (!d || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
-  return set_moving_path(d, radius, nullptr, omega, n_samples, centre, velocity, variant, q_cutoff);
+  return set_moving_paths(d, 1, &radius, nullptr, omega, n_samples, centre, velocity, variant, q_cutoff);
+}
+
+int lbm_set_moving_spheres(lbm_domain d, int32_t n_spheres, const double* radius, int64_t n_samples,
+                           const double* centre, const double* velocity, const double* omega, int32_t variant,
+                           double q_cutoff) {
+  if (!d || !radius || !omega || !centre || !velocity) return fail(LBM_EINVAL, "null argument");
+  return set_moving_paths(d, n_spheres, radius, nullptr, omega, n_samples, centre, velocity, variant, q_cutoff);
 }
 
 int lbm_step(lbm_domain d, int32_t n_steps) {
@@ -873,6 +915,7 @@ int lbm_set_force_tracking(lbm_domain d, int32_t on) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   if (!d->moving) return fail(LBM_ESTATE, "force tracking is for moving spheres (static links: lbm_force_torque)");
   if (on != 0 && on != 1) return fail(LBM_EINVAL, "on must be 0 or 1");
+  if (on && d->mv_ns > 1) return fail(LBM_ESTATE, "force tracking covers a domain with one moving sphere");
   if (on && !d->mforce)
     if (int e = dalloc(d->mforce, ((size_t)d->link_cap + 1) * 6 * 8)) return e;
   d->track_force = on != 0;

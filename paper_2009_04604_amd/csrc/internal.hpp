@@ -183,18 +183,24 @@ struct ForceParams {
 };
 
 // Kinematics of a moving sphere for the geometry of time t.
+// Spheres per domain in the moving rebuild.
+constexpr int MAX_SPHERES = 4;
+
+// Kinematics of a domain's spheres for the geometry of time t.
 struct MovingKin {
-  double c[3];                   // centre at t
-  double V[3], V1[3];            // translational velocity at t and t+1
-  double Om[3], Om1[3];          // angular velocity at t and t+1
+  double c[MAX_SPHERES][3];                 // centres at t
+  double V[MAX_SPHERES][3], V1[MAX_SPHERES][3];    // translational velocities at t and t+1
+  double Om[MAX_SPHERES][3], Om1[MAX_SPHERES][3];  // angular velocities at t and t+1
 };
 
-// One moving sphere (dense layout, slot mode): the geometry of time t is rebuilt
-// on the device over a fixed region of segments (the sphere's sweep box).
+// Moving spheres of one domain (dense layout, slot mode): the geometry of time t
+// is rebuilt on the device over a fixed region of segments (the union of the
+// spheres' sweep boxes).
 struct MovingParams {
   GridGeom g;
   MovingKin k;                   // single-domain launches; batched launches read a table
-  double r;                      // radius
+  int32_t ns;                    // number of spheres (1 .. MAX_SPHERES)
+  double r[MAX_SPHERES];         // radii
   int32_t kin_slot;              // batched launches: column of this sphere in the table
   int32_t variant;
   double q_cut;
@@ -331,9 +337,11 @@ struct lbm_domain_s {
   int64_t state_step;            // steps when the state was last imported (set_state, links)
   // moving sphere (lbm_set_moving_sphere)
   bool moving;
-  double mv_x0[3], mv_r, mv_amp, mv_period, mv_dir[3], mv_om[3];
-  std::vector<double> path_c, path_v;  // [n][3] prescribed centre and velocity per step (empty: the sinusoid)
-  std::vector<double> path_om;         // [n][3] angular velocity per step (empty: constant mv_om)
+  double mv_x0[3], mv_amp, mv_period, mv_dir[3], mv_om[3];
+  int mv_ns = 1;                       // spheres (the sinusoid: one)
+  double mv_r[lbm::MAX_SPHERES];       // radii
+  std::vector<double> path_c, path_v;  // [n][ns][3] prescribed centres and velocities per step (empty: the sinusoid)
+  std::vector<double> path_om;         // [n][ns][3] angular velocities per step (empty: constant mv_om)
   int32_t* reg_seg;
   int64_t nreg;
   uint64_t* seg_prev;

@@ -45,21 +45,25 @@ __device__ __forceinline__ double min_image(double d, int L, int periodic) {
   return __dsub_rn(d, __dmul_rn(Ld, rint(__ddiv_rn(d, Ld))));
 }
 
-__device__ __forceinline__ void rel(const MovingParams& p, double x, double y, double z, double (&d)[3]) {
-  d[0] = min_image(__dsub_rn(x, p.k.c[0]), p.g.nx, p.g.perx);
-  d[1] = min_image(__dsub_rn(y, p.k.c[1]), p.g.ny, p.g.pery);
-  d[2] = min_image(__dsub_rn(z, p.k.c[2]), p.g.nz, p.g.perz);
+// position relative to sphere s's centre (minimum image on periodic axes)
+__device__ __forceinline__ void rel(const MovingParams& p, int s, double x, double y, double z, double (&d)[3]) {
+  d[0] = min_image(__dsub_rn(x, p.k.c[s][0]), p.g.nx, p.g.perx);
+  d[1] = min_image(__dsub_rn(y, p.k.c[s][1]), p.g.ny, p.g.pery);
+  d[2] = min_image(__dsub_rn(z, p.k.c[s][2]), p.g.nz, p.g.perz);
 }
 
 __device__ __forceinline__ double norm2(const double (&d)[3]) {
   return __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])), __dmul_rn(d[2], d[2]));
 }
 
-// solid (inside or on the sphere) at integer node coordinates
+// solid (inside or on some sphere) at integer node coordinates
 __device__ __forceinline__ bool solid_at(const MovingParams& p, int x, int y, int z) {
-  double d[3];
-  rel(p, (double)x, (double)y, (double)z, d);
-  return norm2(d) <= __dmul_rn(p.r, p.r);
+  for (int s = 0; s < p.ns; ++s) {
+    double d[3];
+    rel(p, s, (double)x, (double)y, (double)z, d);
+    if (norm2(d) <= __dmul_rn(p.r[s], p.r[s])) return true;
+  }
+  return false;
 }
 
 __device__ __forceinline__ int wrap(int v, int n, int periodic) {
@@ -67,18 +71,57 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic) {
   return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
-// first crossing lam in (0, 1] of x_F - lam c with the sphere (entering root)
-__device__ __forceinline__ double crossing(const MovingParams& p, int x, int y, int z, int cx, int cy, int cz) {
+// entering root lam of x_F - lam c with sphere s; `reach` tells whether it lies
+// on the segment (0, 1] (a root within 1e-12 of the segment's ends counts)
+__device__ __forceinline__ double crossing(const MovingParams& p, int s, int x, int y, int z, int cx, int cy, int cz,
+                                           bool& reach) {
   double d[3];
-  rel(p, (double)x, (double)y, (double)z, d);
+  rel(p, s, (double)x, (double)y, (double)z, d);
   const double c[3] = {(double)cx, (double)cy, (double)cz};
   const double A = __dadd_rn(__dadd_rn(__dmul_rn(c[0], c[0]), __dmul_rn(c[1], c[1])), __dmul_rn(c[2], c[2]));
   const double B = __dadd_rn(__dadd_rn(__dmul_rn(d[0], c[0]), __dmul_rn(d[1], c[1])), __dmul_rn(d[2], c[2]));
-  const double C0 = __dsub_rn(norm2(d), __dmul_rn(p.r, p.r));
+  const double C0 = __dsub_rn(norm2(d), __dmul_rn(p.r[s], p.r[s]));
   const double disc = __dsub_rn(__dmul_rn(B, B), __dmul_rn(A, C0));
   const double sq = disc >= 0.0 ? __dsqrt_rn(disc) : 0.0;
   const double lam = __ddiv_rn(__dsub_rn(B, sq), A);
-  return fmin(fmax(lam, 1e-12), 1.0);
+  reach = disc >= 0.0 && lam > -1e-12 && lam <= 1.0 + 1e-12;
+  return lam;
+}
+
+// first crossing lam in (0, 1] of a cut link over the spheres (the first
+// sphere wins a tie; with one sphere, that sphere's root) and the sphere crossed
+__device__ __forceinline__ double first_crossing(const MovingParams& p, int x, int y, int z, int cx, int cy, int cz,
+                                                 int& owner) {
+  // roots are compared after clamping onto the segment, as the host builder does
+  bool reach;
+  double best = fmin(fmax(crossing(p, 0, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
+  bool found = reach;
+  owner = 0;
+  for (int s = 1; s < p.ns; ++s) {
+    const double lam = fmin(fmax(crossing(p, s, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
+    if (reach && (!found || lam < best)) {
+      best = lam;
+      owner = s;
+      found = true;
+    }
+  }
+  return best;
+}
+
+// the sphere whose surface is nearest to (x, y, z) (the first one on a tie)
+__device__ __forceinline__ int nearest_sphere(const MovingParams& p, double x, double y, double z) {
+  int best_s = 0;
+  double best = 0.0;
+  for (int s = 0; s < p.ns; ++s) {
+    double d[3];
+    rel(p, s, x, y, z, d);
+    const double gap = __dsub_rn(__dsqrt_rn(norm2(d)), p.r[s]);
+    if (s == 0 || gap < best) {
+      best = gap;
+      best_s = s;
+    }
+  }
+  return best_s;
 }
 
 // rigid-body velocity V + Omega x r, r the minimum image of x - centre(t)
@@ -94,12 +137,16 @@ template <class L>
 __device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y, int z) {
   const GridGeom& g = p.g;
   uint32_t m = 0u;
-  // a node farther than r + 2 from the centre has no neighbour (|c_i| <= sqrt 3) in the sphere
+  // a node farther than r + 2 from every centre has no neighbour (|c_i| <= sqrt 3) in a sphere
   {
-    double d[3];
-    rel(p, (double)x, (double)y, (double)z, d);
-    const double far = p.r + 2.0;
-    if (norm2(d) > far * far) return m;
+    bool near = false;
+    for (int s2 = 0; s2 < p.ns; ++s2) {
+      double d[3];
+      rel(p, s2, (double)x, (double)y, (double)z, d);
+      const double far = p.r[s2] + 2.0;
+      near = near || norm2(d) <= far * far;
+    }
+    if (!near) return m;
   }
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
@@ -195,16 +242,16 @@ __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
   for (int i = 1; i < L::Q; ++i) {
     if (!((cm >> i) & 1u)) continue;
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
-    const double q = crossing(p, s.x, s.y, s.z, cx, cy, cz);
-    // wall point and its rigid-body velocity at t and t+1
+    int o;
+    const double q = first_crossing(p, s.x, s.y, s.z, cx, cy, cz, o);
+    // wall point and its rigid-body velocity at t and t+1 (of the sphere crossed)
     const double xw[3] = {__dsub_rn((double)s.x, __dmul_rn(q, (double)cx)), __dsub_rn((double)s.y, __dmul_rn(q, (double)cy)),
                           __dsub_rn((double)s.z, __dmul_rn(q, (double)cz))};
     double r[3];
-    rel(p, xw[0], xw[1], xw[2], r);
+    rel(p, o, xw[0], xw[1], xw[2], r);
     double u0[3], u1[3];
-    const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]}, V1[3] = {p.k.V1[0], p.k.V1[1], p.k.V1[2]};
-    body_velocity(p.k.Om, V, r, u0);
-    body_velocity(p.k.Om1, V1, r, u1);
+    body_velocity(p.k.Om[o], p.k.V[o], r, u0);
+    body_velocity(p.k.Om1[o], p.k.V1[o], r, u1);
     if (L::D == 2) u0[2] = u1[2] = 0.0;
     const double cu0 = cx * u0[0] + cy * u0[1] + cz * u0[2];
     const double cu1 = cx * u1[0] + cy * u1[1] + cz * u1[2];
@@ -267,9 +314,9 @@ __device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave)
   }
   const double rb = cnt > 0 ? tot / cnt : p.rho0;
   double r[3], u[3];
-  rel(p, (double)s.x, (double)s.y, (double)s.z, r);
-  const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
-  body_velocity(p.k.Om, V, r, u);
+  const int o = nearest_sphere(p, (double)s.x, (double)s.y, (double)s.z);
+  rel(p, o, (double)s.x, (double)s.y, (double)s.z, r);
+  body_velocity(p.k.Om[o], p.k.V[o], r, u);
   if (L::D == 2) u[2] = 0.0;
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -331,9 +378,8 @@ __device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, 
     }
     const double q = (double)lq[k];
     double r[3], u[3];
-    rel(p, x - q * cx, s.y - q * cy, s.z - q * cz, r);
-    const double V[3] = {p.k.V[0], p.k.V[1], p.k.V[2]};
-    body_velocity(p.k.Om, V, r, u);
+    rel(p, 0, x - q * cx, s.y - q * cy, s.z - q * cz, r);   // force tracking: one sphere
+    body_velocity(p.k.Om[0], p.k.V[0], r, u);
     if (L::D == 2) u[2] = r[2] = 0.0;
     const double c[3] = {(double)cx, (double)cy, (double)cz};
     double F[3];

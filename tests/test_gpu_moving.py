@@ -288,6 +288,116 @@ def test_sampled_spin_validation(gpu_lib):
     d.close()
 
 
+def _two_sphere_paths(n_samples):
+    """Sphere A round the tilted circle, sphere B along a straight line, both
+    spinning; [n, 2, 3] arrays of centres, velocities and angular velocities."""
+    C_a, V_a = _circle_path(n_samples, c0=(12.2, 13.6, 14.4), R=3.0)
+    t = np.arange(n_samples, dtype=np.float64)[:, None]
+    U = np.array([-0.05, 0.03, 0.04])
+    C_b = np.array([[28.3, 26.9, 25.1]]) + t * U[None, :]
+    V_b = np.repeat(U[None, :], n_samples, 0)
+    Om_a = _spin_up(n_samples)
+    Om_b = np.repeat(np.array([[0.0, -0.003, 0.001]]), n_samples, 0)
+    return (np.stack([C_a, C_b], 1), np.stack([V_a, V_b], 1), np.stack([Om_a, Om_b], 1))
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_two_spheres_match_oracle(gpu_lib, storage, tol):
+    """lbm_set_moving_spheres: two spheres on different paths with different
+    spins in one 40^3 box against the oracle; identical fluid and link sets."""
+    B = gpu_lib
+    n, steps = 40, 30
+    C, V, Om = _two_sphere_paths(steps + 2)
+    radii = [5.2, 4.1]
+    _say("case two moving spheres 40^3", storage)
+    d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    d.set_moving_spheres(radii, C, V, Om)
+    m = moving.MovingSpheresSim(G.Domain(OL.D3Q19, n, n, n), radii,
+                                [moving.SampledKinematics(C[:, s], V[:, s], Om[:, s]) for s in range(2)], 0.8)
+    fresh = 0
+    for block in range(6):
+        d.step(5)
+        for _ in range(5):
+            prev = m.sim.fluid.copy()
+            m.step()
+            fresh += int((m.sim.fluid & ~prev).sum())
+        info = d.info()
+        assert info["n_fluid"] == int(m.sim.fluid.sum())
+        assert info["n_links"] == m.sim.links["node"].size
+        _, u_g, _, unstable = d.macros()
+        assert not unstable
+        _, u_o = m.sim.macros()
+        fl = m.sim.fluid
+        err = np.linalg.norm(u_g[fl] - u_o[:, fl].T) / np.linalg.norm(u_o[:, fl])
+        _say("t", m.t, "rel L2 velocity", err)
+        assert err <= tol
+    assert fresh > 0
+    d.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16s-sr"])
+def test_sphere_lists_equal_single_forms_and_batches(gpu_lib, storage):
+    """A one-sphere list equals lbm_set_moving_sphere_motion to the bit; a
+    two-sphere domain gives the same alone and in a batch beside a one-sphere
+    domain."""
+    B = gpu_lib
+    n, steps = 40, 20
+    C, V, Om = _two_sphere_paths(steps + 2)
+
+    def dom():
+        return B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    a = dom()
+    a.set_moving_sphere_motion(5.2, C[:, 0], V[:, 0], Om[:, 0])
+    b = dom()
+    b.set_moving_spheres([5.2], C[:, :1], V[:, :1], Om[:, :1])
+    two = dom()
+    two.set_moving_spheres([5.2, 4.1], C, V, Om)
+    two_b = dom()
+    two_b.set_moving_spheres([5.2, 4.1], C, V, Om)
+    one_b = dom()
+    one_b.set_moving_sphere_motion(5.2, C[:, 0], V[:, 0], Om[:, 0])
+    a.step(steps)
+    b.step(steps)
+    two.step(steps)
+    bt = B.Batch()
+    bt.step([two_b, one_b], 7)
+    bt.step([two_b, one_b], steps - 7)
+    bt.close()
+    fa = a.get_state()
+    assert np.array_equal(fa, b.get_state())
+    assert np.array_equal(fa, one_b.get_state())
+    assert np.array_equal(two.get_state(), two_b.get_state())
+    assert not np.array_equal(fa, two.get_state())
+    for d in (a, b, two, two_b, one_b):
+        d.close()
+
+
+def test_sphere_list_validation(gpu_lib):
+    B = gpu_lib
+    n = 40
+    C, V, Om = _two_sphere_paths(8)
+
+    def dom():
+        return B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage="f32", layout="dense")
+    d = dom()
+    close = C.copy()
+    close[:, 1] = close[:, 0] + np.array([5.2 + 4.1 + 1.5, 0.0, 0.0])   # surfaces 1.5 apart
+    with pytest.raises(B.LBMError) as e:
+        d.set_moving_spheres([5.2, 4.1], close, V, Om)
+    assert e.value.code == B.LBM_EINVAL
+    five = np.concatenate([C, C, C[:, :1]], 1)
+    with pytest.raises(B.LBMError) as e:
+        d.set_moving_spheres([2.0] * 5, five, np.zeros_like(five), np.zeros_like(five))
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(ValueError):
+        d.set_moving_spheres([5.2, 4.1], C, V, Om[:, :1])
+    d.set_moving_spheres([5.2, 4.1], C, V, Om)
+    with pytest.raises(B.LBMError) as e:       # force tracking is for one sphere
+        d.set_force_tracking(True)
+    assert e.value.code == B.LBM_ESTATE
+    d.close()
+
+
 def test_sampled_path_validation(gpu_lib):
     B = gpu_lib
     n = 24

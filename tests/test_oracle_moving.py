@@ -146,6 +146,73 @@ def test_reversed_spin_mirrors_the_flow():
     np.testing.assert_allclose(ub[1][fl], -ua[1][:, ::-1, :][fl], atol=1e-15)
 
 
+def _two_paths(n, U, c_a=(5.2, 6.1, 5.3), c_b=(14.6, 13.4, 10.2)):
+    t = np.arange(n)[:, None]
+    return (np.asarray(c_a)[None, :] + t * U[None, :], np.asarray(c_b)[None, :] + t * U[None, :])
+
+
+def test_comoving_uniform_flow_with_two_spheres():
+    """Two spheres carried at the velocity of a uniform flow, rotation off, on
+    sampled paths: the flow stays uniform to round-off, fresh nodes of both
+    spheres included."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 22, 20, 16)
+    U = np.array([0.035, -0.03, 0.025])
+    n = 24
+    Ca, Cb = _two_paths(n, U)
+    Vs = np.repeat(U[None, :], n, 0)
+    zero = (0.0, 0.0, 0.0)
+    m = moving.MovingSpheresSim(dom, [3.4, 2.9], [moving.SampledKinematics(Ca, Vs, zero),
+                                                   moving.SampledKinematics(Cb, Vs, zero)], tau=0.7, rho0=1.05, u0=U)
+    fresh = 0
+    for _ in range(n - 2):
+        prev = m.sim.fluid.copy()
+        m.step()
+        fresh += int((m.sim.fluid & ~prev).sum())
+    assert fresh > 20
+    rho, u = m.sim.macros()
+    fl = m.sim.fluid
+    assert np.abs(u[:, fl] - U[:, None]).max() < 1e-13
+    assert np.abs(rho[fl] - 1.05).max() < 1e-13
+
+
+def test_two_sphere_order_does_not_matter():
+    """Spheres that stay apart give the same flow whichever is listed first
+    (each link crosses one sphere, each fresh node has one nearest sphere)."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 22, 20, 16)
+    n = 12
+    U = np.array([0.02, 0.015, -0.01])
+    Ca, Cb = _two_paths(n, U)
+    ka = moving.SampledKinematics(Ca, np.repeat(U[None, :], n, 0), (0.0, 0.0, 0.004))
+    kb = moving.SampledKinematics(Cb, np.repeat(-U[None, :], n, 0), (0.003, 0.0, 0.0))
+    a = moving.MovingSpheresSim(dom, [3.4, 2.9], [ka, kb], tau=0.8)
+    b = moving.MovingSpheresSim(dom, [2.9, 3.4], [kb, ka], tau=0.8)
+    a.run(10)
+    b.run(10)
+    assert np.array_equal(a.sim.fluid, b.sim.fluid)
+    assert np.array_equal(a.sim.f, b.sim.f, equal_nan=True)
+
+
+def test_refill_velocity_is_the_nearest_spheres():
+    """The refill's body velocity at a point is the rigid-body velocity of the
+    sphere whose surface is nearest: hand-placed points next to each sphere."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 22, 20, 16)
+    A = G.Sphere((5.0, 6.0, 5.0), 3.0, True, V=(0.01, 0.0, 0.0), Omega=(0.0, 0.0, 0.002))
+    Bs = G.Sphere((15.0, 13.0, 10.0), 2.0, True, V=(0.0, -0.02, 0.0), Omega=(0.001, 0.0, 0.0))
+    m = moving.MovingSpheresSim(dom, [3.0], [moving.Kinematics((5.0, 6.0, 5.0), 0.0, 10.0, (1, 0, 0), (0, 0, 0))],
+                                tau=0.8)
+    X = np.array([[8.5, 6.0, 5.0],      # 0.5 off A's surface, far from B
+                  [15.0, 15.5, 10.0],   # 0.5 off B's surface
+                  [10.0, 9.0, 8.0]]).T  # between them: |x - cA| - 3 = 3.56, |x - cB| - 2 = 4.92 -> A
+    u = m.body_velocity([A, Bs], X)
+    # V + Omega x (x - c) of the nearest sphere, written out per point
+    np.testing.assert_allclose(u[:, 0], [0.01 - 0.002 * 0.0, 0.0 + 0.002 * 3.5, 0.0], atol=1e-17)
+    np.testing.assert_allclose(u[:, 1], [0.0, -0.02 - 0.001 * 0.0, 0.0 + 0.001 * 2.5], atol=1e-17)
+    np.testing.assert_allclose(u[:, 2], [0.01 - 0.002 * 3.0, 0.0 + 0.002 * 5.0, 0.0], atol=1e-17)
+
+
 def test_moving_box_runs_and_conserves_mass_roughly():
     box = synth.moving_boxes(1, side_min=40, side_max=40, r_min=6, r_max=6, period=200)[0]
     lat = lattice.D3Q19

@@ -148,6 +148,8 @@ StepParams step_params(const lbm_domain_s* d, int cur) {
 MovingKin moving_kin(const lbm_domain_s* d, int64_t t) {
   MovingKin k{};
   const int ns = d->mv_ns;
+  k.ns = ns;
+  for (int sp = 0; sp < ns; ++sp) k.r[sp] = d->mv_r[sp];
   for (int a = 0; a < 3; ++a) k.Om[0][a] = k.Om1[0][a] = d->mv_om[a];
   if (!d->path_c.empty()) {
     // sampled paths ([n][ns][3]): the geometry of time t needs x_c(t), V(t),
@@ -196,8 +198,6 @@ int64_t path_steps_left(const lbm_domain_s* d) {
 MovingParams moving_params(const lbm_domain_s* d, int cur) {
   MovingParams mp{};
   mp.g = d->g;
-  mp.ns = d->mv_ns;
-  for (int sp = 0; sp < d->mv_ns; ++sp) mp.r[sp] = d->mv_r[sp];
   mp.variant = d->variant;
   mp.q_cut = d->q_cut;
   mp.reg_seg = d->reg_seg;

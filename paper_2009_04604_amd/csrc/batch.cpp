@@ -312,6 +312,7 @@ hipError_t enqueue_step(lbm_batch_s* b, int p, hipStream_t s) {
     MovingBatch mb{};
     mb.tab = static_cast<const MovingParams*>(g.mtab[p].p);
     mb.nbox = (int32_t)g.movers.size();
+    for (int m : g.movers) mb.multi |= b->members[g.members[m]]->mv_ns > 1 ? 1 : 0;
     mb.waves = static_cast<const uint32_t*>(g.waves.p);
     mb.nwaves = g.nwaves;
     mb.kin = static_cast<const MovingKin*>(b->kin.p);

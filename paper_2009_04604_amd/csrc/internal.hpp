@@ -188,6 +188,8 @@ constexpr int MAX_SPHERES = 4;
 
 // Kinematics of a domain's spheres for the geometry of time t.
 struct MovingKin {
+  int32_t ns;                               // spheres in use (1 .. MAX_SPHERES)
+  double r[MAX_SPHERES];                    // radii
   double c[MAX_SPHERES][3];                 // centres at t
   double V[MAX_SPHERES][3], V1[MAX_SPHERES][3];    // translational velocities at t and t+1
   double Om[MAX_SPHERES][3], Om1[MAX_SPHERES][3];  // angular velocities at t and t+1
@@ -199,8 +201,6 @@ struct MovingKin {
 struct MovingParams {
   GridGeom g;
   MovingKin k;                   // single-domain launches; batched launches read a table
-  int32_t ns;                    // number of spheres (1 .. MAX_SPHERES)
-  double r[MAX_SPHERES];         // radii
   int32_t kin_slot;              // batched launches: column of this sphere in the table
   int32_t variant;
   double q_cut;
@@ -276,6 +276,7 @@ hipError_t launch_step_batch(int lattice, int storage, bool compact, bool trt, b
 struct MovingBatch {
   const MovingParams* tab;
   int32_t nbox;
+  int32_t multi;                 // 1: some box holds more than one sphere
   const uint32_t* waves;
   uint32_t nwaves;
   const MovingKin* kin;

@@ -45,11 +45,19 @@ __device__ __forceinline__ double min_image(double d, int L, int periodic) {
   return __dsub_rn(d, __dmul_rn(Ld, rint(__ddiv_rn(d, Ld))));
 }
 
+// The spheres' kinematics K: the kernel argument's MovingKin (single-domain
+// launches) or a row of the batch table read through the constant address space
+// (KinTab: nothing writes it while a kernel runs, so its loads are scalar and
+// need no reload after the kernel's own stores).
+using KinTab = const __attribute__((address_space(4))) MovingKin;
+
 // position relative to sphere s's centre (minimum image on periodic axes)
-__device__ __forceinline__ void rel(const MovingParams& p, int s, double x, double y, double z, double (&d)[3]) {
-  d[0] = min_image(__dsub_rn(x, p.k.c[s][0]), p.g.nx, p.g.perx);
-  d[1] = min_image(__dsub_rn(y, p.k.c[s][1]), p.g.ny, p.g.pery);
-  d[2] = min_image(__dsub_rn(z, p.k.c[s][2]), p.g.nz, p.g.perz);
+template <class K>
+__device__ __forceinline__ void rel(const MovingParams& p, const K& k, int s, double x, double y, double z,
+                                    double (&d)[3]) {
+  d[0] = min_image(__dsub_rn(x, k.c[s][0]), p.g.nx, p.g.perx);
+  d[1] = min_image(__dsub_rn(y, k.c[s][1]), p.g.ny, p.g.pery);
+  d[2] = min_image(__dsub_rn(z, k.c[s][2]), p.g.nz, p.g.perz);
 }
 
 __device__ __forceinline__ double norm2(const double (&d)[3]) {
@@ -57,11 +65,12 @@ __device__ __forceinline__ double norm2(const double (&d)[3]) {
 }
 
 // solid (inside or on some sphere) at integer node coordinates
-__device__ __forceinline__ bool solid_at(const MovingParams& p, int x, int y, int z) {
-  for (int s = 0; s < p.ns; ++s) {
+template <bool M, class K>
+__device__ __forceinline__ bool solid_at(const MovingParams& p, const K& k, int x, int y, int z) {
+  for (int s = 0; s < (M ? k.ns : 1); ++s) {
     double d[3];
-    rel(p, s, (double)x, (double)y, (double)z, d);
-    if (norm2(d) <= __dmul_rn(p.r[s], p.r[s])) return true;
+    rel(p, k, s, (double)x, (double)y, (double)z, d);
+    if (norm2(d) <= __dmul_rn(k.r[s], k.r[s])) return true;
   }
   return false;
 }
@@ -73,14 +82,16 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic) {
 
 // entering root lam of x_F - lam c with sphere s; `reach` tells whether it lies
 // on the segment (0, 1] (a root within 1e-12 of the segment's ends counts)
-__device__ __forceinline__ double crossing(const MovingParams& p, int s, int x, int y, int z, int cx, int cy, int cz,
+template <class K>
+__device__ __forceinline__ double crossing(const MovingParams& p, const K& k, int s, int x, int y, int z, int cx,
+                                           int cy, int cz,
                                            bool& reach) {
   double d[3];
-  rel(p, s, (double)x, (double)y, (double)z, d);
+  rel(p, k, s, (double)x, (double)y, (double)z, d);
   const double c[3] = {(double)cx, (double)cy, (double)cz};
   const double A = __dadd_rn(__dadd_rn(__dmul_rn(c[0], c[0]), __dmul_rn(c[1], c[1])), __dmul_rn(c[2], c[2]));
   const double B = __dadd_rn(__dadd_rn(__dmul_rn(d[0], c[0]), __dmul_rn(d[1], c[1])), __dmul_rn(d[2], c[2]));
-  const double C0 = __dsub_rn(norm2(d), __dmul_rn(p.r[s], p.r[s]));
+  const double C0 = __dsub_rn(norm2(d), __dmul_rn(k.r[s], k.r[s]));
   const double disc = __dsub_rn(__dmul_rn(B, B), __dmul_rn(A, C0));
   const double sq = disc >= 0.0 ? __dsqrt_rn(disc) : 0.0;
   const double lam = __ddiv_rn(__dsub_rn(B, sq), A);
@@ -90,15 +101,17 @@ __device__ __forceinline__ double crossing(const MovingParams& p, int s, int x, 
 
 // first crossing lam in (0, 1] of a cut link over the spheres (the first
 // sphere wins a tie; with one sphere, that sphere's root) and the sphere crossed
-__device__ __forceinline__ double first_crossing(const MovingParams& p, int x, int y, int z, int cx, int cy, int cz,
+template <bool M, class K>
+__device__ __forceinline__ double first_crossing(const MovingParams& p, const K& k, int x, int y, int z, int cx,
+                                                 int cy, int cz,
                                                  int& owner) {
   // roots are compared after clamping onto the segment, as the host builder does
   bool reach;
-  double best = fmin(fmax(crossing(p, 0, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
+  double best = fmin(fmax(crossing(p, k, 0, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
   bool found = reach;
   owner = 0;
-  for (int s = 1; s < p.ns; ++s) {
-    const double lam = fmin(fmax(crossing(p, s, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
+  for (int s = 1; s < (M ? k.ns : 1); ++s) {
+    const double lam = fmin(fmax(crossing(p, k, s, x, y, z, cx, cy, cz, reach), 1e-12), 1.0);
     if (reach && (!found || lam < best)) {
       best = lam;
       owner = s;
@@ -109,13 +122,14 @@ __device__ __forceinline__ double first_crossing(const MovingParams& p, int x, i
 }
 
 // the sphere whose surface is nearest to (x, y, z) (the first one on a tie)
-__device__ __forceinline__ int nearest_sphere(const MovingParams& p, double x, double y, double z) {
+template <bool M, class K>
+__device__ __forceinline__ int nearest_sphere(const MovingParams& p, const K& k, double x, double y, double z) {
   int best_s = 0;
   double best = 0.0;
-  for (int s = 0; s < p.ns; ++s) {
+  for (int s = 0; s < (M ? k.ns : 1); ++s) {
     double d[3];
-    rel(p, s, x, y, z, d);
-    const double gap = __dsub_rn(__dsqrt_rn(norm2(d)), p.r[s]);
+    rel(p, k, s, x, y, z, d);
+    const double gap = __dsub_rn(__dsqrt_rn(norm2(d)), k.r[s]);
     if (s == 0 || gap < best) {
       best = gap;
       best_s = s;
@@ -133,39 +147,38 @@ __device__ __forceinline__ void body_velocity(const double (&Om)[3], const doubl
 }
 
 // cut directions of the fluid node (x, y, z): source x - c_i inside the sphere
-template <class L>
-__device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, int x, int y, int z) {
+template <class L, bool M, class K>
+__device__ __forceinline__ uint32_t cut_mask(const MovingParams& p, const K& k, int x, int y, int z) {
   const GridGeom& g = p.g;
   uint32_t m = 0u;
-  // a node farther than r + 2 from every centre has no neighbour (|c_i| <= sqrt 3) in a sphere
-  {
-    bool near = false;
-    for (int s2 = 0; s2 < p.ns; ++s2) {
-      double d[3];
-      rel(p, s2, (double)x, (double)y, (double)z, d);
-      const double far = p.r[s2] + 2.0;
-      near = near || norm2(d) <= far * far;
-    }
-    if (!near) return m;
-  }
+  for (int s = 0; s < (M ? k.ns : 1); ++s) {
+    // a node farther than r + 2 from the centre has no neighbour (|c_i| <= sqrt 3) in the sphere
+    double d[3];
+    rel(p, k, s, (double)x, (double)y, (double)z, d);
+    const double far = k.r[s] + 2.0;
+    if (norm2(d) > far * far) continue;
+    const double r2 = __dmul_rn(k.r[s], k.r[s]);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) {
-    const int sx = wrap(x - L::cx(i), g.nx, g.perx);
-    const int sy = wrap(y - L::cy(i), g.ny, g.pery);
-    const int sz = wrap(z - L::cz(i), g.nz, g.perz);
-    if (solid_at(p, sx, sy, sz)) m |= 1u << i;
+    for (int i = 1; i < L::Q; ++i) {
+      const int sx = wrap(x - L::cx(i), g.nx, g.perx);
+      const int sy = wrap(y - L::cy(i), g.ny, g.pery);
+      const int sz = wrap(z - L::cz(i), g.nz, g.perz);
+      double e[3];
+      rel(p, k, s, (double)sx, (double)sy, (double)sz, e);
+      if (norm2(e) <= r2) m |= 1u << i;
+    }
   }
   return m;
 }
 
-template <class L>
-__device__ __forceinline__ void classify_body(const MovingParams& p, int64_t wave) {
+template <class L, bool M, class K>
+__device__ __forceinline__ void classify_body(const MovingParams& p, const K& k, int64_t wave) {
   const Site s = region_site(p, wave);
   const GridGeom& g = p.g;
   const bool in = s.x < g.nx;
-  const bool fluid = in && !solid_at(p, s.x, s.y, s.z);
+  const bool fluid = in && !solid_at<M>(p, k, s.x, s.y, s.z);
   const uint64_t fm = __ballot(fluid);
-  const uint32_t cm = fluid ? cut_mask<L>(p, s.x, s.y, s.z) : 0u;
+  const uint32_t cm = fluid ? cut_mask<L, M, K>(p, k, s.x, s.y, s.z) : 0u;
   p.reg_cut[wave * 64 + s.lane] = cm;   // read back by fill in the same rebuild
   const int cnt = __popc(cm);
   const uint64_t bm = __ballot(cnt > 0);
@@ -223,8 +236,8 @@ __device__ __forceinline__ void region_scan_body(const MovingParams& p) {
   }
 }
 
-template <class L, typename R>
-__device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
+template <class L, typename R, bool M, class K>
+__device__ __forceinline__ void fill_body(const MovingParams& p, const K& kn, int64_t wave) {
   if (p.reg_count[wave] == 0) return;   // wave-uniform: no cut link in this segment
   const Site s = region_site(p, wave);
   const uint32_t cm = p.reg_cut[wave * 64 + s.lane];   // classify's cut directions (0 off the fluid)
@@ -243,15 +256,17 @@ __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
     if (!((cm >> i) & 1u)) continue;
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     int o;
-    const double q = first_crossing(p, s.x, s.y, s.z, cx, cy, cz, o);
+    const double q = first_crossing<M>(p, kn, s.x, s.y, s.z, cx, cy, cz, o);
     // wall point and its rigid-body velocity at t and t+1 (of the sphere crossed)
     const double xw[3] = {__dsub_rn((double)s.x, __dmul_rn(q, (double)cx)), __dsub_rn((double)s.y, __dmul_rn(q, (double)cy)),
                           __dsub_rn((double)s.z, __dmul_rn(q, (double)cz))};
     double r[3];
-    rel(p, o, xw[0], xw[1], xw[2], r);
+    rel(p, kn, o, xw[0], xw[1], xw[2], r);
     double u0[3], u1[3];
-    body_velocity(p.k.Om[o], p.k.V[o], r, u0);
-    body_velocity(p.k.Om1[o], p.k.V1[o], r, u1);
+    const double Om0[3] = {kn.Om[o][0], kn.Om[o][1], kn.Om[o][2]}, Om1[3] = {kn.Om1[o][0], kn.Om1[o][1], kn.Om1[o][2]};
+    const double V0[3] = {kn.V[o][0], kn.V[o][1], kn.V[o][2]}, V1[3] = {kn.V1[o][0], kn.V1[o][1], kn.V1[o][2]};
+    body_velocity(Om0, V0, r, u0);
+    body_velocity(Om1, V1, r, u1);
     if (L::D == 2) u0[2] = u1[2] = 0.0;
     const double cu0 = cx * u0[0] + cy * u0[1] + cz * u0[2];
     const double cu1 = cx * u1[0] + cy * u1[1] + cz * u1[2];
@@ -276,8 +291,8 @@ __device__ __forceinline__ void fill_body(const MovingParams& p, int64_t wave) {
 
 // fresh nodes (solid at t-1, fluid at t): f = f^eq(rho_bar, u_body(x)), rho_bar the
 // mean density of the neighbours that are fluid at t-1 and t (rho0 if none)
-template <class L, int S>
-__device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave) {
+template <class L, int S, bool M, class K>
+__device__ __forceinline__ void refill_body(const MovingParams& p, const K& kn, int64_t wave) {
   using St = Storage<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -314,9 +329,10 @@ __device__ __forceinline__ void refill_body(const MovingParams& p, int64_t wave)
   }
   const double rb = cnt > 0 ? tot / cnt : p.rho0;
   double r[3], u[3];
-  const int o = nearest_sphere(p, (double)s.x, (double)s.y, (double)s.z);
-  rel(p, o, (double)s.x, (double)s.y, (double)s.z, r);
-  body_velocity(p.k.Om[o], p.k.V[o], r, u);
+  const int o = nearest_sphere<M>(p, kn, (double)s.x, (double)s.y, (double)s.z);
+  rel(p, kn, o, (double)s.x, (double)s.y, (double)s.z, r);
+  const double Om0[3] = {kn.Om[o][0], kn.Om[o][1], kn.Om[o][2]}, V0[3] = {kn.V[o][0], kn.V[o][1], kn.V[o][2]};
+  body_velocity(Om0, V0, r, u);
   if (L::D == 2) u[2] = 0.0;
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -378,7 +394,7 @@ __device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, 
     }
     const double q = (double)lq[k];
     double r[3], u[3];
-    rel(p, 0, x - q * cx, s.y - q * cy, s.z - q * cz, r);   // force tracking: one sphere
+    rel(p, p.k, 0, x - q * cx, s.y - q * cy, s.z - q * cz, r);   // force tracking: one sphere
     body_velocity(p.k.Om[0], p.k.V[0], r, u);
     if (L::D == 2) u[2] = r[2] = 0.0;
     const double c[3] = {(double)cx, (double)cy, (double)cz};
@@ -396,24 +412,24 @@ __device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, 
 }
 
 // Single sphere: one wave per region segment.
-template <class L>
+template <class L, bool M>
 __global__ __launch_bounds__(256) void classify_kernel(MovingParams p) {
   const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave < p.nreg) classify_body<L>(p, wave);
+  if (wave < p.nreg) classify_body<L, M>(p, p.k, wave);
 }
 
 __global__ __launch_bounds__(1024) void region_scan_kernel(MovingParams p) { region_scan_body(p); }
 
-template <class L, typename R>
+template <class L, typename R, bool M>
 __global__ __launch_bounds__(256) void fill_kernel(MovingParams p) {
   const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave < p.nreg) fill_body<L, R>(p, wave);
+  if (wave < p.nreg) fill_body<L, R, M>(p, p.k, wave);
 }
 
-template <class L, int S>
+template <class L, int S, bool M>
 __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
   const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave < p.nreg) refill_body<L, S>(p, wave);
+  if (wave < p.nreg) refill_body<L, S, M>(p, p.k, wave);
 }
 
 template <class L, int S>
@@ -444,39 +460,43 @@ __device__ __forceinline__ MovingParams table_entry(const MovingParams* e) {
 
 // Batched spheres: the wave table names (sphere, region wave); the kinematics
 // come from row *ctr of the table.
-__device__ __forceinline__ bool batch_wave(const MovingBatch& b, MovingParams& p, int64_t& wave) {
+__device__ __forceinline__ bool batch_wave(const MovingBatch& b, MovingParams& p, KinTab*& kp, int64_t& wave) {
   const uint32_t gw = blockIdx.x * 4u + threadIdx.x / 64u;
   if (gw >= b.nwaves) return false;
   const uint32_t w = __builtin_amdgcn_readfirstlane(b.waves[gw]);
   p = table_entry(b.tab + (w >> TILE_SHIFT));
-  p.k = b.kin[*b.ctr * b.nkin + p.kin_slot];
+  // the kinematics stay in the table (read where used, not copied)
+  kp = (KinTab*)(b.kin + (*b.ctr * b.nkin + p.kin_slot));
   wave = (int64_t)(w & TILE_MASK);
   return true;
 }
 
-template <class L>
+template <class L, bool M>
 __global__ __launch_bounds__(256) void classify_batch_kernel(MovingBatch b) {
   MovingParams p;
+  KinTab* kp;
   int64_t wave;
-  if (batch_wave(b, p, wave)) classify_body<L>(p, wave);
+  if (batch_wave(b, p, kp, wave)) classify_body<L, M>(p, *kp, wave);
 }
 
 __global__ __launch_bounds__(1024) void region_scan_batch_kernel(MovingBatch b) {
   region_scan_body(table_entry(b.tab + blockIdx.x));
 }
 
-template <class L, typename R>
+template <class L, typename R, bool M>
 __global__ __launch_bounds__(256) void fill_batch_kernel(MovingBatch b) {
   MovingParams p;
+  KinTab* kp;
   int64_t wave;
-  if (batch_wave(b, p, wave)) fill_body<L, R>(p, wave);
+  if (batch_wave(b, p, kp, wave)) fill_body<L, R, M>(p, *kp, wave);
 }
 
-template <class L, int S>
+template <class L, int S, bool M>
 __global__ __launch_bounds__(256) void refill_batch_kernel(MovingBatch b) {
   MovingParams p;
+  KinTab* kp;
   int64_t wave;
-  if (batch_wave(b, p, wave)) refill_body<L, S>(p, wave);
+  if (batch_wave(b, p, kp, wave)) refill_body<L, S, M>(p, *kp, wave);
 }
 
 __global__ void advance_kernel(int64_t* ctr) {
@@ -487,11 +507,20 @@ __global__ void advance_kernel(int64_t* ctr) {
 
 static inline dim3 region_grid(const MovingParams& p) { return dim3((unsigned)((p.nreg + 3) / 4)); }
 
+// The kernels come in a one-sphere form (M = false: the sphere loops are a
+// single iteration known at compile time, as fast as a kernel for one sphere)
+// and a form for several spheres per domain.
+template <bool M>
+static void classify_launch(int lattice, const MovingParams& p, hipStream_t s) {
+  if (lattice == LBM_D2Q9) classify_kernel<D2Q9, M><<<region_grid(p), 256, 0, s>>>(p);
+  else if (lattice == LBM_D3Q19) classify_kernel<D3Q19, M><<<region_grid(p), 256, 0, s>>>(p);
+  else classify_kernel<D3Q27, M><<<region_grid(p), 256, 0, s>>>(p);
+}
+
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s) {
   if (p.nreg == 0) return hipSuccess;
-  if (lattice == LBM_D2Q9) classify_kernel<D2Q9><<<region_grid(p), 256, 0, s>>>(p);
-  else if (lattice == LBM_D3Q19) classify_kernel<D3Q19><<<region_grid(p), 256, 0, s>>>(p);
-  else classify_kernel<D3Q27><<<region_grid(p), 256, 0, s>>>(p);
+  if (p.k.ns > 1) classify_launch<true>(lattice, p, s);
+  else classify_launch<false>(lattice, p, s);
   return hipGetLastError();
 }
 
@@ -500,30 +529,36 @@ hipError_t launch_region_scan(const MovingParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <bool M>
+static void fill_launch(int lattice, bool f64, const MovingParams& p, hipStream_t s) {
+  if (lattice == LBM_D2Q9) {
+    if (f64) fill_kernel<D2Q9, double, M><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D2Q9, float, M><<<region_grid(p), 256, 0, s>>>(p);
+  } else if (lattice == LBM_D3Q19) {
+    if (f64) fill_kernel<D3Q19, double, M><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D3Q19, float, M><<<region_grid(p), 256, 0, s>>>(p);
+  } else {
+    if (f64) fill_kernel<D3Q27, double, M><<<region_grid(p), 256, 0, s>>>(p);
+    else fill_kernel<D3Q27, float, M><<<region_grid(p), 256, 0, s>>>(p);
+  }
+}
+
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s) {
   if (p.nreg == 0) return hipSuccess;
   const bool f64 = storage == ST_F64;
-  if (lattice == LBM_D2Q9) {
-    if (f64) fill_kernel<D2Q9, double><<<region_grid(p), 256, 0, s>>>(p);
-    else fill_kernel<D2Q9, float><<<region_grid(p), 256, 0, s>>>(p);
-  } else if (lattice == LBM_D3Q19) {
-    if (f64) fill_kernel<D3Q19, double><<<region_grid(p), 256, 0, s>>>(p);
-    else fill_kernel<D3Q19, float><<<region_grid(p), 256, 0, s>>>(p);
-  } else {
-    if (f64) fill_kernel<D3Q27, double><<<region_grid(p), 256, 0, s>>>(p);
-    else fill_kernel<D3Q27, float><<<region_grid(p), 256, 0, s>>>(p);
-  }
+  if (p.k.ns > 1) fill_launch<true>(lattice, f64, p, s);
+  else fill_launch<false>(lattice, f64, p, s);
   return hipGetLastError();
 }
 
-hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s) {
-  if (p.nreg == 0) return hipSuccess;
+template <bool M>
+static void refill_launch(int lattice, int storage, const MovingParams& p, hipStream_t s) {
 #define LBM_REFILL(LAT)                                                                     \
   switch (storage) {                                                                        \
-    case ST_F64: refill_kernel<LAT, ST_F64><<<region_grid(p), 256, 0, s>>>(p); break;       \
-    case ST_F32: refill_kernel<LAT, ST_F32><<<region_grid(p), 256, 0, s>>>(p); break;       \
-    case ST_F16S: refill_kernel<LAT, ST_F16S><<<region_grid(p), 256, 0, s>>>(p); break;     \
-    default: refill_kernel<LAT, ST_BF16S><<<region_grid(p), 256, 0, s>>>(p); break;         \
+    case ST_F64: refill_kernel<LAT, ST_F64, M><<<region_grid(p), 256, 0, s>>>(p); break;    \
+    case ST_F32: refill_kernel<LAT, ST_F32, M><<<region_grid(p), 256, 0, s>>>(p); break;    \
+    case ST_F16S: refill_kernel<LAT, ST_F16S, M><<<region_grid(p), 256, 0, s>>>(p); break;  \
+    default: refill_kernel<LAT, ST_BF16S, M><<<region_grid(p), 256, 0, s>>>(p); break;      \
   }
   if (lattice == LBM_D2Q9) {
     LBM_REFILL(D2Q9)
@@ -533,6 +568,12 @@ hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p,
     LBM_REFILL(D3Q27)
   }
 #undef LBM_REFILL
+}
+
+hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s) {
+  if (p.nreg == 0) return hipSuccess;
+  if (p.k.ns > 1) refill_launch<true>(lattice, storage, p, s);
+  else refill_launch<false>(lattice, storage, p, s);
   return hipGetLastError();
 }
 
@@ -560,20 +601,20 @@ hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, 
   return launch_group_sum(contrib, nullptr, 0, p.seg_lbase + p.g.nseg, 1, out, s);
 }
 
-hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s) {
-  if (b.nbox == 0) return hipSuccess;
+template <bool M>
+static void moving_batch_launch(int lattice, int storage, const MovingBatch& b, hipStream_t s) {
   const dim3 grid((b.nwaves + 3) / 4);
   const bool f64 = storage == ST_F64;
 #define LBM_MOVING_BATCH(LAT)                                                                  \
-  classify_batch_kernel<LAT><<<grid, 256, 0, s>>>(b);                                          \
+  classify_batch_kernel<LAT, M><<<grid, 256, 0, s>>>(b);                                       \
   region_scan_batch_kernel<<<b.nbox, 1024, 0, s>>>(b);                                         \
-  if (f64) fill_batch_kernel<LAT, double><<<grid, 256, 0, s>>>(b);                             \
-  else fill_batch_kernel<LAT, float><<<grid, 256, 0, s>>>(b);                                  \
+  if (f64) fill_batch_kernel<LAT, double, M><<<grid, 256, 0, s>>>(b);                          \
+  else fill_batch_kernel<LAT, float, M><<<grid, 256, 0, s>>>(b);                               \
   switch (storage) {                                                                           \
-    case ST_F64: refill_batch_kernel<LAT, ST_F64><<<grid, 256, 0, s>>>(b); break;              \
-    case ST_F32: refill_batch_kernel<LAT, ST_F32><<<grid, 256, 0, s>>>(b); break;              \
-    case ST_F16S: refill_batch_kernel<LAT, ST_F16S><<<grid, 256, 0, s>>>(b); break;            \
-    default: refill_batch_kernel<LAT, ST_BF16S><<<grid, 256, 0, s>>>(b); break;                \
+    case ST_F64: refill_batch_kernel<LAT, ST_F64, M><<<grid, 256, 0, s>>>(b); break;           \
+    case ST_F32: refill_batch_kernel<LAT, ST_F32, M><<<grid, 256, 0, s>>>(b); break;           \
+    case ST_F16S: refill_batch_kernel<LAT, ST_F16S, M><<<grid, 256, 0, s>>>(b); break;         \
+    default: refill_batch_kernel<LAT, ST_BF16S, M><<<grid, 256, 0, s>>>(b); break;             \
   }
   if (lattice == LBM_D2Q9) {
     LBM_MOVING_BATCH(D2Q9)
@@ -583,6 +624,12 @@ hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, h
     LBM_MOVING_BATCH(D3Q27)
   }
 #undef LBM_MOVING_BATCH
+}
+
+hipError_t launch_moving_batch(int lattice, int storage, const MovingBatch& b, hipStream_t s) {
+  if (b.nbox == 0) return hipSuccess;
+  if (b.multi) moving_batch_launch<true>(lattice, storage, b, s);
+  else moving_batch_launch<false>(lattice, storage, b, s);
   return hipGetLastError();
 }
 

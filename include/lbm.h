@@ -214,8 +214,8 @@ int lbm_set_moving_sphere_motion(lbm_domain d, double radius, int64_t n_samples,
  * node takes the rigid-body velocity of the sphere whose surface is nearest.
  * The sweep region is the union of the spheres' sweep boxes.  The surfaces must
  * stay more than two nodes apart at every sample (LBM_EINVAL otherwise, naming
- * the pair and the sample); force tracking (lbm_set_force_tracking) is for one
- * sphere (LBM_ESTATE).  Other errors as lbm_set_moving_sphere_motion. */
+ * the pair and the sample).  Force tracking gives one force and torque per
+ * sphere (lbm_moving_forces).  Other errors as lbm_set_moving_sphere_motion. */
 int lbm_set_moving_spheres(lbm_domain d, int32_t n_spheres, const double* radius, int64_t n_samples,
                            const double* centre, const double* velocity, const double* omega, int32_t variant,
                            double q_cutoff);
@@ -312,12 +312,18 @@ int lbm_force_torque(lbm_domain d, const double* centres, double* force, double*
  *   T = sum r x F_link,  r = x_W - x_c(t) (minimum image), x_W = x_F - q c_i,
  * u_w = V(t) + omega x r, summed in FP64 in a fixed order; lbm_moving_force
  * copies the result out (force, torque: 3 doubles each, caller-owned;
- * synchronises the stream).  Batched steps (lbm_batch_step) do not evaluate it.
+ * synchronises the stream).  With several spheres (lbm_set_moving_spheres)
+ * each link counts for the sphere that holds its solid node, with that
+ * sphere's x_c, V and omega, and lbm_moving_forces copies n_spheres (the
+ * domain's count, LBM_EINVAL otherwise) forces and torques out as
+ * [n_spheres][3] each; lbm_moving_force is the one-sphere form (LBM_EINVAL
+ * with several).  Batched steps (lbm_batch_step) do not evaluate it.
  * Errors: LBM_ESTATE without a moving sphere, with tracking off, or when the
  * last step was not taken by lbm_step with tracking on; LBM_ENOMEM when the
  * per-link scratch cannot be allocated (done by lbm_set_force_tracking). */
 int lbm_set_force_tracking(lbm_domain d, int32_t on);
 int lbm_moving_force(lbm_domain d, double* force, double* torque);
+int lbm_moving_forces(lbm_domain d, int32_t n_spheres, double* force, double* torque);
 
 /* Change the stream used by later calls. */
 int lbm_set_stream(lbm_domain d, void* stream);

@@ -21,7 +21,9 @@ samples and against the co-moving invariant on a straight path; a sampled spin
 against the constant spin it repeats, its time index (an impulsive spin-up
 moves the walls at t+1 only) and the mirror symmetry of a reversed spin;
 several spheres by the co-moving invariant with two spheres, the independence
-of their order and hand-placed refill points; the refill
+of their order (flow, and each sphere's force and torque) and hand-placed
+refill points; the per-sphere force and torque (links grouped by the sphere
+they cross, torques about each centre) by two mirror-image spheres; the refill
 rule against hand-listed
 neighbour sets (tests/test_oracle_refill.py); the co-moving invariant (a sphere
 moving at the velocity of a uniform flow leaves it unchanged, refills
@@ -139,8 +141,10 @@ class MovingSpheresSim:
         self.sim.set_geometry(fluid, links, self.variant, self.q_cut, wall_neq=self.wall_neq)
 
     def step(self):
-        # torques about the (first) sphere's centre at the geometry's time t
-        self.sim.centres = self.kins[0].centre(self.t)[None, :].copy()
+        # one force group per sphere (the sphere each link crosses), torques about
+        # the sphere centres at the geometry's time t
+        self.sim.set_link_groups(self.sim.links["shape"], len(self.kins),
+                                 np.array([k.centre(self.t) for k in self.kins]))
         self.sim.step()
         self.t += 1
         self._install()

@@ -38,7 +38,7 @@ EXPORTED = [
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_option", "lbm_batch_autotune", "lbm_batch_get_choice",
     "lbm_batch_free", "lbm_step_batch", "lbm_set_link_groups", "lbm_momentum_exchange", "lbm_geometry_get_shapes",
     "lbm_set_wall_neq", "lbm_geometry_add_cylinder", "lbm_force_torque", "lbm_set_force_tracking",
-    "lbm_moving_force", "lbm_macros_noalloc", "lbm_stream_probe", "lbm_set_moving_sphere_path",
+    "lbm_moving_force", "lbm_moving_forces", "lbm_macros_noalloc", "lbm_stream_probe", "lbm_set_moving_sphere_path",
     "lbm_set_moving_sphere_motion", "lbm_set_moving_spheres",
 ]
 BATCH_OPTIONS = {"graph": 0, "grid": 1, "order": 2, "autotune": 3}
@@ -128,6 +128,7 @@ def lib():
         "lbm_force_torque": (I32, [P, P, P, P]),
         "lbm_set_force_tracking": (I32, [P, I32]),
         "lbm_moving_force": (I32, [P, P, P]),
+        "lbm_moving_forces": (I32, [P, I32, P, P]),
         "lbm_macros_noalloc": (I32, [P, P, P, P]),
         "lbm_stream_probe": (I32, [P, P, I64, I64, I32, I32, P]),
     }
@@ -418,6 +419,13 @@ class Domain:
         """(force (3,), torque (3,)) on the moving sphere during the last step."""
         f, t = np.zeros(3), np.zeros(3)
         _check(lib().lbm_moving_force(self.h, _ptr(f), _ptr(t)))
+        return f, t
+
+    def moving_forces(self, n_spheres):
+        """(force (n, 3), torque (n, 3)) on each of the domain's n moving spheres
+        during the last step, torques about each sphere's own centre."""
+        f, t = np.zeros((n_spheres, 3)), np.zeros((n_spheres, 3))
+        _check(lib().lbm_moving_forces(self.h, int(n_spheres), _ptr(f), _ptr(t)))
         return f, t
 
     def set_launch_option(self, option, value):

@@ -273,6 +273,8 @@ void free_links(lbm_domain_s* d) {
   dfree(d->lgrp);
   dfree(d->lforce);
   dfree(d->gforce);
+  dfree(d->mforce);    // sized by the link capacity: set again with it
+  dfree(d->mgroup);
   d->link_order.clear();
   d->n_groups = 1;
   d->nb = d->nl = 0;
@@ -603,6 +605,11 @@ int install_moving(lbm_domain d, int ns, const double (*lo_c)[3], const double (
   if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
   if (d->wall_neq == LBM_NEQ_REGULARIZED)
     if (int e = dalloc(d->luv, 6 * d->link_cap * rs)) return e;
+  if (d->track_force) {
+    if (int e = dalloc(d->mforce, ((size_t)d->link_cap + MAX_SPHERES) * 6 * 8)) return e;
+    if (int e = dalloc(d->mgroup, (size_t)d->link_cap * 4)) return e;
+    d->force_step = -1;
+  }
   HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));
@@ -744,7 +751,7 @@ int lbm_step(lbm_domain d, int32_t n_steps) {
         // force and torque on the links of the geometry this step used, before the rebuild
         MovingParams mp = moving_params(d, d->cur);
         mp.k = moving_kin(d, d->steps - 1);
-        e = launch_moving_force(d->desc.lattice, d->desc.storage, mp, d->mforce, d->mforce + 6 * d->link_cap,
+        e = launch_moving_force(d->desc.lattice, d->desc.storage, mp, d->mforce, d->mgroup, d->mforce + 6 * d->link_cap,
                                 d->stream);
         if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("moving force: ") + hipGetErrorString(e));
         d->force_step = d->steps;
@@ -915,29 +922,40 @@ int lbm_set_force_tracking(lbm_domain d, int32_t on) {
   if (!d) return fail(LBM_EINVAL, "null domain");
   if (!d->moving) return fail(LBM_ESTATE, "force tracking is for moving spheres (static links: lbm_force_torque)");
   if (on != 0 && on != 1) return fail(LBM_EINVAL, "on must be 0 or 1");
-  if (on && d->mv_ns > 1) return fail(LBM_ESTATE, "force tracking covers a domain with one moving sphere");
   if (on && !d->mforce)
-    if (int e = dalloc(d->mforce, ((size_t)d->link_cap + 1) * 6 * 8)) return e;
+    if (int e = dalloc(d->mforce, ((size_t)d->link_cap + MAX_SPHERES) * 6 * 8)) return e;
+  if (on && !d->mgroup)
+    if (int e = dalloc(d->mgroup, (size_t)d->link_cap * 4)) return e;
   d->track_force = on != 0;
   d->force_step = -1;
   clear_error();
   return LBM_OK;
 }
 
-int lbm_moving_force(lbm_domain d, double* force, double* torque) {
+int lbm_moving_forces(lbm_domain d, int32_t n_spheres, double* force, double* torque) {
   if (!d || !force || !torque) return fail(LBM_EINVAL, "null argument");
   if (!d->moving || !d->track_force) return fail(LBM_ESTATE, "force tracking is not on (lbm_set_force_tracking)");
+  if (n_spheres != d->mv_ns)
+    return fail(LBM_EINVAL, "the domain has " + std::to_string(d->mv_ns) + " moving sphere(s)");
   if (d->force_step != d->steps)
     return fail(LBM_ESTATE, "the last step was not taken by lbm_step with tracking on (or none was taken)");
-  double h[6];
-  HIP_TRY(hipMemcpyAsync(h, d->mforce + 6 * d->link_cap, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  double h[6 * MAX_SPHERES];
+  HIP_TRY(hipMemcpyAsync(h, d->mforce + 6 * d->link_cap, 6 * n_spheres * sizeof(double), hipMemcpyDeviceToHost,
+                         d->stream));
   HIP_TRY(hipStreamSynchronize(d->stream));
-  for (int a = 0; a < 3; ++a) {
-    force[a] = h[a];
-    torque[a] = h[3 + a];
-  }
+  for (int sp = 0; sp < n_spheres; ++sp)
+    for (int a = 0; a < 3; ++a) {
+      force[3 * sp + a] = h[6 * sp + a];
+      torque[3 * sp + a] = h[6 * sp + 3 + a];
+    }
   clear_error();
   return LBM_OK;
+}
+
+int lbm_moving_force(lbm_domain d, double* force, double* torque) {
+  if (!d || !force || !torque) return fail(LBM_EINVAL, "null argument");
+  if (d->moving && d->mv_ns != 1) return fail(LBM_EINVAL, "several moving spheres: lbm_moving_forces");
+  return lbm_moving_forces(d, 1, force, torque);
 }
 
 int lbm_stream_probe(const float* src, float* dst, int64_t n, int64_t stride, int32_t arrays, int32_t shift,
@@ -1017,7 +1035,6 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->seg_prev);
   dfree(d->reg_count);
   dfree(d->reg_cut);
-  dfree(d->mforce);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

@@ -261,10 +261,11 @@ hipError_t launch_stream_probe(const float* src, float* dst, int64_t n, int64_t 
 hipError_t launch_group_sum(const double* contrib, const int32_t* group, int64_t nl, const int32_t* nl_dev,
                             int32_t n_groups, double* out, hipStream_t s);
 hipError_t launch_moving_classify(int lattice, const MovingParams& p, hipStream_t s);
-// force and torque of the moving sphere over the links of the geometry the last
-// step used (before the rebuild); contrib: [6 link_cap] scratch, out: [6]
-hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, double* contrib, double* out,
-                               hipStream_t s);
+// force and torque of the moving spheres over the links of the geometry the last
+// step used (before the rebuild); contrib: [6 link_cap] scratch, grp: [link_cap]
+// scratch (the sphere of each link), out: [ns][6]
+hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, double* contrib, int32_t* grp,
+                               double* out, hipStream_t s);
 hipError_t launch_region_scan(const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_fill(int lattice, int storage, const MovingParams& p, hipStream_t s);
 hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p, hipStream_t s);
@@ -351,7 +352,8 @@ struct lbm_domain_s {
   int64_t link_cap;
   bool track_force;                  // lbm_set_force_tracking: force of the last step of each lbm_step call
   int64_t force_step;                // steps when that force was computed
-  double* mforce;                    // [6 link_cap] per-link contributions, then [6] the sums
+  double* mforce;                    // [6 link_cap] per-link contributions, then [ns][6] the sums
+  int32_t* mgroup;                   // [link_cap] the sphere of each link (several spheres)
   // momentum-exchange force (static link list)
   std::vector<int64_t> link_order;   // position in the caller's list of each stored link
   double* luw;                       // [3 nl] wall velocity at t, or null

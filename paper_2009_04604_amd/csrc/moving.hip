@@ -355,7 +355,7 @@ __device__ __forceinline__ void refill_body(const MovingParams& p, const K& kn, 
 // step stored in the solid-side slot x_F - c_i.  `pop` is the buffer the step
 // wrote; out receives 6 doubles per link.
 template <class L, int S>
-__device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, double* out) {
+__device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, double* out, int32_t* grp) {
   using St = Storage<S>;
   using T = typename St::T;
   using R = typename St::R;
@@ -393,9 +393,21 @@ __device__ __forceinline__ void force_body(const MovingParams& p, int64_t wave, 
                                                                wrap(s.z - cz, g.nz, g.perz)), j) + w;
     }
     const double q = (double)lq[k];
+    // the sphere the link crosses: the one holding its solid source node (the
+    // spheres keep more than two nodes apart, so a link reaches one of them)
+    int own = 0;
+    for (int sp = 1; sp < p.k.ns; ++sp) {
+      double e[3];
+      rel(p, p.k, sp, (double)wrap(x - cx, g.nx, g.perx), (double)wrap(s.y - cy, g.ny, g.pery),
+          (double)wrap(s.z - cz, g.nz, g.perz), e);
+      if (norm2(e) <= __dmul_rn(p.k.r[sp], p.k.r[sp])) own = sp;
+    }
     double r[3], u[3];
-    rel(p, p.k, 0, x - q * cx, s.y - q * cy, s.z - q * cz, r);   // force tracking: one sphere
-    body_velocity(p.k.Om[0], p.k.V[0], r, u);
+    rel(p, p.k, own, x - q * cx, s.y - q * cy, s.z - q * cz, r);
+    const double Om0[3] = {p.k.Om[own][0], p.k.Om[own][1], p.k.Om[own][2]};
+    const double V0[3] = {p.k.V[own][0], p.k.V[own][1], p.k.V[own][2]};
+    body_velocity(Om0, V0, r, u);
+    if (grp) grp[k] = own;
     if (L::D == 2) u[2] = r[2] = 0.0;
     const double c[3] = {(double)cx, (double)cy, (double)cz};
     double F[3];
@@ -433,9 +445,9 @@ __global__ __launch_bounds__(256) void refill_kernel(MovingParams p) {
 }
 
 template <class L, int S>
-__global__ __launch_bounds__(256) void moving_force_kernel(MovingParams p, double* out) {
+__global__ __launch_bounds__(256) void moving_force_kernel(MovingParams p, double* out, int32_t* grp) {
   const int64_t wave = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (wave < p.nreg) force_body<L, S>(p, wave, out);
+  if (wave < p.nreg) force_body<L, S>(p, wave, out, grp);
 }
 
 // Entry of the sphere table with its pointers read through the constant address
@@ -577,15 +589,15 @@ hipError_t launch_moving_refill(int lattice, int storage, const MovingParams& p,
   return hipGetLastError();
 }
 
-hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, double* contrib, double* out,
-                               hipStream_t s) {
+hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, double* contrib, int32_t* grp,
+                               double* out, hipStream_t s) {
   if (p.nreg > 0) {
 #define LBM_MFORCE(LAT)                                                                            \
   switch (storage) {                                                                               \
-    case ST_F64: moving_force_kernel<LAT, ST_F64><<<region_grid(p), 256, 0, s>>>(p, contrib); break;  \
-    case ST_F32: moving_force_kernel<LAT, ST_F32><<<region_grid(p), 256, 0, s>>>(p, contrib); break;  \
-    case ST_F16S: moving_force_kernel<LAT, ST_F16S><<<region_grid(p), 256, 0, s>>>(p, contrib); break;\
-    default: moving_force_kernel<LAT, ST_BF16S><<<region_grid(p), 256, 0, s>>>(p, contrib); break;    \
+    case ST_F64: moving_force_kernel<LAT, ST_F64><<<region_grid(p), 256, 0, s>>>(p, contrib, grp); break;\
+    case ST_F32: moving_force_kernel<LAT, ST_F32><<<region_grid(p), 256, 0, s>>>(p, contrib, grp); break;\
+    case ST_F16S: moving_force_kernel<LAT, ST_F16S><<<region_grid(p), 256, 0, s>>>(p, contrib, grp); break;\
+    default: moving_force_kernel<LAT, ST_BF16S><<<region_grid(p), 256, 0, s>>>(p, contrib, grp); break;\
   }
     if (lattice == LBM_D2Q9) {
       LBM_MFORCE(D2Q9)
@@ -598,7 +610,7 @@ hipError_t launch_moving_force(int lattice, int storage, const MovingParams& p, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return launch_group_sum(contrib, nullptr, 0, p.seg_lbase + p.g.nseg, 1, out, s);
+  return launch_group_sum(contrib, p.k.ns > 1 ? grp : nullptr, 0, p.seg_lbase + p.g.nseg, p.k.ns, out, s);
 }
 
 template <bool M>

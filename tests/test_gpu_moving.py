@@ -335,6 +335,47 @@ def test_two_spheres_match_oracle(gpu_lib, storage, tol):
     d.close()
 
 
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_two_sphere_forces_match_oracle(gpu_lib, storage, tol):
+    """Force tracking with two spheres: each link counts for the sphere holding
+    its solid node, torques about that sphere's centre; per-sphere force and
+    torque against the oracle's link groups, and a one-sphere list against the
+    one-sphere call."""
+    B = gpu_lib
+    n, steps = 40, 16
+    C, V, Om = _two_sphere_paths(steps + 2)
+    radii = [5.2, 4.1]
+    _say("case two moving spheres force 40^3", storage)
+    d = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    d.set_moving_spheres(radii, C, V, Om)
+    d.set_force_tracking(True)
+    m = moving.MovingSpheresSim(G.Domain(OL.D3Q19, n, n, n), radii,
+                                [moving.SampledKinematics(C[:, s], V[:, s], Om[:, s]) for s in range(2)], 0.8)
+    for k in (1, 6, 9):
+        d.step(k)
+        m.run(k)
+        F, T = d.moving_forces(2)
+        Fo, To = m.sim.last_force, m.sim.last_torque
+        for sp in range(2):
+            ferr = np.abs(F[sp] - Fo[sp]).max() / np.abs(Fo[sp]).max()
+            terr = np.abs(T[sp] - To[sp]).max() / np.abs(To[sp]).max()
+            _say("t", m.t, "sphere", sp, "force", F[sp], "torque", T[sp], "rel err", ferr, terr)
+            assert ferr <= tol and terr <= tol
+    d.close()
+    one = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    ref = B.Domain("D3Q19", n, n, n, np.ones(n ** 3, np.uint8), 0.8, storage=storage, layout="dense")
+    one.set_moving_spheres(radii[:1], C[:, :1], V[:, :1], Om[:, :1])
+    ref.set_moving_sphere_motion(radii[0], C[:, 0], V[:, 0], Om[:, 0])
+    for x in (one, ref):
+        x.set_force_tracking(True)
+        x.step(5)
+    F1, T1 = one.moving_forces(1)
+    F0, T0 = ref.moving_force()
+    assert np.array_equal(F1[0], F0) and np.array_equal(T1[0], T0)
+    one.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16s-sr"])
 def test_sphere_lists_equal_single_forms_and_batches(gpu_lib, storage):
     """A one-sphere list equals lbm_set_moving_sphere_motion to the bit; a
@@ -392,9 +433,16 @@ def test_sphere_list_validation(gpu_lib):
     with pytest.raises(ValueError):
         d.set_moving_spheres([5.2, 4.1], C, V, Om[:, :1])
     d.set_moving_spheres([5.2, 4.1], C, V, Om)
-    with pytest.raises(B.LBMError) as e:       # force tracking is for one sphere
-        d.set_force_tracking(True)
-    assert e.value.code == B.LBM_ESTATE
+    d.set_force_tracking(True)
+    d.step(1)
+    with pytest.raises(B.LBMError) as e:       # two spheres: the per-sphere form
+        d.moving_force()
+    assert e.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LBMError) as e:
+        d.moving_forces(3)
+    assert e.value.code == B.LBM_EINVAL
+    F, T = d.moving_forces(2)
+    assert np.isfinite(F).all() and np.isfinite(T).all()
     d.close()
 
 

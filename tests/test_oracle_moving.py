@@ -192,6 +192,38 @@ def test_two_sphere_order_does_not_matter():
     b.run(10)
     assert np.array_equal(a.sim.fluid, b.sim.fluid)
     assert np.array_equal(a.sim.f, b.sim.f, equal_nan=True)
+    # each sphere's own force and torque (its links, about its centre) follow it
+    assert np.abs(a.sim.last_force).max() > 1e-6
+    assert np.array_equal(a.sim.last_force, b.sim.last_force[::-1])
+    assert np.array_equal(a.sim.last_torque, b.sim.last_torque[::-1])
+
+
+def test_mirrored_spheres_have_mirrored_forces():
+    """Two spheres mirror images of each other in the plane x = 12 of a periodic
+    box, moving and spinning as mirror images: the flow is mirror symmetric, so
+    the second sphere's force is the first's with F_x negated, and its torque
+    (an axial vector, about its own centre) the first's with T_y and T_z
+    negated.  A link counted for the wrong sphere or a torque about the wrong
+    centre breaks the symmetry."""
+    lat = lattice.D3Q19
+    dom = G.Domain(lat, 24, 22, 20)
+    n = 10
+    t = np.arange(n, dtype=np.float64)[:, None]
+    V = np.array([0.02, 0.004, -0.003])
+    Ca = np.array([[8.3, 11.1, 9.7]]) + t * V[None, :]
+    Cb = Ca * np.array([-1.0, 1.0, 1.0]) + np.array([24.0, 0.0, 0.0])
+    Vb = V * np.array([-1.0, 1.0, 1.0])
+    Om = np.array([0.002, 0.0015, 0.001])
+    ka = moving.SampledKinematics(Ca, np.repeat(V[None, :], n, 0), Om)
+    kb = moving.SampledKinematics(Cb, np.repeat(Vb[None, :], n, 0), Om * np.array([1.0, -1.0, -1.0]))
+    m = moving.MovingSpheresSim(dom, [2.4, 2.4], [ka, kb], tau=0.8)
+    for _ in range(n - 2):
+        m.step()
+        F, T = m.sim.last_force, m.sim.last_torque
+        scale = max(np.abs(F).max(), np.abs(T).max())
+        assert scale > 1e-5
+        assert np.abs(F[1] - F[0] * np.array([-1.0, 1.0, 1.0])).max() <= 1e-10 * scale
+        assert np.abs(T[1] - T[0] * np.array([1.0, -1.0, -1.0])).max() <= 1e-10 * scale
 
 
 def test_refill_velocity_is_the_nearest_spheres():

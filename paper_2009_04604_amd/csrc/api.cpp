@@ -273,8 +273,6 @@ void free_links(lbm_domain_s* d) {
   dfree(d->lgrp);
   dfree(d->lforce);
   dfree(d->gforce);
-  dfree(d->mforce);    // sized by the link capacity: set again with it
-  dfree(d->mgroup);
   d->link_order.clear();
   d->n_groups = 1;
   d->nb = d->nl = 0;
@@ -605,11 +603,6 @@ int install_moving(lbm_domain d, int ns, const double (*lo_c)[3], const double (
   if (int e = dalloc(d->lg, d->link_cap * rs)) return e;
   if (d->wall_neq == LBM_NEQ_REGULARIZED)
     if (int e = dalloc(d->luv, 6 * d->link_cap * rs)) return e;
-  if (d->track_force) {
-    if (int e = dalloc(d->mforce, ((size_t)d->link_cap + MAX_SPHERES) * 6 * 8)) return e;
-    if (int e = dalloc(d->mgroup, (size_t)d->link_cap * 4)) return e;
-    d->force_step = -1;
-  }
   HIP_TRY(hipMemcpy(d->reg_seg, reg.data(), reg.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(d->seg_prev, d->seg_fluid, g.nseg * 8, hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemset(d->reg_count, 0, reg.size() * 4));
@@ -1035,6 +1028,8 @@ int lbm_free_domain(lbm_domain d) {
   dfree(d->seg_prev);
   dfree(d->reg_count);
   dfree(d->reg_cut);
+  dfree(d->mforce);   // sized once: the spheres are set once, before tracking
+  dfree(d->mgroup);
   dfree(d->rho_tmp);
   dfree(d->u_tmp);
   delete d;

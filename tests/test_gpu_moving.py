@@ -443,17 +443,13 @@ def test_sphere_list_validation(gpu_lib):
     assert e.value.code == B.LBM_EINVAL
     F, T = d.moving_forces(2)
     assert np.isfinite(F).all() and np.isfinite(T).all()
-    # spheres set again with tracking on: larger spheres, a larger sweep region
-    # and link capacity, so the per-link force scratch is allocated again
-    cap = d.info()["n_links"]
-    d.set_moving_spheres([6.5, 5.5], C, V, Om)
-    with pytest.raises(B.LBMError) as e:       # no step yet on the new spheres
-        d.moving_forces(2)
+    # the spheres are set once (the force scratch is sized by their link capacity)
+    with pytest.raises(B.LBMError) as e:
+        d.set_moving_spheres([6.5, 5.5], C, V, Om)
     assert e.value.code == B.LBM_ESTATE
-    d.step(2)
-    F, T = d.moving_forces(2)
-    assert d.info()["n_links"] > cap
-    assert np.isfinite(F).all() and np.isfinite(T).all() and np.abs(F).max() > 0
+    d.step(1)
+    F2, T2 = d.moving_forces(2)
+    assert np.isfinite(F2).all() and np.isfinite(T2).all()
     d.close()
 
 
